@@ -1,0 +1,166 @@
+/*
+ * aggx -- bounded-memory hash GROUP BY on AMD Instinct MI355X (gfx950).
+ *
+ * The operator is the hybrid-hash local aggregation studied in Wen, Borkar,
+ * Carey, Tsotras, "Revisiting Aggregation for Data Intensive Applications: A
+ * Performance Study" (arXiv:1311.0059):
+ *   - the query is a GROUP BY with bounded-state accumulating aggregates
+ *     (Sec. 3.1: COUNT, SUM, MIN, MAX); the result has one group record
+ *     (key + grouping state) per distinct key;
+ *   - it runs under a strict memory budget M (Sec. 3.2), here in bytes of
+ *     device working memory;
+ *   - records are hash-partitioned; resident partitions are aggregated in
+ *     hash tables, partitions that overflow the budget are spilled, and the
+ *     spilled partitions are re-aggregated recursively with a new hash digit
+ *     per level (Sec. 4.3, Fig. "General Hybrid-hash algorithm structure",
+ *     Phases 1 and 2; Sec. 4.3.3 Dynamic Destaging; Sec. 7.7 per-level hash
+ *     seeds);
+ *   - the number of distinct keys G is an optional input (Sec. 4.3, Formula
+ *     (1) and the text after it), used only to plan partitions.
+ *
+ * Conventions for every entry point:
+ *   - return codes: AGG_OK (0) or a negative agg_status; no exception crosses
+ *     this interface;
+ *   - after AGG_E_DEVICE the handle is poisoned and only agg_destroy is valid;
+ *   - a handle is not thread-safe; distinct handles are independent and may be
+ *     used from different threads and streams concurrently;
+ *   - "device pointer" means memory of the current HIP device; the library
+ *     never frees memory it did not allocate.
+ */
+#ifndef AGGX_H
+#define AGGX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum agg_status {
+  AGG_OK = 0,
+  AGG_E_INVALID = -1,  /* malformed spec or argument (offsets, widths, ops, NULL pointers) */
+  AGG_E_BUDGET = -2,   /* budget below the minimum working set, or workspace smaller than the budget */
+  AGG_E_DEVICE = -3,   /* a HIP call failed; the handle is poisoned */
+  AGG_E_STATE = -4,    /* call not allowed in the handle's current state (e.g. consume after finish) */
+  AGG_E_NOMEM = -5,    /* host or device allocation outside the budget failed (results, spill runs) */
+  AGG_E_INTERNAL = -6  /* recursion guard tripped beyond the hash's digit range (should not happen) */
+} agg_status;
+
+typedef enum agg_type { AGG_U32 = 0, AGG_U64 = 1, AGG_I32 = 2, AGG_I64 = 3 } agg_type;
+
+/* Bounded-state aggregate functions of Sec. 3.1.
+ * COUNT counts records; SUM adds modulo 2^64 (two's complement wrap, so the
+ * result is independent of the order of accumulation); MIN/MAX compare signed
+ * for I32/I64 inputs and unsigned for U32/U64 inputs.  32-bit inputs are
+ * widened (sign- or zero-extended) to 64 bits; every output column is 64-bit. */
+typedef enum agg_op { AGG_COUNT = 0, AGG_SUM = 1, AGG_MIN = 2, AGG_MAX = 3 } agg_op;
+
+typedef struct agg_field {
+  uint32_t offset; /* byte offset inside the record; naturally aligned for its width */
+  uint32_t type;   /* agg_type */
+} agg_field;
+
+typedef struct agg_fn {
+  uint32_t op;     /* agg_op */
+  agg_field in;    /* input field; ignored for COUNT */
+} agg_fn;
+
+/* Spill policies once a partition's table is full (Sec. 4.3.3, 4.3.4). */
+typedef enum agg_policy {
+  AGG_POLICY_DESTAGE = 0,  /* Dynamic Destaging: a full partition is spilled whole (its grouping states
+                              plus every later record of it, raw) at the next synchronisation point */
+  AGG_POLICY_PREPART = 1   /* Pre-Partitioning: a full partition keeps its groups; later records whose
+                              key is resident are aggregated, the others are spilled raw */
+} agg_policy;
+
+#define AGG_MAX_AGGS 8
+#define AGG_MAX_LEVELS 8
+
+typedef struct agg_spec {
+  uint32_t record_bytes;     /* fixed record width: a multiple of 4, 4..256; records are packed (AoS) */
+  uint32_t n_keys;           /* 1: one U32/U64/I32/I64 key field;
+                                2: two U32 fields (k1, k2), the composite key k1 * 2^32 + k2,
+                                   compared as one unsigned 64-bit number (lexicographic on (k1, k2)) */
+  agg_field keys[2];
+  uint32_t n_aggs;           /* 1..AGG_MAX_AGGS */
+  agg_fn aggs[AGG_MAX_AGGS];
+  uint64_t budget_bytes;     /* device working memory for tables, partition metadata and staging;
+                                0 = unlimited.  Inputs and result rows are outside the budget. */
+  uint64_t est_groups;       /* estimate of distinct keys (the paper's G); 0 = unknown */
+  void *device_workspace;    /* optional caller-owned device slab of workspace_bytes >= budget_bytes
+                                (256-byte aligned); NULL = the library allocates the budget itself */
+  uint64_t workspace_bytes;
+  void *stream;              /* hipStream_t for all work of this handle; NULL = a library-owned stream */
+  uint32_t fanout_bits;      /* partition digit width per level, 0 = automatic (1..12 otherwise) */
+  uint32_t load_pct;         /* maximum table load in percent, 0 = automatic (10..95 otherwise) */
+  uint32_t policy;           /* agg_policy */
+  uint32_t reserved;         /* must be 0 */
+} agg_spec;
+
+typedef struct agg_handle agg_handle;
+
+/* Result of agg_finish.  Row order is unspecified.  d_keys[r] is the canonical
+ * 64-bit key (the U64/I64 bit pattern, a U32 zero-extended, an I32
+ * sign-extended, or k1 * 2^32 + k2); d_cols[a][r] is aggregate a of row r as a
+ * 64-bit two's-complement value.  The buffers are device memory owned by the
+ * handle until agg_destroy, and may be wrapped zero-copy by the caller. */
+typedef struct agg_result {
+  uint64_t n_rows;
+  const uint64_t *d_keys;
+  const int64_t *d_cols[AGG_MAX_AGGS];
+} agg_result;
+
+typedef struct agg_stats {
+  uint64_t records_in;          /* records passed to agg_consume */
+  uint64_t groups_out;          /* rows of the result (after agg_finish) */
+  uint64_t resident_groups_l0;  /* groups finished in memory at level 0 */
+  uint64_t records_spilled;     /* raw records written to spill runs, all levels */
+  uint64_t states_spilled;      /* grouping states written to spill runs, all levels */
+  uint64_t bytes_spilled_d2h;   /* bytes moved device -> host by spilling */
+  uint64_t bytes_reloaded_h2d;  /* bytes read back host -> device for recursion */
+  uint32_t levels;              /* levels run (1 = no recursion) */
+  uint32_t partitions;          /* level-0 partitions (fan-out) */
+  uint32_t partitions_spilled;  /* level-0 partitions spilled (planned or overflowed) */
+  uint32_t guard_trips;         /* spilled partitions that kept more than 80% of their parent's input */
+  uint64_t pool_high_water;     /* peak bytes of the working budget in use */
+  uint64_t pool_bytes;          /* size of the working budget actually reserved */
+} agg_stats;
+
+/* Validate and copy `spec`, reserve the working budget (or adopt the caller's
+ * workspace), and plan level 0.  On success *out owns a new handle. */
+agg_status agg_create(const agg_spec *spec, agg_handle **out);
+
+/* Aggregate `n` records from the device buffer `d_records` (packed, record_bytes
+ * each; 8-byte aligned when record_bytes is a multiple of 8, else 4-byte
+ * aligned -- AGG_E_INVALID otherwise).  Specs with an 8-byte key or input field
+ * need record_bytes to be a multiple of 8.  The buffer is borrowed: the work is ordered on the
+ * handle's stream, and the caller must not modify or free the buffer until the
+ * stream has reached this point (synchronize the stream, or make the next
+ * agg_* call on this handle, which orders after it).  n = 0 is a no-op.
+ * After agg_finish it returns AGG_E_STATE. */
+agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n);
+
+/* Finish level 0, run every recursion level over the spilled partitions, and
+ * publish the rows in *out.  Blocks until the result is complete.  Calling it
+ * again returns the same result. */
+agg_status agg_finish(agg_handle *h, agg_result *out);
+
+/* Counters of the run so far (complete after agg_finish). */
+agg_status agg_get_stats(const agg_handle *h, agg_stats *out);
+
+/* Free everything the handle owns.  Safe on a poisoned handle and on NULL. */
+void agg_destroy(agg_handle *h);
+
+/* Static description of a status code. */
+const char *agg_strerror(agg_status s);
+
+/* Size in bytes of the smallest budget accepted for `spec` (its other fields as
+ * given): the working set below which AGG_E_BUDGET is returned. */
+uint64_t agg_min_budget(const agg_spec *spec);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AGGX_H */

@@ -1,0 +1,102 @@
+"""ctypes declarations of the C ABI in include/aggx.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaggx.so")
+
+MAX_AGGS = 8
+
+STATUS = {0: "AGG_OK", -1: "AGG_E_INVALID", -2: "AGG_E_BUDGET", -3: "AGG_E_DEVICE", -4: "AGG_E_STATE",
+          -5: "AGG_E_NOMEM", -6: "AGG_E_INTERNAL"}
+TYPES = {"u32": 0, "u64": 1, "i32": 2, "i64": 3}
+OPS = {"COUNT": 0, "SUM": 1, "MIN": 2, "MAX": 3}
+POLICIES = {"destage": 0, "prepart": 1}
+
+
+class Field(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_uint32), ("type", ctypes.c_uint32)]
+
+
+class Fn(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("in_", Field)]
+
+
+class Spec(ctypes.Structure):
+    _fields_ = [
+        ("record_bytes", ctypes.c_uint32),
+        ("n_keys", ctypes.c_uint32),
+        ("keys", Field * 2),
+        ("n_aggs", ctypes.c_uint32),
+        ("aggs", Fn * MAX_AGGS),
+        ("budget_bytes", ctypes.c_uint64),
+        ("est_groups", ctypes.c_uint64),
+        ("device_workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_uint64),
+        ("stream", ctypes.c_void_p),
+        ("fanout_bits", ctypes.c_uint32),
+        ("load_pct", ctypes.c_uint32),
+        ("policy", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_uint64), ("d_keys", ctypes.c_void_p), ("d_cols", ctypes.c_void_p * MAX_AGGS)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("records_in", ctypes.c_uint64),
+        ("groups_out", ctypes.c_uint64),
+        ("resident_groups_l0", ctypes.c_uint64),
+        ("records_spilled", ctypes.c_uint64),
+        ("states_spilled", ctypes.c_uint64),
+        ("bytes_spilled_d2h", ctypes.c_uint64),
+        ("bytes_reloaded_h2d", ctypes.c_uint64),
+        ("levels", ctypes.c_uint32),
+        ("partitions", ctypes.c_uint32),
+        ("partitions_spilled", ctypes.c_uint32),
+        ("guard_trips", ctypes.c_uint32),
+        ("pool_high_water", ctypes.c_uint64),
+        ("pool_bytes", ctypes.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol include/aggx.h declares
+EXPORTS = ["agg_create", "agg_consume", "agg_finish", "agg_get_stats", "agg_destroy", "agg_strerror",
+           "agg_min_budget"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libaggx.so; raises if it is not built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_1311_0059_amd.build` (needs hipcc)")
+    lib = ctypes.CDLL(path)
+    vp, u64 = ctypes.c_void_p, ctypes.c_uint64
+    lib.agg_create.argtypes = [ctypes.POINTER(Spec), ctypes.POINTER(vp)]
+    lib.agg_create.restype = ctypes.c_int
+    lib.agg_consume.argtypes = [vp, vp, u64]
+    lib.agg_consume.restype = ctypes.c_int
+    lib.agg_finish.argtypes = [vp, ctypes.POINTER(Result)]
+    lib.agg_finish.restype = ctypes.c_int
+    lib.agg_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.agg_get_stats.restype = ctypes.c_int
+    lib.agg_destroy.argtypes = [vp]
+    lib.agg_destroy.restype = None
+    lib.agg_strerror.argtypes = [ctypes.c_int]
+    lib.agg_strerror.restype = ctypes.c_char_p
+    lib.agg_min_budget.argtypes = [ctypes.POINTER(Spec)]
+    lib.agg_min_budget.restype = u64
+    _lib = lib
+    return lib

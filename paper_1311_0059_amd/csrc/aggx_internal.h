@@ -1,0 +1,110 @@
+// Internal definitions shared by the host runtime (aggx_runtime.cpp) and the
+// HIP kernels (aggx_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aggx {
+
+// Every 64-bit pattern is a legal key, so there is no free marker value.
+// Tables reserve two: kEmpty marks a free slot and kClosed a slot closed
+// because its partition was full.  Records whose key equals one of them are
+// accumulated in a dedicated side group instead (it never enters a table, is
+// never spilled, and is emitted as one extra row at the end).
+constexpr uint64_t kEmpty = ~0ULL;
+constexpr uint64_t kClosed = ~0ULL - 1;
+
+constexpr int kMaxAggs = 8;
+constexpr int kMaxFanBits = 12;
+constexpr uint32_t kMaxFan = 1u << kMaxFanBits;
+constexpr int kHllBits = 12;                 // 4096 HyperLogLog registers per sketch
+constexpr uint32_t kHllRegs = 1u << kHllBits;
+
+// agg descriptor packed in one word: op (2 bits) | type (2 bits) << 2 | offset << 8
+enum : uint32_t { T_U32 = 0, T_U64 = 1, T_I32 = 2, T_I64 = 3 };
+enum : uint32_t { OP_COUNT = 0, OP_SUM = 1, OP_MIN = 2, OP_MAX = 3 };
+
+__host__ __device__ inline uint32_t desc_op(uint32_t d) { return d & 3u; }
+__host__ __device__ inline uint32_t desc_type(uint32_t d) { return (d >> 2) & 3u; }
+__host__ __device__ inline uint32_t desc_off(uint32_t d) { return d >> 8; }
+__host__ __device__ inline bool type_signed(uint32_t t) { return t == T_I32 || t == T_I64; }
+
+// Record layout and aggregate list as the kernels see it (passed by value).
+struct KSpec {
+  uint32_t rb;       // record bytes
+  uint32_t nk;       // 1 or 2 key fields
+  uint32_t koff0, koff1;
+  uint32_t ktype0;   // type of the single key field
+  uint32_t na;       // number of aggregates
+  uint32_t agg[kMaxAggs];
+};
+
+// One hybrid-hash pass ("level"): which digit of the hash selects the
+// partition, and the seed of the slot hash.
+struct KLevel {
+  uint32_t level;
+  uint32_t digit_shift;  // partition = (h0 >> digit_shift) & fan_mask
+  uint32_t fan_mask;
+  uint32_t slot_shift;   // level 0: slot hash = h0 << slot_shift; deeper levels use seed_slot
+  uint64_t seed_slot;
+};
+
+// Per-partition table descriptor.  A partition is either resident (a table of
+// nslots slots starting at slot `base` of the arena) or spilled (nslots = 0).
+struct PartMeta {
+  uint64_t base;
+  uint32_t nslots;
+  uint32_t cap;      // groups allowed in the table (its load limit)
+  uint32_t spilled;  // 1: every record of this partition goes to the spill run
+  uint32_t pad;
+};
+
+// Control block in device memory (inside the working budget).
+struct Ctrl {
+  unsigned long long raw_ctr;     // records appended to the current raw spill region
+  unsigned long long state_ctr;   // states appended to the current state spill region
+  unsigned long long rows;        // rows appended by the flush kernel
+  unsigned long long any_ovf;     // number of overflow events in the last launch (saturating use)
+  unsigned long long side_n[2];   // records with the reserved key values kEmpty, kClosed
+  unsigned long long pad[2];
+  unsigned long long side[2][kMaxAggs];  // their side groups' aggregates
+};
+
+// Output columns of the flush kernel (passed by value).
+struct OutCols {
+  int64_t *c[kMaxAggs];
+};
+
+// Where spilled data goes (pinned host memory, written by the kernels).
+struct KSpill {
+  uint8_t *raw;       // raw record region (device-visible host pointer)
+  uint8_t *state;     // state region
+  uint32_t *hll;      // sketch of distinct keys in the spilled data
+};
+
+}  // namespace aggx
+
+// Launch wrappers (defined in aggx_kernels.hip, called by the runtime).
+namespace aggx {
+hipError_t launch_table_init(hipStream_t s, uint64_t *arena, uint64_t nslots, const KSpec &ks);
+hipError_t launch_words_init(hipStream_t s, uint64_t *words, uint64_t nwords, uint64_t value);
+hipError_t launch_u32_fill(hipStream_t s, uint32_t *p, uint64_t n, uint32_t value);
+hipError_t launch_ctrl_init(hipStream_t s, Ctrl *c, const KSpec &ks);
+// input_kind: 0 = raw records (record layout), 1 = state records (key + na words)
+hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint64_t n, const KSpec &ks,
+                         const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint32_t *ovf, uint64_t *arena,
+                         Ctrl *ctrl, KSpill spill, int grid_hint);
+hipError_t launch_flush(hipStream_t s, const uint64_t *arena, uint64_t nslots, const KSpec &ks, uint64_t *out_keys,
+                        const OutCols &out_cols, uint64_t out_cap, Ctrl *ctrl);
+hipError_t launch_u64_set(hipStream_t s, unsigned long long *p, uint32_t n, unsigned long long v);
+hipError_t launch_extract(hipStream_t s, uint64_t *arena, uint64_t base, uint64_t nslots, const KSpec &ks,
+                          Ctrl *ctrl, KSpill spill);
+// Grace partitioning of a run: histogram of the digit (h0 >> shift) & mask,
+// then a scatter of every element to cursor[digit]++ in `out`.
+hipError_t launch_digit_hist(hipStream_t s, int kind, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
+                             uint32_t mask, unsigned long long *hist);
+hipError_t launch_digit_scatter(hipStream_t s, int kind, const uint8_t *in, uint64_t n, const KSpec &ks,
+                                uint32_t shift, uint32_t mask, unsigned long long *cursor, uint8_t *out);
+uint64_t hll_seed();
+}  // namespace aggx

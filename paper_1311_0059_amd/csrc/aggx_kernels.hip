@@ -1,0 +1,473 @@
+// HIP kernels for gfx950: hybrid-hash aggregation into per-partition
+// open-addressing tables in HBM, spill to pinned host memory, flush, extract.
+//
+// Method (Wen et al., arXiv:1311.0059):
+//   - records are hash-partitioned; partition i's groups live in its own
+//     table; records of spilled partitions are written out raw (Sec. 4.3,
+//     Phase 1; Sec. 4.3.3 Dynamic Destaging, Stage 2);
+//   - a table is "full" when no new group fits (Sec. 3.2); a record of a new
+//     key that finds its partition full is spilled raw, and its partition is
+//     flagged so that the host applies the spill policy;
+//   - Murmur hashing with a separate hash per level keeps adjacent levels
+//     uncorrelated (Sec. 7.7).  The partition digit of every level is a
+//     disjoint bit field of one bijective 64-bit hash h0, so recursion always
+//     terminates; slots use an independently seeded hash per level.
+//
+// Table slot layout (AoS, 8-byte words): [key, agg_0, ..., agg_{na-1}].
+// Aggregates are updated with 64-bit device-scope atomics (add for COUNT and
+// SUM, signed/unsigned min/max).  MIN/MAX first read the current value and
+// skip the atomic when it cannot change the result: a stale read is never
+// below (MIN) / above (MAX) the true value, so skipping is always safe.
+#include "aggx_internal.h"
+
+namespace aggx {
+
+// MurmurHash3 64-bit finalizer (Appleby), a bijection on 64-bit words.
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdULL;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ULL;
+  k ^= k >> 33;
+  return k;
+}
+
+constexpr uint32_t kProbeLimit = 4096;
+constexpr uint64_t kSeed0 = 0x5851f42d4c957f2dULL;    // digit hash h0 = fmix64(key ^ kSeed0)
+constexpr uint64_t kSeedHll = 0x2545f4914f6cdd1dULL;  // distinct-count sketch hash
+uint64_t hll_seed() { return kSeedHll; }
+
+__device__ __forceinline__ uint32_t ld32(const uint8_t *p) { return *reinterpret_cast<const uint32_t *>(p); }
+__device__ __forceinline__ uint64_t ld64(const uint8_t *p) { return *reinterpret_cast<const uint64_t *>(p); }
+
+__device__ __forceinline__ uint64_t read_field(const uint8_t *rec, uint32_t off, uint32_t type) {
+  switch (type) {
+    case T_U32: return (uint64_t)ld32(rec + off);
+    case T_I32: return (uint64_t)(int64_t)(int32_t)ld32(rec + off);
+    default: return ld64(rec + off);
+  }
+}
+
+__device__ __forceinline__ uint64_t read_key(const uint8_t *rec, const KSpec &ks) {
+  if (ks.nk == 2) return ((uint64_t)ld32(rec + ks.koff0) << 32) | (uint64_t)ld32(rec + ks.koff1);
+  return read_field(rec, ks.koff0, ks.ktype0);
+}
+
+__device__ __forceinline__ uint64_t identity_of(uint32_t d) {
+  switch (desc_op(d)) {
+    case OP_MIN: return type_signed(desc_type(d)) ? (uint64_t)INT64_MAX : ~0ULL;
+    case OP_MAX: return type_signed(desc_type(d)) ? (uint64_t)INT64_MIN : 0ULL;
+    default: return 0ULL;
+  }
+}
+
+__device__ __forceinline__ uint64_t relaxed_load(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Fold one contribution (a raw record read as a state with count 1, or a
+// spilled state) into the aggregates starting at `acc`.
+__device__ __forceinline__ void fold_global(uint64_t *acc, const KSpec &ks, const uint64_t *vals) {
+#pragma unroll
+  for (int a = 0; a < kMaxAggs; ++a) {
+    if (a >= (int)ks.na) break;
+    const uint32_t d = ks.agg[a];
+    uint64_t *w = acc + a;
+    const uint64_t v = vals[a];
+    switch (desc_op(d)) {
+      case OP_COUNT:
+      case OP_SUM:
+        __hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(w), (unsigned long long)v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      case OP_MIN:
+        if (type_signed(desc_type(d))) {
+          if ((int64_t)v < (int64_t)relaxed_load(w))
+            __hip_atomic_fetch_min(reinterpret_cast<long long *>(w), (long long)v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          if (v < relaxed_load(w))
+            __hip_atomic_fetch_min(reinterpret_cast<unsigned long long *>(w), (unsigned long long)v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        break;
+      default:  // OP_MAX
+        if (type_signed(desc_type(d))) {
+          if ((int64_t)v > (int64_t)relaxed_load(w))
+            __hip_atomic_fetch_max(reinterpret_cast<long long *>(w), (long long)v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          if (v > relaxed_load(w))
+            __hip_atomic_fetch_max(reinterpret_cast<unsigned long long *>(w), (unsigned long long)v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        break;
+    }
+  }
+}
+
+// HyperLogLog register update (Flajolet, Fusy, Gandouet, Meunier, 2007).
+__device__ __forceinline__ void hll_add(uint32_t *regs, uint64_t key) {
+  uint64_t x = fmix64(key ^ kSeedHll);
+  uint32_t j = (uint32_t)(x >> (64 - kHllBits));
+  uint64_t w = (x << kHllBits) | (1ULL << (kHllBits - 1));
+  uint32_t rho = (uint32_t)__builtin_clzll(w) + 1;
+  if (rho > __hip_atomic_load(regs + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+    __hip_atomic_fetch_max(regs + j, rho, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t lane = __lane_id();
+  return lane == 0 ? 0ULL : (~0ULL >> (64 - lane));
+}
+
+// Append the record/state of every lane with `want` set to a spill region, in
+// one atomic per wave.  Must be reached by every lane of the wave.
+__device__ __forceinline__ void spill_append(bool want, const uint8_t *src, uint32_t bytes, uint8_t *region,
+                                             unsigned long long *ctr, uint32_t *hll, uint64_t key) {
+  const uint64_t mask = __ballot(want);
+  if (mask == 0) return;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  unsigned long long base = 0;
+  if ((int)__lane_id() == leader)
+    base = __hip_atomic_fetch_add(ctr, (unsigned long long)__popcll(mask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  base = __shfl(base, leader);
+  if (want) {
+    const unsigned long long pos = base + (unsigned long long)__popcll(mask & lanemask_lt());
+    uint32_t *dst = reinterpret_cast<uint32_t *>(region + pos * bytes);
+    const uint32_t *s = reinterpret_cast<const uint32_t *>(src);
+    for (uint32_t i = 0; i < bytes / 4; ++i) dst[i] = s[i];
+    hll_add(hll, key);
+  }
+}
+
+// Input readers: raw records (record layout) or spilled states (key + na words).
+template <int KIND>
+__device__ __forceinline__ uint64_t in_key(const uint8_t *rec, const KSpec &ks) {
+  if (KIND == 0) return read_key(rec, ks);
+  return ld64(rec);
+}
+
+template <int KIND>
+__device__ __forceinline__ void in_vals(const uint8_t *rec, const KSpec &ks, uint64_t *vals) {
+#pragma unroll
+  for (int a = 0; a < kMaxAggs; ++a) {
+    if (a >= (int)ks.na) break;
+    const uint32_t d = ks.agg[a];
+    if (KIND == 0)
+      vals[a] = desc_op(d) == OP_COUNT ? 1ULL : read_field(rec, desc_off(d), desc_type(d));
+    else
+      vals[a] = ld64(rec + 8 + 8 * a);
+  }
+}
+
+__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+
+// Main pass: every record is routed to its partition's table or to the spill run.
+template <int KIND>
+__global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, uint64_t n, KSpec ks, KLevel lv,
+                                                const PartMeta *__restrict__ meta, uint32_t *cnt, uint32_t *ovf,
+                                                uint64_t *arena, Ctrl *ctrl, KSpill spill) {
+  const uint32_t W = 1 + ks.na;
+  const uint32_t in_bytes = KIND == 0 ? ks.rb : 8 * W;
+  const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  const uint32_t lane = __lane_id();
+  for (uint64_t base = wave * 64; base < n; base += nwaves * 64) {
+    const uint64_t i = base + lane;
+    const bool valid = i < n;
+    const uint8_t *rec = in + (valid ? i : 0) * (uint64_t)in_bytes;
+    uint64_t key = 0;
+    uint64_t vals[kMaxAggs];
+    bool to_spill = false;
+    if (valid) {
+      key = in_key<KIND>(rec, ks);
+      in_vals<KIND>(rec, ks, vals);
+      if (key >= kClosed) {  // the two reserved values: side groups
+        const int sg = key == kEmpty ? 0 : 1;
+        fold_global(reinterpret_cast<uint64_t *>(ctrl->side[sg]), ks, vals);
+        __hip_atomic_fetch_add(&ctrl->side_n[sg], 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        const uint64_t h0 = fmix64(key ^ kSeed0);
+        const uint32_t p = lv.fan_mask ? (uint32_t)(h0 >> lv.digit_shift) & lv.fan_mask : 0u;
+        const PartMeta pm = meta[p];
+        if (pm.spilled) {
+          to_spill = true;
+        } else {
+          const uint64_t hs = lv.level == 0 ? (h0 << lv.slot_shift) : fmix64(key ^ lv.seed_slot);
+          uint64_t idx = mulhi64(hs, pm.nslots);
+          bool done = false;
+          // Linear probing over at most kProbeLimit slots.  A slot changes
+          // once, from kEmpty to a key or to kClosed, and every observation of
+          // kEmpty is confirmed by a CAS.  While the partition has room the CAS
+          // inserts the key; once its group count reached `cap` the CAS closes
+          // the slot instead.  kClosed ends every probe that reaches it, so no
+          // key is ever inserted behind it: a record that meets kClosed (or
+          // finds no empty slot within the limit) before its key can conclude
+          // that the key is not resident and never will be, and spill.  A key is
+          // therefore either resident for all of its records or spilled for all.
+          const uint32_t lim = pm.nslots < kProbeLimit ? pm.nslots : kProbeLimit;
+          for (uint32_t t = 0; t < lim; ++t) {
+            uint64_t *slot = arena + (pm.base + idx) * W;
+            uint64_t sk = relaxed_load(slot);
+            if (sk == kEmpty) {
+              const bool full = __hip_atomic_load(cnt + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= pm.cap;
+              const uint64_t desired = full ? kClosed : key;
+              unsigned long long expect = kEmpty;
+              __hip_atomic_compare_exchange_strong(reinterpret_cast<unsigned long long *>(slot), &expect,
+                                                   (unsigned long long)desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+              if (expect == kEmpty) {
+                if (!full) __hip_atomic_fetch_add(cnt + p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sk = desired;
+              } else {
+                sk = expect;
+              }
+            }
+            if (sk == key) {
+              fold_global(slot + 1, ks, vals);
+              done = true;
+              break;
+            }
+            if (sk == kClosed) break;
+            idx = (idx + 1 == pm.nslots) ? 0 : idx + 1;
+          }
+          if (!done) {
+            to_spill = true;
+            __hip_atomic_store(ovf + p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&ctrl->any_ovf, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+      }
+    }
+    if (KIND == 0)
+      spill_append(to_spill, rec, ks.rb, spill.raw, &ctrl->raw_ctr, spill.hll, key);
+    else
+      spill_append(to_spill, rec, 8 * W, spill.state, &ctrl->state_ctr, spill.hll, key);
+  }
+}
+
+__global__ void k_table_init(uint64_t *arena, uint64_t nslots, KSpec ks) {
+  const uint32_t W = 1 + ks.na;
+  for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < nslots; s += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t *slot = arena + s * W;
+    slot[0] = kEmpty;
+    for (uint32_t a = 0; a < ks.na; ++a) slot[1 + a] = identity_of(ks.agg[a]);
+  }
+}
+
+__global__ void k_words_init(uint64_t *w, uint64_t n, uint64_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) w[i] = v;
+}
+
+__global__ void k_u32_fill(uint32_t *p, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_u64_set(unsigned long long *p, uint32_t n, unsigned long long v) {
+  if (blockIdx.x == 0 && threadIdx.x < n) p[threadIdx.x] = v;
+}
+
+__global__ void k_ctrl_init(Ctrl *c, KSpec ks) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    c->raw_ctr = 0;
+    c->state_ctr = 0;
+    c->rows = 0;
+    c->any_ovf = 0;
+    for (int g = 0; g < 2; ++g) {
+      c->side_n[g] = 0;
+      for (int a = 0; a < kMaxAggs; ++a) c->side[g][a] = a < (int)ks.na ? identity_of(ks.agg[a]) : 0;
+    }
+  }
+}
+
+// Compact the occupied slots of [arena, arena + nslots) into SoA output rows.
+__global__ void __launch_bounds__(256) k_flush(const uint64_t *__restrict__ arena, uint64_t nslots, KSpec ks,
+                                               uint64_t *out_keys, OutCols out_cols, uint64_t out_cap,
+                                               Ctrl *ctrl) {
+  const uint32_t W = 1 + ks.na;
+  const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t base = wave * 64; base < nslots; base += nwaves * 64) {
+    const uint64_t s = base + __lane_id();
+    const uint64_t *slot = arena + (s < nslots ? s : 0) * W;
+    const bool occ = s < nslots && slot[0] < kClosed;
+    const uint64_t mask = __ballot(occ);
+    if (mask == 0) continue;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long pos0 = 0;
+    if ((int)__lane_id() == leader)
+      pos0 = __hip_atomic_fetch_add(&ctrl->rows, (unsigned long long)__popcll(mask), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    pos0 = __shfl(pos0, leader);
+    if (occ) {
+      const uint64_t r = pos0 + __popcll(mask & lanemask_lt());
+      if (r < out_cap) {
+        out_keys[r] = slot[0];
+        for (uint32_t a = 0; a < ks.na; ++a) out_cols.c[a][r] = (int64_t)slot[1 + a];
+      }
+    }
+  }
+}
+
+// Spill a partition's groups as state records and reset its slots to empty.
+__global__ void __launch_bounds__(256) k_extract(uint64_t *arena, uint64_t first, uint64_t nslots, KSpec ks,
+                                                 Ctrl *ctrl, KSpill spill) {
+  const uint32_t W = 1 + ks.na;
+  const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t base = wave * 64; base < nslots; base += nwaves * 64) {
+    const uint64_t s = base + __lane_id();
+    uint64_t *slot = arena + (first + (s < nslots ? s : 0)) * W;
+    const bool occ = s < nslots && slot[0] < kClosed;
+    spill_append(occ, reinterpret_cast<const uint8_t *>(slot), 8 * W, spill.state, &ctrl->state_ctr, spill.hll,
+                 occ ? slot[0] : 0);
+    if (s < nslots) {
+      slot[0] = kEmpty;
+      for (uint32_t a = 0; a < ks.na; ++a) slot[1 + a] = identity_of(ks.agg[a]);
+    }
+  }
+}
+
+// ---- Grace partitioning of spilled runs (Sec. 4.3, Phase 1: when the groups
+// far exceed memory, the input is first only partitioned, one run per
+// partition).  Two passes over a run in pinned memory: a digit histogram, then
+// a scatter that writes each record to its partition's sub-run.
+template <int KIND>
+__global__ void __launch_bounds__(256) k_digit_hist(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
+                                                    uint32_t shift, uint32_t mask, unsigned long long *hist) {
+  extern __shared__ uint32_t lh[];
+  for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) lh[b] = 0;
+  __syncthreads();
+  const uint32_t bytes = KIND == 0 ? ks.rb : 8 * (1 + ks.na);
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = in_key<KIND>(in + i * bytes, ks);
+    const uint32_t d = (uint32_t)(fmix64(key ^ kSeed0) >> shift) & mask;
+    atomicAdd(&lh[d], 1u);
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x)
+    if (lh[b]) __hip_atomic_fetch_add(hist + b, (unsigned long long)lh[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_digit_scatter(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
+                                                       uint32_t shift, uint32_t mask, unsigned long long *cursor,
+                                                       uint8_t *out) {
+  extern __shared__ uint32_t lc[];  // mask+1 local counts, then mask+1 bases (64-bit)
+  unsigned long long *lbase = reinterpret_cast<unsigned long long *>(lc + ((mask + 2) & ~1u));
+  const uint32_t bytes = KIND == 0 ? ks.rb : 8 * (1 + ks.na);
+  for (uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x; t0 < n; t0 += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) lc[b] = 0;
+    __syncthreads();
+    const uint64_t i = t0 + threadIdx.x;
+    const bool valid = i < n;
+    uint32_t d = 0, r = 0;
+    if (valid) {
+      const uint64_t key = in_key<KIND>(in + i * bytes, ks);
+      d = (uint32_t)(fmix64(key ^ kSeed0) >> shift) & mask;
+      r = atomicAdd(&lc[d], 1u);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x)
+      if (lc[b])
+        lbase[b] = __hip_atomic_fetch_add(cursor + b, (unsigned long long)lc[b], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (valid) {
+      const uint32_t *src = reinterpret_cast<const uint32_t *>(in + i * bytes);
+      uint32_t *dst = reinterpret_cast<uint32_t *>(out + (lbase[d] + r) * bytes);
+      for (uint32_t w = 0; w < bytes / 4; ++w) dst[w] = src[w];
+    }
+    __syncthreads();
+  }
+}
+
+static int grid_for(uint64_t items, int per_block, int max_blocks) {
+  uint64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > (uint64_t)max_blocks) b = max_blocks;
+  return (int)b;
+}
+
+hipError_t launch_table_init(hipStream_t s, uint64_t *arena, uint64_t nslots, const KSpec &ks) {
+  if (nslots == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_table_init, dim3(grid_for(nslots, 256, 8192)), dim3(256), 0, s, arena, nslots, ks);
+  return hipGetLastError();
+}
+
+hipError_t launch_words_init(hipStream_t s, uint64_t *words, uint64_t nwords, uint64_t value) {
+  if (nwords == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_words_init, dim3(grid_for(nwords, 256, 4096)), dim3(256), 0, s, words, nwords, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_u32_fill(hipStream_t s, uint32_t *p, uint64_t n, uint32_t value) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_u32_fill, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_u64_set(hipStream_t s, unsigned long long *p, uint32_t n, unsigned long long v) {
+  hipLaunchKernelGGL(k_u64_set, dim3(1), dim3(64), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctrl_init(hipStream_t s, Ctrl *c, const KSpec &ks) {
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, c, ks);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint64_t n, const KSpec &ks,
+                         const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint32_t *ovf, uint64_t *arena,
+                         Ctrl *ctrl, KSpill spill, int grid_hint) {
+  if (n == 0) return hipSuccess;
+  const int blocks = grid_for(n, 256, grid_hint > 0 ? grid_hint : 256 * 16);
+  if (input_kind == 0)
+    hipLaunchKernelGGL(k_update<0>, dim3(blocks), dim3(256), 0, s, in, n, ks, lv, meta, cnt, ovf, arena, ctrl, spill);
+  else
+    hipLaunchKernelGGL(k_update<1>, dim3(blocks), dim3(256), 0, s, in, n, ks, lv, meta, cnt, ovf, arena, ctrl, spill);
+  return hipGetLastError();
+}
+
+hipError_t launch_flush(hipStream_t s, const uint64_t *arena, uint64_t nslots, const KSpec &ks, uint64_t *out_keys,
+                        const OutCols &out_cols, uint64_t out_cap, Ctrl *ctrl) {
+  if (nslots == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_flush, dim3(grid_for(nslots, 256, 256 * 16)), dim3(256), 0, s, arena, nslots, ks, out_keys,
+                     out_cols, out_cap, ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract(hipStream_t s, uint64_t *arena, uint64_t base, uint64_t nslots, const KSpec &ks,
+                          Ctrl *ctrl, KSpill spill) {
+  if (nslots == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_extract, dim3(grid_for(nslots, 256, 1024)), dim3(256), 0, s, arena, base, nslots, ks, ctrl,
+                     spill);
+  return hipGetLastError();
+}
+
+hipError_t launch_digit_hist(hipStream_t s, int kind, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
+                             uint32_t mask, unsigned long long *hist) {
+  if (n == 0) return hipSuccess;
+  const size_t lds = 4ull * (mask + 1);
+  const int blocks = grid_for(n, 256, 1024);
+  if (kind == 0)
+    hipLaunchKernelGGL(k_digit_hist<0>, dim3(blocks), dim3(256), lds, s, in, n, ks, shift, mask, hist);
+  else
+    hipLaunchKernelGGL(k_digit_hist<1>, dim3(blocks), dim3(256), lds, s, in, n, ks, shift, mask, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_digit_scatter(hipStream_t s, int kind, const uint8_t *in, uint64_t n, const KSpec &ks,
+                                uint32_t shift, uint32_t mask, unsigned long long *cursor, uint8_t *out) {
+  if (n == 0) return hipSuccess;
+  const size_t lds = 4ull * (((mask + 2) & ~1u)) + 8ull * (mask + 1);
+  const int blocks = grid_for(n, 256, 1024);
+  if (kind == 0)
+    hipLaunchKernelGGL(k_digit_scatter<0>, dim3(blocks), dim3(256), lds, s, in, n, ks, shift, mask, cursor, out);
+  else
+    hipLaunchKernelGGL(k_digit_scatter<1>, dim3(blocks), dim3(256), lds, s, in, n, ks, shift, mask, cursor, out);
+  return hipGetLastError();
+}
+
+}  // namespace aggx

@@ -1,0 +1,917 @@
+// Host runtime of the C ABI declared in include/aggx.h.
+//
+// One handle = one GROUP BY query under a device-memory budget.  The runtime
+// plans each hybrid-hash pass ("level"), reserves its tables inside the
+// budget, launches the kernels on the handle's stream, keeps the spilled
+// partitions in pinned host memory, and recursively re-aggregates them
+// (Wen et al., arXiv:1311.0059, Sec. 4.3, Fig. "General Hybrid-hash algorithm
+// structure": Phase 1 hash-partition, Phase 2 recursive hybrid-hash).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/aggx.h"
+#include "aggx_internal.h"
+
+using namespace aggx;
+
+namespace {
+
+constexpr uint64_t kCtrlBytes = 4096;
+constexpr uint64_t kHllBytes = kHllRegs * 4;
+constexpr uint64_t kMetaBytes = (uint64_t)kMaxFan * sizeof(PartMeta);
+constexpr uint64_t kCntBytes = (uint64_t)kMaxFan * 4;
+constexpr uint64_t kOverhead = kCtrlBytes + kHllBytes + kMetaBytes + 2 * kCntBytes;  // fixed part of the budget
+constexpr uint64_t kMinArenaBytes = 64 * 1024;
+constexpr uint64_t kScratchBytes = 128 * 1024;  // pinned host mirror for flag / count / sketch / histogram readbacks
+constexpr uint64_t kMinBudget = 1u << 20;
+constexpr uint64_t kChunkBytes = 512ull << 20;      // input bytes per launch (bounds the spill reservation)
+constexpr uint64_t kPinnedSegment = 256ull << 20;   // pinned spill memory is taken in segments of this size
+constexpr double kDefaultLoad = 0.70;               // planned table load
+constexpr double kMaxLoad = 0.90;                   // groups a table may take before it is full
+constexpr uint64_t kGroupsPerPartition = 16384;     // automatic fan-out target
+
+uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// ---- process-wide caches: pinned spill segments and device blocks ----------
+// Spill segments are pinned (page-locked) host memory mapped into the device
+// address space; kernels write spilled records straight into them and read
+// them back at the next level.  Freed segments are kept for reuse because
+// pinning is slow.
+struct PinnedSeg {
+  uint8_t *host = nullptr;
+  uint8_t *dev = nullptr;
+  uint64_t bytes = 0;
+};
+
+std::mutex g_cache_mu;
+std::vector<PinnedSeg> g_pinned_free;
+struct DevBlock {
+  void *p;
+  uint64_t bytes;
+  int device;
+};
+std::vector<DevBlock> g_dev_free;
+
+bool pinned_get(uint64_t min_bytes, PinnedSeg *out) {
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int best = -1;
+    for (int i = 0; i < (int)g_pinned_free.size(); ++i)
+      if (g_pinned_free[i].bytes >= min_bytes && (best < 0 || g_pinned_free[i].bytes < g_pinned_free[best].bytes)) best = i;
+    if (best >= 0) {
+      *out = g_pinned_free[best];
+      g_pinned_free.erase(g_pinned_free.begin() + best);
+      return true;
+    }
+  }
+  PinnedSeg s;
+  s.bytes = std::max(round_up(min_bytes, 1 << 20), kPinnedSegment);
+  if (hipHostMalloc((void **)&s.host, s.bytes, hipHostMallocMapped) != hipSuccess) return false;
+  if (hipHostGetDevicePointer((void **)&s.dev, s.host, 0) != hipSuccess) {
+    (void)hipHostFree(s.host);
+    return false;
+  }
+  *out = s;
+  return true;
+}
+
+void pinned_put(const PinnedSeg &s) {
+  if (!s.host) return;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_pinned_free.push_back(s);
+}
+
+// Device blocks outside the budget (results) and library-owned budget pools.
+bool dev_get(uint64_t bytes, void **p) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  bytes = round_up(std::max<uint64_t>(bytes, 256), 2 << 20);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (size_t i = 0; i < g_dev_free.size(); ++i)
+      if (g_dev_free[i].bytes == bytes && g_dev_free[i].device == dev) {
+        *p = g_dev_free[i].p;
+        g_dev_free.erase(g_dev_free.begin() + i);
+        return true;
+      }
+  }
+  if (hipMalloc(p, bytes) == hipSuccess) return true;
+  // release cached blocks and retry once
+  std::vector<DevBlock> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    drop.swap(g_dev_free);
+  }
+  for (auto &b : drop) (void)hipFree(b.p);
+  return hipMalloc(p, bytes) == hipSuccess;
+}
+
+void dev_put(void *p, uint64_t bytes) {
+  if (!p) return;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  bytes = round_up(std::max<uint64_t>(bytes, 256), 2 << 20);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_dev_free.push_back({p, bytes, dev});
+}
+
+// A spill run: records (raw) or states written by the kernels into pinned
+// segments.  Each launch gets a contiguous region large enough for its worst
+// case; after the launch the region is trimmed to what was written.
+struct RunPiece {
+  const uint8_t *dev;  // device-visible pointer to the first element
+  uint64_t count;
+};
+
+struct RunSet {
+  std::vector<PinnedSeg> segs;
+  uint64_t cursor = 0;  // bytes used in segs.back()
+  std::vector<RunPiece> raw, state;
+  uint64_t n_raw = 0, n_state = 0;
+
+  bool reserve(uint64_t bytes, uint8_t **dev) {
+    if (segs.empty() || segs.back().bytes - cursor < bytes) {
+      PinnedSeg s;
+      if (!pinned_get(bytes, &s)) return false;
+      segs.push_back(s);
+      cursor = 0;
+    }
+    *dev = segs.back().dev + cursor;
+    return true;
+  }
+  void commit(uint8_t *dev, uint64_t count, uint64_t elem_bytes, bool is_state) {
+    if (count == 0) return;
+    cursor += round_up(count * elem_bytes, 256);
+    if (is_state) {
+      state.push_back({dev, count});
+      n_state += count;
+    } else {
+      raw.push_back({dev, count});
+      n_raw += count;
+    }
+  }
+  void release() {
+    for (auto &s : segs) pinned_put(s);
+    segs.clear();
+    raw.clear();
+    state.clear();
+    cursor = 0;
+    n_raw = n_state = 0;
+  }
+  bool empty() const { return n_raw == 0 && n_state == 0; }
+};
+
+enum HState { H_OPEN = 0, H_FINISHED = 1, H_POISONED = 2 };
+
+struct LevelPlan {
+  uint32_t level = 0;
+  uint32_t fan_bits = 0;
+  uint32_t F = 1;
+  uint32_t digit_shift = 0;  // the digit's lowest bit
+  uint64_t seed_slot = 0;
+  uint64_t arena_slots = 0;
+  uint32_t planned_spilled = 0;
+  std::vector<PartMeta> meta;
+};
+
+}  // namespace
+
+struct agg_handle {
+  agg_spec spec{};
+  KSpec ks{};
+  uint32_t W8 = 0;  // bytes per table slot / state record
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+
+  uint8_t *pool = nullptr;
+  uint64_t pool_bytes = 0;
+  bool own_pool = false;
+  bool unlimited = false;
+
+  Ctrl *d_ctrl = nullptr;
+  uint32_t *d_hll = nullptr;
+  PartMeta *d_meta = nullptr;
+  uint32_t *d_cnt = nullptr;
+  uint32_t *d_ovf = nullptr;
+  uint64_t *d_arena = nullptr;
+  uint64_t arena_cap_bytes = 0;
+
+  Ctrl *h_ctrl = nullptr;       // pinned mirror of the control block
+  uint32_t *h_scratch = nullptr;  // pinned mirror for cnt / ovf / hll readbacks
+
+  LevelPlan plan;
+  bool planned = false;
+  uint32_t used_bits = 0;  // hash bits consumed by the digits of the levels so far
+  RunSet next;             // spill runs written by the current level
+
+  // results
+  uint64_t *r_keys = nullptr;
+  int64_t *r_cols[kMaxAggs] = {};
+  uint64_t r_cap = 0, r_rows = 0;
+  void *r_block = nullptr;
+  uint64_t r_block_bytes = 0;
+
+  int state = H_OPEN;
+  agg_stats st{};
+  uint64_t lvl_in = 0;  // records + states fed to the current level (for the shrink guard)
+};
+
+namespace {
+
+agg_status dev_fail(agg_handle *h, hipError_t e, const char *what) {
+  if (getenv("AGGX_DEBUG")) fprintf(stderr, "aggx: %s failed: %s\n", what, hipGetErrorString(e));
+  h->state = H_POISONED;
+  return AGG_E_DEVICE;
+}
+
+#define HCK(h, expr)                                  \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return dev_fail(h, _e, #expr); \
+  } while (0)
+
+bool valid_type(uint32_t t) { return t <= AGG_I64; }
+uint32_t type_width(uint32_t t) { return (t == AGG_U32 || t == AGG_I32) ? 4 : 8; }
+
+agg_status validate(const agg_spec *s) {
+  if (!s) return AGG_E_INVALID;
+  if (s->record_bytes < 4 || s->record_bytes > 256 || s->record_bytes % 4) return AGG_E_INVALID;
+  if (s->n_keys < 1 || s->n_keys > 2) return AGG_E_INVALID;
+  for (uint32_t i = 0; i < s->n_keys; ++i) {
+    const agg_field &f = s->keys[i];
+    if (!valid_type(f.type)) return AGG_E_INVALID;
+    if (s->n_keys == 2 && f.type != AGG_U32) return AGG_E_INVALID;
+    const uint32_t w = type_width(f.type);
+    if (f.offset % w || f.offset + w > s->record_bytes) return AGG_E_INVALID;
+  }
+  if (s->n_aggs < 1 || s->n_aggs > AGG_MAX_AGGS) return AGG_E_INVALID;
+  for (uint32_t a = 0; a < s->n_aggs; ++a) {
+    const agg_fn &g = s->aggs[a];
+    if (g.op > AGG_MAX) return AGG_E_INVALID;
+    if (g.op == AGG_COUNT) continue;
+    if (!valid_type(g.in.type)) return AGG_E_INVALID;
+    const uint32_t w = type_width(g.in.type);
+    if (g.in.offset % w || g.in.offset + w > s->record_bytes) return AGG_E_INVALID;
+  }
+  // every 8-byte field must stay 8-byte aligned in every record
+  bool wide = s->n_keys == 1 && type_width(s->keys[0].type) == 8;
+  for (uint32_t a = 0; a < s->n_aggs; ++a)
+    if (s->aggs[a].op != AGG_COUNT && type_width(s->aggs[a].in.type) == 8) wide = true;
+  if (wide && s->record_bytes % 8) return AGG_E_INVALID;
+  if (s->fanout_bits > (uint32_t)kMaxFanBits) return AGG_E_INVALID;
+  if (s->load_pct != 0 && (s->load_pct < 10 || s->load_pct > 95)) return AGG_E_INVALID;
+  if (s->policy > AGG_POLICY_PREPART || s->reserved != 0) return AGG_E_INVALID;
+  if (s->device_workspace && (s->workspace_bytes < s->budget_bytes || ((uintptr_t)s->device_workspace & 255)))
+    return AGG_E_BUDGET;
+  if (s->device_workspace && s->budget_bytes == 0) return AGG_E_INVALID;
+  return AGG_OK;
+}
+
+KSpec make_kspec(const agg_spec &s) {
+  KSpec k{};
+  k.rb = s.record_bytes;
+  k.nk = s.n_keys;
+  k.koff0 = s.keys[0].offset;
+  k.koff1 = s.n_keys == 2 ? s.keys[1].offset : 0;
+  k.ktype0 = s.keys[0].type;
+  k.na = s.n_aggs;
+  for (uint32_t a = 0; a < s.n_aggs; ++a) {
+    const agg_fn &g = s.aggs[a];
+    const uint32_t type = g.op == AGG_COUNT ? T_U64 : g.in.type;
+    const uint32_t off = g.op == AGG_COUNT ? 0 : g.in.offset;
+    k.agg[a] = (g.op & 3u) | ((type & 3u) << 2) | (off << 8);
+  }
+  return k;
+}
+
+// Lay out the fixed control region at the start of the pool.
+void carve(agg_handle *h) {
+  uint8_t *p = h->pool;
+  h->d_ctrl = reinterpret_cast<Ctrl *>(p);
+  p += kCtrlBytes;
+  h->d_hll = reinterpret_cast<uint32_t *>(p);
+  p += kHllBytes;
+  h->d_meta = reinterpret_cast<PartMeta *>(p);
+  p += kMetaBytes;
+  h->d_cnt = reinterpret_cast<uint32_t *>(p);
+  p += kCntBytes;
+  h->d_ovf = reinterpret_cast<uint32_t *>(p);
+  p += kCntBytes;
+  h->d_arena = reinterpret_cast<uint64_t *>(p);
+  h->arena_cap_bytes = h->pool_bytes - kOverhead;
+}
+
+// Distinct-key estimate from the HyperLogLog registers (Flajolet et al., 2007:
+// raw estimate with the small-range linear-counting correction).
+double hll_estimate(const uint32_t *regs) {
+  const double m = kHllRegs;
+  double sum = 0.0;
+  uint32_t zeros = 0;
+  for (uint32_t j = 0; j < kHllRegs; ++j) {
+    sum += std::ldexp(1.0, -(int)regs[j]);
+    zeros += regs[j] == 0;
+  }
+  const double alpha = 0.7213 / (1.0 + 1.079 / m);
+  double e = alpha * m * m / sum;
+  if (e <= 2.5 * m && zeros > 0) e = m * std::log(m / zeros);
+  return e;
+}
+
+uint64_t level_seed(uint32_t level) {
+  // distinct odd constants per level for the slot hash (level 0 reuses the digit hash)
+  static const uint64_t seeds[AGG_MAX_LEVELS] = {0,
+                                                 0x9e3779b97f4a7c15ULL,
+                                                 0xbf58476d1ce4e5b9ULL,
+                                                 0x94d049bb133111ebULL,
+                                                 0xd6e8feb86659fd93ULL,
+                                                 0xa0761d6478bd642fULL,
+                                                 0xe7037ed1a0b428dbULL,
+                                                 0x8ebc6af09c88c6e3ULL};
+  return seeds[level % AGG_MAX_LEVELS];
+}
+
+uint32_t floor_log2(uint64_t x) { return x ? 63u - (uint32_t)__builtin_clzll(x) : 0u; }
+
+// Plan one hybrid-hash pass: fan-out, per-partition table sizes, and which
+// partitions are resident.  With an estimate G of the distinct keys, each of
+// the F partitions expects g = G/F groups; a resident table gets room for g
+// plus four standard deviations of the binomial spread, at the planned load.
+// If the budget cannot hold every partition's table, the first T partitions
+// are resident and the rest are spilled from the start -- the in-memory
+// partition plus P spilling partitions of the paper's Formula (1), with T
+// chosen so that the resident tables exactly fill the budget.
+agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_bits) {
+  LevelPlan &pl = h->plan;
+  pl = LevelPlan();
+  pl.level = level;
+  if (G < 1) G = 1;
+  const double lam = h->spec.load_pct ? h->spec.load_pct / 100.0 : kDefaultLoad;
+  const uint64_t W8 = h->W8;
+  const uint32_t bits_left = 64 - consumed_bits;
+  uint32_t b;
+  if (h->spec.fanout_bits) {
+    b = h->spec.fanout_bits;
+  } else {
+    b = floor_log2((uint64_t)std::max(1.0, G / kGroupsPerPartition));
+    if (!h->unlimited) {
+      // at least one partition's table must fit the arena
+      const double need = G * W8 / lam;
+      while (b < (uint32_t)kMaxFanBits && need / (double)(1u << b) > 0.9 * (double)h->arena_cap_bytes) ++b;
+    }
+    b = std::min<uint32_t>(b, kMaxFanBits);
+  }
+  b = std::min(b, bits_left);
+  if (level + 1 >= AGG_MAX_LEVELS && b < bits_left) b = std::min<uint32_t>(bits_left, kMaxFanBits);
+  pl.fan_bits = b;
+  pl.F = 1u << b;
+  pl.digit_shift = b ? 64 - consumed_bits - b : 0;
+  pl.seed_slot = level_seed(level);
+  const double g = G / pl.F;
+  const double cap_need = g + 4.0 * std::sqrt(g) + 16.0;
+  uint64_t slots_need = (uint64_t)std::ceil(cap_need / lam) + 1;
+  uint64_t T = pl.F;
+  uint64_t slots = slots_need;
+  if (h->unlimited) {
+    const uint64_t need = (uint64_t)pl.F * slots * W8;
+    if (need > h->arena_cap_bytes) {
+      // grow the library-owned pool (unlimited budget); the control block and
+      // the sketch carry over (the side group accumulates across levels)
+      const uint64_t bytes = round_up(kOverhead + round_up(need, 1 << 20), 2 << 20);
+      uint8_t *np = nullptr;
+      if (!dev_get(bytes, (void **)&np)) return AGG_E_NOMEM;
+      HCK(h, hipMemcpyAsync(np, h->pool, kCtrlBytes + kHllBytes, hipMemcpyDeviceToDevice, h->stream));
+      HCK(h, hipStreamSynchronize(h->stream));
+      dev_put(h->pool, h->pool_bytes);
+      h->pool = np;
+      h->pool_bytes = bytes;
+      h->st.pool_bytes = bytes;
+      carve(h);
+    }
+  } else {
+    const uint64_t per = slots * W8;
+    T = std::min<uint64_t>(pl.F, h->arena_cap_bytes / per);
+    if (T == 0) {
+      T = 1;
+      slots = std::max<uint64_t>(8, h->arena_cap_bytes / W8);
+    } else if (T == pl.F) {
+      // spread the spare budget over all tables, down to a load of one half
+      const uint64_t spread = h->arena_cap_bytes / ((uint64_t)pl.F * W8);
+      const uint64_t half = (uint64_t)std::ceil(cap_need / 0.5) + 1;
+      slots = std::max(slots, std::min(spread, half));
+    }
+  }
+  if (slots > 0xffffffffULL) slots = 0xffffffffULL;
+  pl.meta.resize(pl.F);
+  uint64_t base = 0;
+  for (uint32_t p = 0; p < pl.F; ++p) {
+    PartMeta &m = pl.meta[p];
+    if (p < T) {
+      m.base = base;
+      m.nslots = (uint32_t)slots;
+      m.cap = (uint32_t)std::min<uint64_t>(slots - 1, (uint64_t)std::floor(slots * kMaxLoad));
+      if (m.cap == 0) m.cap = 1;
+      m.spilled = 0;
+      base += slots;
+    } else {
+      m.base = 0;
+      m.nslots = 0;
+      m.cap = 0;
+      m.spilled = 1;
+    }
+  }
+  pl.arena_slots = base;
+  pl.planned_spilled = pl.F - (uint32_t)T;
+  h->planned = true;
+  const uint64_t used = kOverhead + base * W8;
+  h->st.pool_high_water = std::max(h->st.pool_high_water, used);
+  return AGG_OK;
+}
+
+// Upload the plan and reset the tables, counters and flags for a new level.
+agg_status start_level(agg_handle *h) {
+  LevelPlan &pl = h->plan;
+  HCK(h, hipMemcpyAsync(h->d_meta, pl.meta.data(), sizeof(PartMeta) * pl.F, hipMemcpyHostToDevice, h->stream));
+  HCK(h, launch_u32_fill(h->stream, h->d_cnt, pl.F, 0));
+  HCK(h, launch_u32_fill(h->stream, h->d_ovf, pl.F, 0));
+  HCK(h, launch_table_init(h->stream, h->d_arena, pl.arena_slots, h->ks));
+  HCK(h, launch_u64_set(h->stream, &h->d_ctrl->raw_ctr, 4, 0));  // raw_ctr, state_ctr, rows, any_ovf
+  // the meta upload reads host memory: wait before the vector can change
+  HCK(h, hipStreamSynchronize(h->stream));
+  return AGG_OK;
+}
+
+agg_status read_ctrl(agg_handle *h) {
+  HCK(h, hipMemcpyAsync(h->h_ctrl, h->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+  HCK(h, hipStreamSynchronize(h->stream));
+  return AGG_OK;
+}
+
+KSpill spill_target(agg_handle *h, uint8_t *raw, uint8_t *state) {
+  KSpill s;
+  s.raw = raw;
+  s.state = state;
+  s.hll = h->d_hll;
+  return s;
+}
+
+// Apply the spill policy to partitions whose table became full.
+// Dynamic Destaging (Sec. 4.3.3): the partition is spilled -- its groups are
+// written out as states, its table is released, and all its later records go
+// to the spill run.  With equal per-partition tables, the partition that hit
+// its limit is the fullest one, i.e. the victim the paper's rule picks.
+// Pre-Partitioning (Sec. 4.3.4): nothing to do -- the full table keeps its
+// groups, hits keep aggregating, misses keep spilling.
+agg_status handle_overflow(agg_handle *h) {
+  if (h->h_ctrl->any_ovf == 0) return AGG_OK;
+  LevelPlan &pl = h->plan;
+  HCK(h, hipMemcpyAsync(h->h_scratch, h->d_ovf, 4ull * pl.F, hipMemcpyDeviceToHost, h->stream));
+  HCK(h, hipMemcpyAsync(h->h_scratch + kMaxFan, h->d_cnt, 4ull * pl.F, hipMemcpyDeviceToHost, h->stream));
+  HCK(h, hipStreamSynchronize(h->stream));
+  std::vector<uint32_t> victims;
+  for (uint32_t p = 0; p < pl.F; ++p)
+    if (h->h_scratch[p] && !pl.meta[p].spilled) victims.push_back(p);
+  if (h->spec.policy == AGG_POLICY_DESTAGE) {
+    for (uint32_t p : victims) {
+      PartMeta &m = pl.meta[p];
+      const uint64_t groups = h->h_scratch[kMaxFan + p];  // exact count of inserted groups
+      uint8_t *dst = nullptr;
+      if (!h->next.reserve(std::max<uint64_t>(groups, 1) * h->W8, &dst)) return AGG_E_NOMEM;
+      HCK(h, launch_u64_set(h->stream, &h->d_ctrl->state_ctr, 1, 0));
+      HCK(h, launch_extract(h->stream, h->d_arena, m.base, m.nslots, h->ks, h->d_ctrl, spill_target(h, nullptr, dst)));
+      agg_status s = read_ctrl(h);
+      if (s) return s;
+      h->next.commit(dst, h->h_ctrl->state_ctr, h->W8, true);
+      h->st.states_spilled += h->h_ctrl->state_ctr;
+      h->st.bytes_spilled_d2h += h->h_ctrl->state_ctr * h->W8;
+      m.spilled = 1;
+      m.nslots = 0;
+      m.cap = 0;
+      HCK(h, hipMemcpyAsync(h->d_meta + p, &m, sizeof(PartMeta), hipMemcpyHostToDevice, h->stream));
+      if (pl.level == 0) h->st.partitions_spilled += 1;
+    }
+  }
+  HCK(h, launch_u32_fill(h->stream, h->d_ovf, pl.F, 0));
+  HCK(h, launch_u64_set(h->stream, &h->d_ctrl->any_ovf, 1, 0));
+  HCK(h, hipStreamSynchronize(h->stream));
+  h->h_ctrl->any_ovf = 0;
+  return AGG_OK;
+}
+
+// Run one input stream (raw records or states) through the current level,
+// in launches of at most kChunkBytes so the worst-case spill of each launch
+// has a bounded pinned reservation.
+agg_status run_stream(agg_handle *h, const uint8_t *in, uint64_t n, int kind) {
+  const uint64_t in_bytes = kind == 0 ? h->ks.rb : h->W8;
+  const uint64_t chunk = std::max<uint64_t>(1, kChunkBytes / in_bytes);
+  KLevel lv;
+  lv.level = h->plan.level;
+  lv.digit_shift = h->plan.digit_shift;
+  lv.fan_mask = h->plan.F - 1;
+  lv.slot_shift = h->plan.fan_bits;
+  lv.seed_slot = h->plan.seed_slot;
+  for (uint64_t off = 0; off < n; off += chunk) {
+    const uint64_t c = std::min(chunk, n - off);
+    uint8_t *dst = nullptr;
+    if (!h->next.reserve(c * in_bytes, &dst)) return AGG_E_NOMEM;
+    HCK(h, launch_u64_set(h->stream, kind == 0 ? &h->d_ctrl->raw_ctr : &h->d_ctrl->state_ctr, 1, 0));
+    KSpill sp = spill_target(h, kind == 0 ? dst : nullptr, kind == 0 ? nullptr : dst);
+    HCK(h, launch_update(h->stream, kind, in + off * in_bytes, c, h->ks, lv, h->d_meta, h->d_cnt, h->d_ovf,
+                         h->d_arena, h->d_ctrl, sp, 0));
+    agg_status s = read_ctrl(h);
+    if (s) return s;
+    const uint64_t got = kind == 0 ? h->h_ctrl->raw_ctr : h->h_ctrl->state_ctr;
+    h->next.commit(dst, got, in_bytes, kind == 1);
+    if (kind == 0)
+      h->st.records_spilled += got;
+    else
+      h->st.states_spilled += got;
+    h->st.bytes_spilled_d2h += got * in_bytes;
+    s = handle_overflow(h);
+    if (s) return s;
+  }
+  return AGG_OK;
+}
+
+agg_status ensure_result_cap(agg_handle *h, uint64_t need) {
+  if (need <= h->r_cap) return AGG_OK;
+  const uint64_t cap = std::max<uint64_t>(need, h->r_cap + h->r_cap / 2);
+  const uint64_t ncol = 1 + h->spec.n_aggs;
+  const uint64_t col_bytes = round_up(cap * 8, 256);
+  void *blk = nullptr;
+  if (!dev_get(col_bytes * ncol, &blk)) return AGG_E_NOMEM;
+  uint8_t *b = (uint8_t *)blk;
+  uint64_t *keys = (uint64_t *)b;
+  int64_t *cols[kMaxAggs] = {};
+  for (uint32_t a = 0; a < h->spec.n_aggs; ++a) cols[a] = (int64_t *)(b + col_bytes * (1 + a));
+  if (h->r_rows) {
+    HCK(h, hipMemcpyAsync(keys, h->r_keys, h->r_rows * 8, hipMemcpyDeviceToDevice, h->stream));
+    for (uint32_t a = 0; a < h->spec.n_aggs; ++a)
+      HCK(h, hipMemcpyAsync(cols[a], h->r_cols[a], h->r_rows * 8, hipMemcpyDeviceToDevice, h->stream));
+    HCK(h, hipStreamSynchronize(h->stream));
+  }
+  if (h->r_block) dev_put(h->r_block, h->r_block_bytes);
+  h->r_block = blk;
+  h->r_block_bytes = col_bytes * ncol;
+  h->r_keys = keys;
+  for (uint32_t a = 0; a < kMaxAggs; ++a) h->r_cols[a] = cols[a];
+  h->r_cap = cap;
+  return AGG_OK;
+}
+
+// Flush the resident tables of the current level to the result rows
+// (Sec. 4.3.3: partitions that stay in memory go straight to the final output).
+agg_status flush_level(agg_handle *h, double extra_hint) {
+  LevelPlan &pl = h->plan;
+  HCK(h, hipMemcpyAsync(h->h_scratch + kMaxFan, h->d_cnt, 4ull * pl.F, hipMemcpyDeviceToHost, h->stream));
+  HCK(h, hipStreamSynchronize(h->stream));
+  uint64_t ub = 0;
+  for (uint32_t p = 0; p < pl.F; ++p)
+    if (!pl.meta[p].spilled) ub += h->h_scratch[kMaxFan + p];
+  agg_status s = ensure_result_cap(h, h->r_rows + ub + (uint64_t)extra_hint + 1);
+  if (s) return s;
+  HCK(h, launch_u64_set(h->stream, &h->d_ctrl->rows, 1, 0));
+  OutCols oc{};
+  for (uint32_t a = 0; a < h->spec.n_aggs; ++a) oc.c[a] = h->r_cols[a] + h->r_rows;
+  HCK(h, launch_flush(h->stream, h->d_arena, pl.arena_slots, h->ks, h->r_keys + h->r_rows, oc, h->r_cap - h->r_rows,
+                      h->d_ctrl));
+  s = read_ctrl(h);
+  if (s) return s;
+  if (h->h_ctrl->rows > h->r_cap - h->r_rows) return AGG_E_INTERNAL;
+  h->r_rows += h->h_ctrl->rows;
+  return AGG_OK;
+}
+
+// Records of the two reserved key values were accumulated in side groups.
+agg_status append_side_rows(agg_handle *h) {
+  for (int g = 0; g < 2; ++g) {
+    if (h->h_ctrl->side_n[g] == 0) continue;
+    agg_status s = ensure_result_cap(h, h->r_rows + 1);
+    if (s) return s;
+    const uint64_t key = g == 0 ? kEmpty : kClosed;
+    HCK(h, hipMemcpyAsync(h->r_keys + h->r_rows, &key, 8, hipMemcpyHostToDevice, h->stream));
+    for (uint32_t a = 0; a < h->spec.n_aggs; ++a)
+      HCK(h, hipMemcpyAsync(h->r_cols[a] + h->r_rows, &h->h_ctrl->side[g][a], 8, hipMemcpyHostToDevice, h->stream));
+    HCK(h, hipStreamSynchronize(h->stream));
+    h->r_rows += 1;
+  }
+  return AGG_OK;
+}
+
+// Run the pieces of a run set through the current level: states first, then raw records.
+agg_status run_pieces(agg_handle *h, const std::vector<RunPiece> &state, const std::vector<RunPiece> &raw) {
+  agg_status s = AGG_OK;
+  for (auto &pc : state)
+    if (!s) s = run_stream(h, pc.dev, pc.count, 1);
+  for (auto &pc : raw)
+    if (!s) s = run_stream(h, pc.dev, pc.count, 0);
+  return s;
+}
+
+double read_hll(agg_handle *h, agg_status *st) {
+  *st = AGG_OK;
+  if (hipMemcpyAsync(h->h_scratch, h->d_hll, kHllBytes, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    h->state = H_POISONED;
+    *st = AGG_E_DEVICE;
+    return 0.0;
+  }
+  return hll_estimate(h->h_scratch);
+}
+
+// Grace split (Sec. 4.3, Phase 1 when the groups far exceed memory): scatter
+// every element of `in` into 2^bg sub-runs by the digit below `consumed` bits.
+// Sub-run d is raw[raw_off[d], raw_off[d+1]) and state[st_off[d], st_off[d+1]).
+agg_status grace_split(agg_handle *h, const RunSet &in, uint32_t consumed, uint32_t bg, RunSet &sub,
+                       std::vector<uint64_t> &raw_off, std::vector<uint64_t> &st_off, uint8_t **raw_base,
+                       uint8_t **st_base) {
+  const uint32_t F = 1u << bg, shift = 64 - consumed - bg, mask = F - 1;
+  unsigned long long *d_hraw = reinterpret_cast<unsigned long long *>(h->d_meta);  // meta is idle here
+  unsigned long long *d_hst = d_hraw + kMaxFan;
+  HCK(h, launch_words_init(h->stream, reinterpret_cast<uint64_t *>(d_hraw), 2 * kMaxFan, 0));
+  for (auto &pc : in.raw) HCK(h, launch_digit_hist(h->stream, 0, pc.dev, pc.count, h->ks, shift, mask, d_hraw));
+  for (auto &pc : in.state) HCK(h, launch_digit_hist(h->stream, 1, pc.dev, pc.count, h->ks, shift, mask, d_hst));
+  uint64_t *hh = reinterpret_cast<uint64_t *>(h->h_scratch);
+  HCK(h, hipMemcpyAsync(hh, d_hraw, 2 * kMaxFan * 8, hipMemcpyDeviceToHost, h->stream));
+  HCK(h, hipStreamSynchronize(h->stream));
+  raw_off.assign(F + 1, 0);
+  st_off.assign(F + 1, 0);
+  for (uint32_t d = 0; d < F; ++d) {
+    raw_off[d + 1] = raw_off[d] + hh[d];
+    st_off[d + 1] = st_off[d] + hh[kMaxFan + d];
+  }
+  if (raw_off[F] != in.n_raw || st_off[F] != in.n_state) return AGG_E_INTERNAL;
+  *raw_base = *st_base = nullptr;
+  if (in.n_raw) {
+    PinnedSeg seg;
+    if (!pinned_get(in.n_raw * h->ks.rb, &seg)) return AGG_E_NOMEM;
+    sub.segs.push_back(seg);
+    *raw_base = seg.dev;
+  }
+  if (in.n_state) {
+    PinnedSeg seg;
+    if (!pinned_get(in.n_state * h->W8, &seg)) return AGG_E_NOMEM;
+    sub.segs.push_back(seg);
+    *st_base = seg.dev;
+  }
+  for (uint32_t d = 0; d < F; ++d) {
+    hh[d] = raw_off[d];
+    hh[kMaxFan + d] = st_off[d];
+  }
+  HCK(h, hipMemcpyAsync(d_hraw, hh, 2 * kMaxFan * 8, hipMemcpyHostToDevice, h->stream));
+  for (auto &pc : in.raw)
+    HCK(h, launch_digit_scatter(h->stream, 0, pc.dev, pc.count, h->ks, shift, mask, d_hraw, *raw_base));
+  for (auto &pc : in.state)
+    HCK(h, launch_digit_scatter(h->stream, 1, pc.dev, pc.count, h->ks, shift, mask, d_hst, *st_base));
+  HCK(h, hipStreamSynchronize(h->stream));
+  return AGG_OK;
+}
+
+// One hybrid-hash pass over a run set: plan for G groups with the digit below
+// `consumed` bits, aggregate, spill what does not fit, flush the rest.
+agg_status hybrid_pass(agg_handle *h, uint32_t depth, double G, uint32_t consumed, const std::vector<RunPiece> &state,
+                       const std::vector<RunPiece> &raw, uint32_t *bits_used) {
+  agg_status s = make_plan(h, depth, G, consumed);
+  if (s) return s;
+  *bits_used = h->plan.fan_bits;
+  s = start_level(h);
+  if (s) return s;
+  s = run_pieces(h, state, raw);
+  if (s) return s;
+  return flush_level(h, 0.0);
+}
+
+agg_status finish_impl(agg_handle *h) {
+  if (!h->planned) {
+    agg_status s = make_plan(h, 0, h->spec.est_groups ? (double)h->spec.est_groups : 1.0, 0);
+    if (s) return s;
+    h->used_bits = h->plan.fan_bits;
+    h->st.partitions = h->plan.F;
+    s = start_level(h);
+    if (s) return s;
+  }
+  agg_status s = read_ctrl(h);
+  if (s) return s;
+  // level 0 is complete: estimate the distinct keys of what was spilled
+  double G = h->next.empty() ? 0.0 : read_hll(h, &s);
+  if (s) return s;
+  s = flush_level(h, G * 1.1);
+  if (s) return s;
+  h->st.resident_groups_l0 = h->r_rows;
+  h->st.levels = 1;
+  const double lam = h->spec.load_pct ? h->spec.load_pct / 100.0 : kDefaultLoad;
+  const double cap_groups = h->unlimited ? 1e300 : (double)h->arena_cap_bytes * lam / h->W8;
+  uint32_t consumed = h->used_bits;
+  uint32_t depth = 0;
+  // Phase 2: the spilled partitions are re-aggregated, one level at a time
+  while (!h->next.empty()) {
+    if (++depth >= AGG_MAX_LEVELS || consumed >= 64) return AGG_E_INTERNAL;
+    RunSet in = h->next;
+    h->next = RunSet();
+    const uint64_t fed = in.n_raw + in.n_state;
+    const uint64_t fed_bytes = in.n_raw * h->ks.rb + in.n_state * h->W8;
+    G = std::max(1.0, G * 1.05);
+    HCK(h, launch_u32_fill(h->stream, h->d_hll, kHllRegs, 0));  // sketch of what this level spills
+    uint32_t used = 0;
+    if (G <= 0.8 * cap_groups || consumed + 2 > 64) {
+      s = hybrid_pass(h, depth, G, consumed, in.state, in.raw, &used);
+      consumed += used;
+    } else {
+      // too many groups for one pass: grace-split, then aggregate groups of sub-runs that fit
+      const double target = 0.6 * cap_groups;
+      uint32_t bg = 1;
+      while (bg < (uint32_t)kMaxFanBits && (double)(1u << bg) < 2.0 * G / target) ++bg;
+      bg = std::min(bg, 64 - consumed - 1);
+      RunSet sub;
+      std::vector<uint64_t> roff, soff;
+      uint8_t *rbase = nullptr, *sbase = nullptr;
+      s = grace_split(h, in, consumed, bg, sub, roff, soff, &rbase, &sbase);
+      in.release();
+      // the split reads the run twice and writes it once more
+      h->st.bytes_reloaded_h2d += 2 * fed_bytes;
+      h->st.bytes_spilled_d2h += fed_bytes;
+      const uint32_t F = 1u << bg;
+      const double g_bin = G / F;
+      const uint32_t per = std::max<uint32_t>(1, (uint32_t)std::floor(target / g_bin));
+      uint32_t used_max = 0;
+      for (uint32_t d0 = 0; d0 < F && !s; d0 += per) {
+        const uint32_t d1 = std::min(F, d0 + per);
+        std::vector<RunPiece> gr, gs;
+        if (roff[d1] > roff[d0]) gr.push_back({rbase + roff[d0] * h->ks.rb, roff[d1] - roff[d0]});
+        if (soff[d1] > soff[d0]) gs.push_back({sbase + soff[d0] * h->W8, soff[d1] - soff[d0]});
+        if (gr.empty() && gs.empty()) continue;
+        s = hybrid_pass(h, depth, g_bin * (d1 - d0), consumed + bg, gs, gr, &used);
+        used_max = std::max(used_max, used);
+      }
+      sub.release();
+      consumed += bg + used_max;
+    }
+    h->st.bytes_reloaded_h2d += fed_bytes;
+    in.release();
+    if (s) return s;
+    const uint64_t out = h->next.n_raw + h->next.n_state;
+    if ((double)out > 0.8 * (double)fed) h->st.guard_trips += 1;
+    if (!h->next.empty()) {
+      G = read_hll(h, &s);
+      if (s) return s;
+    }
+    h->st.levels = depth + 1;
+  }
+  s = read_ctrl(h);
+  if (s) return s;
+  s = append_side_rows(h);
+  if (s) return s;
+  h->st.groups_out = h->r_rows;
+  return AGG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *agg_strerror(agg_status s) {
+  switch (s) {
+    case AGG_OK: return "ok";
+    case AGG_E_INVALID: return "invalid spec or argument";
+    case AGG_E_BUDGET: return "memory budget below the minimum working set, or workspace smaller than the budget";
+    case AGG_E_DEVICE: return "HIP device error (handle poisoned)";
+    case AGG_E_STATE: return "call not allowed in the handle's current state";
+    case AGG_E_NOMEM: return "allocation outside the budget failed";
+    case AGG_E_INTERNAL: return "recursion exceeded the hash digit range";
+  }
+  return "unknown status";
+}
+
+uint64_t agg_min_budget(const agg_spec *spec) {
+  (void)spec;
+  return std::max<uint64_t>(kMinBudget, kOverhead + kMinArenaBytes);
+}
+
+agg_status agg_create(const agg_spec *spec, agg_handle **out) {
+  if (!out) return AGG_E_INVALID;
+  *out = nullptr;
+  agg_status s = validate(spec);
+  if (s) return s;
+  if (spec->budget_bytes && spec->budget_bytes < agg_min_budget(spec)) return AGG_E_BUDGET;
+  agg_handle *h = new (std::nothrow) agg_handle();
+  if (!h) return AGG_E_NOMEM;
+  h->spec = *spec;
+  h->ks = make_kspec(*spec);
+  h->W8 = 8 * (1 + spec->n_aggs);
+  (void)hipGetDevice(&h->device);
+  if (spec->stream) {
+    h->stream = (hipStream_t)spec->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete h;
+      return AGG_E_DEVICE;
+    }
+    h->own_stream = true;
+  }
+  if (hipHostMalloc((void **)&h->h_ctrl, sizeof(Ctrl), 0) != hipSuccess ||
+      hipHostMalloc((void **)&h->h_scratch, kScratchBytes, 0) != hipSuccess) {
+    agg_destroy(h);
+    return AGG_E_NOMEM;
+  }
+  h->unlimited = spec->budget_bytes == 0;
+  if (spec->device_workspace) {
+    h->pool = (uint8_t *)spec->device_workspace;
+    h->pool_bytes = spec->budget_bytes;
+  } else {
+    const uint64_t bytes = h->unlimited ? kOverhead + kMinArenaBytes : spec->budget_bytes;
+    if (!dev_get(bytes, (void **)&h->pool)) {
+      agg_destroy(h);
+      return AGG_E_NOMEM;
+    }
+    h->pool_bytes = h->unlimited ? round_up(bytes, 2 << 20) : bytes;
+    h->own_pool = true;
+  }
+  carve(h);
+  h->st.pool_bytes = h->pool_bytes;
+  if (launch_ctrl_init(h->stream, h->d_ctrl, h->ks) != hipSuccess ||
+      launch_u32_fill(h->stream, h->d_hll, kHllRegs, 0) != hipSuccess) {
+    agg_destroy(h);
+    return AGG_E_DEVICE;
+  }
+  if (spec->est_groups) {
+    s = make_plan(h, 0, (double)spec->est_groups, 0);
+    h->used_bits = h->plan.fan_bits;
+    if (!s) s = start_level(h);
+    if (s) {
+      agg_destroy(h);
+      return s;
+    }
+    h->st.partitions = h->plan.F;
+    h->st.partitions_spilled = h->plan.planned_spilled;
+  }
+  *out = h;
+  return AGG_OK;
+}
+
+agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
+  if (!h) return AGG_E_INVALID;
+  if (h->state == H_POISONED) return AGG_E_DEVICE;
+  if (h->state != H_OPEN) return AGG_E_STATE;
+  if (n == 0) return AGG_OK;
+  if (!d_records || ((uintptr_t)d_records & (h->ks.rb % 8 ? 3 : 7))) return AGG_E_INVALID;
+  if (!h->planned) {
+    // no estimate of the distinct keys: plan for what the budget can hold
+    // (unlimited budget: for as many groups as this batch has records)
+    double G = h->unlimited ? (double)n : (double)h->arena_cap_bytes * kDefaultLoad / h->W8;
+    agg_status s = make_plan(h, 0, G, 0);
+    h->used_bits = h->plan.fan_bits;
+    if (!s) s = start_level(h);
+    if (s) return s;
+    h->st.partitions = h->plan.F;
+    h->st.partitions_spilled = h->plan.planned_spilled;
+  }
+  h->st.records_in += n;
+  return run_stream(h, (const uint8_t *)d_records, n, 0);
+}
+
+agg_status agg_finish(agg_handle *h, agg_result *out) {
+  if (!h || !out) return AGG_E_INVALID;
+  if (h->state == H_POISONED) return AGG_E_DEVICE;
+  if (h->state == H_OPEN) {
+    agg_status s = finish_impl(h);
+    if (s) {
+      if (s != AGG_E_DEVICE) h->state = H_POISONED;
+      h->next.release();
+      return s;
+    }
+    h->state = H_FINISHED;
+  }
+  memset(out, 0, sizeof(*out));
+  out->n_rows = h->r_rows;
+  out->d_keys = h->r_keys;
+  for (uint32_t a = 0; a < h->spec.n_aggs; ++a) out->d_cols[a] = h->r_cols[a];
+  return AGG_OK;
+}
+
+agg_status agg_get_stats(const agg_handle *h, agg_stats *out) {
+  if (!h || !out) return AGG_E_INVALID;
+  *out = h->st;
+  return AGG_OK;
+}
+
+void agg_destroy(agg_handle *h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  h->next.release();
+  if (h->own_pool && h->pool) dev_put(h->pool, h->pool_bytes);
+  if (h->r_block) dev_put(h->r_block, h->r_block_bytes);
+  if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
+  if (h->h_scratch) (void)hipHostFree(h->h_scratch);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+}  // extern "C"

@@ -16,7 +16,7 @@ import oracle
 from datagen import workloads
 from tests.wl import brute_force, make_spec, oracle_spec
 
-EDGE_U64 = [0, 1, (1 << 63) - 1, 1 << 63, (1 << 64) - 1]
+EDGE_U64 = [0, 1, (1 << 63) - 1, 1 << 63, (1 << 64) - 2, (1 << 64) - 1]
 EDGE_I64 = [-(1 << 63), -1, 0, 1, (1 << 63) - 1]
 EDGE_I32 = [-(1 << 31), -1, 0, 1, (1 << 31) - 1]
 EDGE_U32 = [0, 1, (1 << 31), (1 << 32) - 1]
