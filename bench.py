@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the bounded-memory hash GROUP BY on one MI355X.
+
+A step is one whole query through the C ABI over one batch that is already
+resident in HBM: agg_create (on a preallocated workspace of the budget's size)
++ agg_consume + agg_finish (every recursion level, result rows in HBM) +
+agg_destroy.  Default workload: 200M R16 records {u64 key, i64 v}, 20M
+distinct uniform keys, v uniform in [-1e6, 1e6], COUNT+SUM+MIN+MAX, 1 GiB
+device budget (forces partition spill and recursive re-aggregation).
+
+Prints one JSON line.  `roofline` describes the dominant kernel (the level-0
+aggregation/routing kernel), timed with HIP events recorded by the library on
+the stream it launches on; `cpu_baseline` is the CPU oracle timed on a bounded
+sample of the same input on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "input records/s + % HBM peak (bit-exact); served p50/p99 latency vs plain path"
+
+WORKLOADS = {
+    "uniform-spill": "uniform_spill",
+    "uniform-small": "uniform_small",
+    "zipf-composite": "zipf_composite",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uniform-spill", choices=sorted(WORKLOADS))
+    ap.add_argument("--policy", default="destage", choices=["destage", "prepart"])
+    ap.add_argument("--cpu-sample", type=int, default=48_000_000,
+                    help="records of the input the CPU oracle is timed on (0 = skip)")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU design is described in DESIGN.md and is not built", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1311_0059_amd as P
+    from datagen import workloads
+
+    wl = getattr(workloads, WORKLOADS[args.workload])()
+    log(args, f"[bench] generating {wl.name}: {wl.n} records x {wl.record_bytes} B, {wl.d} keys")
+    t = time.perf_counter()
+    host = wl.generate()
+    raw = host.view(np.uint8).reshape(-1)
+    log(args, f"[bench] generated in {time.perf_counter() - t:.1f}s, checksum {datagen.checksum(raw[: 1 << 24])}")
+    dev = torch.empty(raw.size, dtype=torch.uint8, device="cuda")
+    dev.copy_(torch.from_numpy(raw))
+    workspace = torch.empty(wl.budget, dtype=torch.uint8, device="cuda") if wl.budget else None
+    torch.cuda.synchronize()
+    spec = P.make_spec(wl.record_bytes, wl.key_fields, wl.aggs, budget=wl.budget, est_groups=wl.d,
+                       workspace=workspace, policy=args.policy)
+    W8 = 8 * (1 + len(wl.aggs))
+
+    def step():
+        g = P.GroupBy(spec)
+        g.consume_ptr(dev.data_ptr(), wl.n)
+        res = g.finish()
+        st = g.stats()
+        g.close()
+        return int(res.n_rows), st
+
+    for i in range(args.warmup):
+        rows, st = step()
+        log(args, f"[bench] warmup {i}: rows={rows} levels={st['levels']} spilled={st['records_spilled']}")
+    torch.cuda.synchronize()
+    agg = {}
+    rows_ok = True
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rows, st = step()
+        rows_ok &= rows == wl.d
+        for k, v in st.items():
+            agg[k] = agg.get(k, 0) + v
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = wl.n * args.steps / elapsed
+    log(args, f"[bench] {args.steps} steps in {elapsed:.3f}s ({ms_per_step:.2f} ms/step)")
+
+    # algorithmic bytes (per unit of work: input read once + result rows written once)
+    alg_bytes_step = wl.n * wl.record_bytes + wl.d * W8
+    # dominant kernel: the level-0 aggregation/routing kernel; its algorithmic bytes are the
+    # records it reads plus the grouping states it leaves in the resident tables
+    l0_bytes = agg["update_records_l0"] * wl.record_bytes + agg["resident_groups_l0"] * W8
+    l0_ms = agg["update_ms_l0"]
+    launches = max(1, agg["update_launches_l0"])
+    achieved = (l0_bytes / launches) / (l0_ms / launches * 1e-3) / 1e9 if l0_ms > 0 else 0.0
+    roofline = {
+        "bound": "hbm",
+        "kernel": "aggx::k_update<0> (level 0)",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBPS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBPS, 4),
+        "traffic": None,
+        "avg_launch_ms": round(l0_ms / launches, 4),
+        "launches_per_step": agg["update_launches_l0"] / args.steps,
+        "bytes_per_launch": int(l0_bytes / launches),
+    }
+
+    cpu = None
+    if rank == 0 and args.cpu_sample > 0:
+        import oracle
+        from tests.wl import oracle_spec  # the oracle's own spec format
+        s = min(args.cpu_sample, wl.n)
+        log(args, f"[bench] timing the CPU oracle on {s} records")
+        tc = time.perf_counter()
+        oracle.groupby(host[:s], oracle_spec(wl))
+        dt = time.perf_counter() - tc
+        cpu = {"value": round(s / dt, 1), "unit": "records/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {s} records of the same input, one run, {dt:.1f}s; single-threaded sort-then-scan"}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "records/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name,
+            "records": wl.n,
+            "record_bytes": wl.record_bytes,
+            "distinct_keys": wl.d,
+            "key_distribution": "zipf s=%.1f" % wl.s if wl.dist == datagen.ZIPF else "uniform",
+            "aggregates": [a[0] for a in wl.aggs],
+            "budget_bytes": wl.budget,
+            "policy": args.policy,
+            "parallelism": "1 GPU",
+        },
+        "gbps_algorithmic": round(alg_bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
+        "pct_hbm_peak": round(100.0 * alg_bytes_step / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 2),
+        "rows_ok": bool(rows_ok),
+        "per_step": {
+            "levels": agg["levels"] / args.steps,
+            "records_spilled": agg["records_spilled"] // args.steps,
+            "states_spilled": agg["states_spilled"] // args.steps,
+            "bytes_spilled_d2h": agg["bytes_spilled_d2h"] // args.steps,
+            "bytes_reloaded_h2d": agg["bytes_reloaded_h2d"] // args.steps,
+            "partitions": agg["partitions"] // args.steps,
+            "partitions_spilled": agg["partitions_spilled"] // args.steps,
+            "resident_groups_l0": agg["resident_groups_l0"] // args.steps,
+            "update_ms": round(agg["update_ms"] / args.steps, 3),
+            "update_ms_l0": round(agg["update_ms_l0"] / args.steps, 3),
+            "flush_ms": round(agg["flush_ms"] / args.steps, 3),
+            "pool_high_water": agg["pool_high_water"] // args.steps,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -125,6 +125,16 @@ typedef struct agg_stats {
   uint32_t guard_trips;         /* spilled partitions that kept more than 80% of their parent's input */
   uint64_t pool_high_water;     /* peak bytes of the working budget in use */
   uint64_t pool_bytes;          /* size of the working budget actually reserved */
+  /* Device time of the two main kernels, measured with HIP events recorded on
+   * the handle's stream around each launch. */
+  uint64_t update_launches;     /* launches of the aggregation/routing kernel (all levels) */
+  uint64_t update_records;      /* records + states they processed */
+  double update_ms;             /* their summed duration */
+  uint64_t update_launches_l0;  /* the level-0 share of the three figures above */
+  uint64_t update_records_l0;
+  double update_ms_l0;
+  uint64_t flush_launches;      /* launches of the kernel that writes result rows */
+  double flush_ms;
 } agg_stats;
 
 /* Validate and copy `spec`, reserve the working budget (or adopt the caller's

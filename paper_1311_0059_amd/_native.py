@@ -62,6 +62,14 @@ class Stats(ctypes.Structure):
         ("guard_trips", ctypes.c_uint32),
         ("pool_high_water", ctypes.c_uint64),
         ("pool_bytes", ctypes.c_uint64),
+        ("update_launches", ctypes.c_uint64),
+        ("update_records", ctypes.c_uint64),
+        ("update_ms", ctypes.c_double),
+        ("update_launches_l0", ctypes.c_uint64),
+        ("update_records_l0", ctypes.c_uint64),
+        ("update_ms_l0", ctypes.c_double),
+        ("flush_launches", ctypes.c_uint64),
+        ("flush_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

@@ -18,6 +18,10 @@ constexpr uint64_t kClosed = ~0ULL - 1;
 constexpr int kMaxAggs = 8;
 constexpr int kMaxFanBits = 12;
 constexpr uint32_t kMaxFan = 1u << kMaxFanBits;
+// Per-partition group counters are updated with device-scope atomics on every
+// insert; each gets its own 128-byte line so that partitions never serialize
+// on a shared line at the memory-side atomic units.
+constexpr uint32_t kCntStride = 32;  // uint32 words per counter
 constexpr int kHllBits = 12;                 // 4096 HyperLogLog registers per sketch
 constexpr uint32_t kHllRegs = 1u << kHllBits;
 

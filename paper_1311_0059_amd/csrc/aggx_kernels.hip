@@ -20,6 +20,8 @@
 // below (MIN) / above (MAX) the true value, so skipping is always safe.
 #include "aggx_internal.h"
 
+#include <algorithm>
+
 namespace aggx {
 
 // MurmurHash3 64-bit finalizer (Appleby), a bijection on 64-bit words.
@@ -163,24 +165,46 @@ __device__ __forceinline__ void in_vals(const uint8_t *rec, const KSpec &ks, uin
 
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 
+// Copy `bytes` (a multiple of 4) between two regions with all threads of the block.
+__device__ __forceinline__ void block_copy(uint32_t *dst, const uint32_t *src, uint32_t bytes) {
+  for (uint32_t w = threadIdx.x; w < bytes / 4; w += blockDim.x) dst[w] = src[w];
+}
+
 // Main pass: every record is routed to its partition's table or to the spill run.
+//
+// The block works on tiles of blockDim.x consecutive records.  A tile is first
+// copied into LDS with dword loads that are contiguous across the block (so the
+// reads are fully coalesced whatever the record width, also when the input is a
+// spilled run in host memory), then each thread routes one record.  Spilled
+// records are gathered in an LDS stage and written out in one piece, with one
+// atomic reservation on the run counter per stage flush.
 template <int KIND>
 __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, uint64_t n, KSpec ks, KLevel lv,
                                                 const PartMeta *__restrict__ meta, uint32_t *cnt, uint32_t *ovf,
-                                                uint64_t *arena, Ctrl *ctrl, KSpill spill) {
+                                                uint64_t *arena, Ctrl *ctrl, KSpill spill, uint32_t stage_cap) {
+  extern __shared__ uint4 lds4[];
+  __shared__ uint32_t s_n;
+  __shared__ unsigned long long s_base;
   const uint32_t W = 1 + ks.na;
   const uint32_t in_bytes = KIND == 0 ? ks.rb : 8 * W;
-  const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  const uint32_t lane = __lane_id();
-  for (uint64_t base = wave * 64; base < n; base += nwaves * 64) {
-    const uint64_t i = base + lane;
-    const bool valid = i < n;
-    const uint8_t *rec = in + (valid ? i : 0) * (uint64_t)in_bytes;
-    uint64_t key = 0;
-    uint64_t vals[kMaxAggs];
+  uint8_t *tile = reinterpret_cast<uint8_t *>(lds4);
+  uint8_t *stage = tile + blockDim.x * in_bytes;
+  uint8_t *region = KIND == 0 ? spill.raw : spill.state;
+  unsigned long long *ctr = KIND == 0 ? &ctrl->raw_ctr : &ctrl->state_ctr;
+  const uint32_t tid = threadIdx.x;
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  for (uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x; t0 < n; t0 += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t nt = (uint32_t)((n - t0) < blockDim.x ? (n - t0) : blockDim.x);
+    block_copy(reinterpret_cast<uint32_t *>(tile), reinterpret_cast<const uint32_t *>(in + t0 * in_bytes),
+               nt * in_bytes);
+    __syncthreads();
+    const bool valid = tid < nt;
+    const uint8_t *rec = tile + (valid ? tid : 0) * in_bytes;
     bool to_spill = false;
+    uint64_t key = 0;
     if (valid) {
+      uint64_t vals[kMaxAggs];
       key = in_key<KIND>(rec, ks);
       in_vals<KIND>(rec, ks, vals);
       if (key >= kClosed) {  // the two reserved values: side groups
@@ -211,14 +235,14 @@ __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, 
             uint64_t *slot = arena + (pm.base + idx) * W;
             uint64_t sk = relaxed_load(slot);
             if (sk == kEmpty) {
-              const bool full = __hip_atomic_load(cnt + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= pm.cap;
+              const bool full = __hip_atomic_load(cnt + p * kCntStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= pm.cap;
               const uint64_t desired = full ? kClosed : key;
               unsigned long long expect = kEmpty;
               __hip_atomic_compare_exchange_strong(reinterpret_cast<unsigned long long *>(slot), &expect,
                                                    (unsigned long long)desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
               if (expect == kEmpty) {
-                if (!full) __hip_atomic_fetch_add(cnt + p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (!full) __hip_atomic_fetch_add(cnt + p * kCntStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 sk = desired;
               } else {
                 sk = expect;
@@ -235,15 +259,31 @@ __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, 
           if (!done) {
             to_spill = true;
             __hip_atomic_store(ovf + p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&ctrl->any_ovf, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctrl->any_ovf, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
       }
     }
-    if (KIND == 0)
-      spill_append(to_spill, rec, ks.rb, spill.raw, &ctrl->raw_ctr, spill.hll, key);
-    else
-      spill_append(to_spill, rec, 8 * W, spill.state, &ctrl->state_ctr, spill.hll, key);
+    if (to_spill) {
+      const uint32_t pos = atomicAdd(&s_n, 1u);
+      uint32_t *dst = reinterpret_cast<uint32_t *>(stage + pos * in_bytes);
+      const uint32_t *src = reinterpret_cast<const uint32_t *>(rec);
+      for (uint32_t w = 0; w < in_bytes / 4; ++w) dst[w] = src[w];
+      hll_add(spill.hll, key);
+    }
+    __syncthreads();
+    const uint32_t staged = s_n;
+    if (staged + blockDim.x > stage_cap || (staged && t0 + (uint64_t)gridDim.x * blockDim.x >= n)) {
+      // flush the stage: one reservation for all staged records, then a block-wide copy
+      if (tid == 0) s_base = __hip_atomic_fetch_add(ctr, (unsigned long long)staged, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      block_copy(reinterpret_cast<uint32_t *>(region + s_base * in_bytes), reinterpret_cast<const uint32_t *>(stage),
+                 staged * in_bytes);
+      __syncthreads();
+      if (tid == 0) s_n = 0;
+      __syncthreads();
+    }
   }
 }
 
@@ -281,32 +321,72 @@ __global__ void k_ctrl_init(Ctrl *c, KSpec ks) {
   }
 }
 
+// Exclusive prefix sum over the block (blockDim.x a multiple of 64, at most 1024).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *total, uint32_t *scratch) {
+  const uint32_t lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  if (lane == 63) scratch[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+      const uint32_t t = scratch[w];
+      scratch[w] = acc;
+      acc += t;
+    }
+    scratch[16] = acc;
+  }
+  __syncthreads();
+  const uint32_t r = scratch[wid] + x - v;
+  *total = scratch[16];
+  __syncthreads();
+  return r;
+}
+
+constexpr uint32_t kFlushPerThread = 16;
+
 // Compact the occupied slots of [arena, arena + nslots) into SoA output rows.
+// Each block takes a tile of blockDim.x * kFlushPerThread slots, counts its
+// rows, reserves them with one atomic, and writes them.
 __global__ void __launch_bounds__(256) k_flush(const uint64_t *__restrict__ arena, uint64_t nslots, KSpec ks,
-                                               uint64_t *out_keys, OutCols out_cols, uint64_t out_cap,
-                                               Ctrl *ctrl) {
+                                               uint64_t *out_keys, OutCols out_cols, uint64_t out_cap, Ctrl *ctrl) {
+  __shared__ uint32_t scratch[32];
+  __shared__ unsigned long long s_base;
   const uint32_t W = 1 + ks.na;
-  const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t base = wave * 64; base < nslots; base += nwaves * 64) {
-    const uint64_t s = base + __lane_id();
-    const uint64_t *slot = arena + (s < nslots ? s : 0) * W;
-    const bool occ = s < nslots && slot[0] < kClosed;
-    const uint64_t mask = __ballot(occ);
-    if (mask == 0) continue;
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    unsigned long long pos0 = 0;
-    if ((int)__lane_id() == leader)
-      pos0 = __hip_atomic_fetch_add(&ctrl->rows, (unsigned long long)__popcll(mask), __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
-    pos0 = __shfl(pos0, leader);
-    if (occ) {
-      const uint64_t r = pos0 + __popcll(mask & lanemask_lt());
+  const uint64_t tile = (uint64_t)blockDim.x * kFlushPerThread;
+  for (uint64_t t0 = blockIdx.x * tile; t0 < nslots; t0 += (uint64_t)gridDim.x * tile) {
+    uint32_t occ = 0, c = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kFlushPerThread; ++j) {
+      const uint64_t s = t0 + (uint64_t)j * blockDim.x + threadIdx.x;
+      if (s < nslots && arena[s * W] < kClosed) {
+        occ |= 1u << j;
+        ++c;
+      }
+    }
+    uint32_t total;
+    const uint32_t pre = block_exclusive_scan(c, &total, scratch);
+    if (total == 0) continue;
+    if (threadIdx.x == 0)
+      s_base = __hip_atomic_fetch_add(&ctrl->rows, (unsigned long long)total, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    uint64_t r = s_base + pre;
+    for (uint32_t j = 0; j < kFlushPerThread; ++j) {
+      if (!(occ >> j & 1u)) continue;
+      const uint64_t *slot = arena + (t0 + (uint64_t)j * blockDim.x + threadIdx.x) * W;
       if (r < out_cap) {
         out_keys[r] = slot[0];
         for (uint32_t a = 0; a < ks.na; ++a) out_cols.c[a][r] = (int64_t)slot[1 + a];
       }
+      ++r;
     }
+    __syncthreads();
   }
 }
 
@@ -422,19 +502,30 @@ hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint6
                          const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint32_t *ovf, uint64_t *arena,
                          Ctrl *ctrl, KSpill spill, int grid_hint) {
   if (n == 0) return hipSuccess;
-  const int blocks = grid_for(n, 256, grid_hint > 0 ? grid_hint : 256 * 16);
+  const uint32_t in_bytes = input_kind == 0 ? ks.rb : 8 * (1 + ks.na);
+  // block size: the tile (block * in_bytes) and a stage of at least twice the tile fit 48 KB of LDS
+  uint32_t block = 256;
+  while (block > 64 && 3ull * block * in_bytes > 49152) block -= 64;
+  const uint32_t stage_bytes = std::max<uint32_t>(2 * block * in_bytes, 16384);
+  const uint32_t stage_cap = stage_bytes / in_bytes;
+  const size_t lds = (size_t)block * in_bytes + stage_bytes;
+  // about four tiles per block: enough blocks that the last wave of blocks is a
+  // small tail, few enough that stage flushes stay rare
+  const int blocks = grid_for(n, block * 4, grid_hint > 0 ? grid_hint : 1 << 20);
   if (input_kind == 0)
-    hipLaunchKernelGGL(k_update<0>, dim3(blocks), dim3(256), 0, s, in, n, ks, lv, meta, cnt, ovf, arena, ctrl, spill);
+    hipLaunchKernelGGL(k_update<0>, dim3(blocks), dim3(block), lds, s, in, n, ks, lv, meta, cnt, ovf, arena, ctrl,
+                       spill, stage_cap);
   else
-    hipLaunchKernelGGL(k_update<1>, dim3(blocks), dim3(256), 0, s, in, n, ks, lv, meta, cnt, ovf, arena, ctrl, spill);
+    hipLaunchKernelGGL(k_update<1>, dim3(blocks), dim3(block), lds, s, in, n, ks, lv, meta, cnt, ovf, arena, ctrl,
+                       spill, stage_cap);
   return hipGetLastError();
 }
 
 hipError_t launch_flush(hipStream_t s, const uint64_t *arena, uint64_t nslots, const KSpec &ks, uint64_t *out_keys,
                         const OutCols &out_cols, uint64_t out_cap, Ctrl *ctrl) {
   if (nslots == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_flush, dim3(grid_for(nslots, 256, 256 * 16)), dim3(256), 0, s, arena, nslots, ks, out_keys,
-                     out_cols, out_cap, ctrl);
+  hipLaunchKernelGGL(k_flush, dim3(grid_for(nslots, 256 * kFlushPerThread, 256 * 16)), dim3(256), 0, s, arena, nslots,
+                     ks, out_keys, out_cols, out_cap, ctrl);
   return hipGetLastError();
 }
 

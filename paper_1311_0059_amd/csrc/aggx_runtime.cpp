@@ -27,8 +27,9 @@ namespace {
 constexpr uint64_t kCtrlBytes = 4096;
 constexpr uint64_t kHllBytes = kHllRegs * 4;
 constexpr uint64_t kMetaBytes = (uint64_t)kMaxFan * sizeof(PartMeta);
-constexpr uint64_t kCntBytes = (uint64_t)kMaxFan * 4;
-constexpr uint64_t kOverhead = kCtrlBytes + kHllBytes + kMetaBytes + 2 * kCntBytes;  // fixed part of the budget
+constexpr uint64_t kCntBytes = (uint64_t)kMaxFan * 4 * kCntStride;  // counters, one 128-byte line each
+constexpr uint64_t kOvfBytes = (uint64_t)kMaxFan * 4;
+constexpr uint64_t kOverhead = kCtrlBytes + kHllBytes + kMetaBytes + kCntBytes + kOvfBytes;  // fixed part of the budget
 constexpr uint64_t kMinArenaBytes = 64 * 1024;
 constexpr uint64_t kScratchBytes = 128 * 1024;  // pinned host mirror for flag / count / sketch / histogram readbacks
 constexpr uint64_t kMinBudget = 1u << 20;
@@ -205,6 +206,7 @@ struct agg_handle {
   uint64_t *d_arena = nullptr;
   uint64_t arena_cap_bytes = 0;
 
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // kernel timing on the handle's stream
   Ctrl *h_ctrl = nullptr;       // pinned mirror of the control block
   uint32_t *h_scratch = nullptr;  // pinned mirror for cnt / ovf / hll readbacks
 
@@ -305,7 +307,7 @@ void carve(agg_handle *h) {
   h->d_cnt = reinterpret_cast<uint32_t *>(p);
   p += kCntBytes;
   h->d_ovf = reinterpret_cast<uint32_t *>(p);
-  p += kCntBytes;
+  p += kOvfBytes;
   h->d_arena = reinterpret_cast<uint64_t *>(p);
   h->arena_cap_bytes = h->pool_bytes - kOverhead;
 }
@@ -440,7 +442,7 @@ agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_
 agg_status start_level(agg_handle *h) {
   LevelPlan &pl = h->plan;
   HCK(h, hipMemcpyAsync(h->d_meta, pl.meta.data(), sizeof(PartMeta) * pl.F, hipMemcpyHostToDevice, h->stream));
-  HCK(h, launch_u32_fill(h->stream, h->d_cnt, pl.F, 0));
+  HCK(h, launch_u32_fill(h->stream, h->d_cnt, (uint64_t)pl.F * kCntStride, 0));
   HCK(h, launch_u32_fill(h->stream, h->d_ovf, pl.F, 0));
   HCK(h, launch_table_init(h->stream, h->d_arena, pl.arena_slots, h->ks));
   HCK(h, launch_u64_set(h->stream, &h->d_ctrl->raw_ctr, 4, 0));  // raw_ctr, state_ctr, rows, any_ovf
@@ -474,7 +476,8 @@ agg_status handle_overflow(agg_handle *h) {
   if (h->h_ctrl->any_ovf == 0) return AGG_OK;
   LevelPlan &pl = h->plan;
   HCK(h, hipMemcpyAsync(h->h_scratch, h->d_ovf, 4ull * pl.F, hipMemcpyDeviceToHost, h->stream));
-  HCK(h, hipMemcpyAsync(h->h_scratch + kMaxFan, h->d_cnt, 4ull * pl.F, hipMemcpyDeviceToHost, h->stream));
+  HCK(h, hipMemcpy2DAsync(h->h_scratch + kMaxFan, 4, h->d_cnt, 4 * kCntStride, 4, pl.F, hipMemcpyDeviceToHost,
+                          h->stream));
   HCK(h, hipStreamSynchronize(h->stream));
   std::vector<uint32_t> victims;
   for (uint32_t p = 0; p < pl.F; ++p)
@@ -524,10 +527,22 @@ agg_status run_stream(agg_handle *h, const uint8_t *in, uint64_t n, int kind) {
     if (!h->next.reserve(c * in_bytes, &dst)) return AGG_E_NOMEM;
     HCK(h, launch_u64_set(h->stream, kind == 0 ? &h->d_ctrl->raw_ctr : &h->d_ctrl->state_ctr, 1, 0));
     KSpill sp = spill_target(h, kind == 0 ? dst : nullptr, kind == 0 ? nullptr : dst);
+    HCK(h, hipEventRecord(h->ev0, h->stream));
     HCK(h, launch_update(h->stream, kind, in + off * in_bytes, c, h->ks, lv, h->d_meta, h->d_cnt, h->d_ovf,
                          h->d_arena, h->d_ctrl, sp, 0));
+    HCK(h, hipEventRecord(h->ev1, h->stream));
     agg_status s = read_ctrl(h);
     if (s) return s;
+    float ms = 0.f;
+    HCK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->st.update_launches += 1;
+    h->st.update_records += c;
+    h->st.update_ms += ms;
+    if (h->plan.level == 0) {
+      h->st.update_launches_l0 += 1;
+      h->st.update_records_l0 += c;
+      h->st.update_ms_l0 += ms;
+    }
     const uint64_t got = kind == 0 ? h->h_ctrl->raw_ctr : h->h_ctrl->state_ctr;
     h->next.commit(dst, got, in_bytes, kind == 1);
     if (kind == 0)
@@ -571,7 +586,8 @@ agg_status ensure_result_cap(agg_handle *h, uint64_t need) {
 // (Sec. 4.3.3: partitions that stay in memory go straight to the final output).
 agg_status flush_level(agg_handle *h, double extra_hint) {
   LevelPlan &pl = h->plan;
-  HCK(h, hipMemcpyAsync(h->h_scratch + kMaxFan, h->d_cnt, 4ull * pl.F, hipMemcpyDeviceToHost, h->stream));
+  HCK(h, hipMemcpy2DAsync(h->h_scratch + kMaxFan, 4, h->d_cnt, 4 * kCntStride, 4, pl.F, hipMemcpyDeviceToHost,
+                          h->stream));
   HCK(h, hipStreamSynchronize(h->stream));
   uint64_t ub = 0;
   for (uint32_t p = 0; p < pl.F; ++p)
@@ -581,10 +597,16 @@ agg_status flush_level(agg_handle *h, double extra_hint) {
   HCK(h, launch_u64_set(h->stream, &h->d_ctrl->rows, 1, 0));
   OutCols oc{};
   for (uint32_t a = 0; a < h->spec.n_aggs; ++a) oc.c[a] = h->r_cols[a] + h->r_rows;
+  HCK(h, hipEventRecord(h->ev0, h->stream));
   HCK(h, launch_flush(h->stream, h->d_arena, pl.arena_slots, h->ks, h->r_keys + h->r_rows, oc, h->r_cap - h->r_rows,
                       h->d_ctrl));
+  HCK(h, hipEventRecord(h->ev1, h->stream));
   s = read_ctrl(h);
   if (s) return s;
+  float ms = 0.f;
+  HCK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  h->st.flush_launches += 1;
+  h->st.flush_ms += ms;
   if (h->h_ctrl->rows > h->r_cap - h->r_rows) return AGG_E_INTERNAL;
   h->r_rows += h->h_ctrl->rows;
   return AGG_OK;
@@ -816,6 +838,10 @@ agg_status agg_create(const agg_spec *spec, agg_handle **out) {
     }
     h->own_stream = true;
   }
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+    agg_destroy(h);
+    return AGG_E_DEVICE;
+  }
   if (hipHostMalloc((void **)&h->h_ctrl, sizeof(Ctrl), 0) != hipSuccess ||
       hipHostMalloc((void **)&h->h_scratch, kScratchBytes, 0) != hipSuccess) {
     agg_destroy(h);
@@ -908,6 +934,8 @@ void agg_destroy(agg_handle *h) {
   h->next.release();
   if (h->own_pool && h->pool) dev_put(h->pool, h->pool_bytes);
   if (h->r_block) dev_put(h->r_block, h->r_block_bytes);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
   if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
   if (h->h_scratch) (void)hipHostFree(h->h_scratch);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
