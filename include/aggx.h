@@ -95,7 +95,9 @@ typedef struct agg_spec {
   uint32_t fanout_bits;      /* partition digit width per level, 0 = automatic (1..12 otherwise) */
   uint32_t load_pct;         /* maximum table load in percent, 0 = automatic (10..95 otherwise) */
   uint32_t policy;           /* agg_policy */
-  uint32_t reserved;         /* must be 0 */
+  uint32_t preagg;           /* workgroup pre-aggregation of repeated keys (early aggregation, Sec. 4.2):
+                                0 = automatic (on when a sample of the first batch shows repeated keys),
+                                1 = always on, 2 = always off */
 } agg_spec;
 
 typedef struct agg_handle agg_handle;
@@ -122,7 +124,9 @@ typedef struct agg_stats {
   uint32_t levels;              /* levels run (1 = no recursion) */
   uint32_t partitions;          /* level-0 partitions (fan-out) */
   uint32_t partitions_spilled;  /* level-0 partitions spilled (planned or overflowed) */
-  uint32_t guard_trips;         /* spilled partitions that kept more than 80% of their parent's input */
+  uint32_t guard_trips;         /* levels whose spilled output kept more than 80% of their input */
+  uint32_t preagg;              /* 1 if the workgroup hot-key cache was used (skew seen in a sample) */
+  uint32_t reserved0;
   uint64_t pool_high_water;     /* peak bytes of the working budget in use */
   uint64_t pool_bytes;          /* size of the working budget actually reserved */
   /* Device time of the two main kernels, measured with HIP events recorded on

@@ -39,7 +39,7 @@ class Spec(ctypes.Structure):
         ("fanout_bits", ctypes.c_uint32),
         ("load_pct", ctypes.c_uint32),
         ("policy", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("preagg", ctypes.c_uint32),
     ]
 
 
@@ -60,6 +60,8 @@ class Stats(ctypes.Structure):
         ("partitions", ctypes.c_uint32),
         ("partitions_spilled", ctypes.c_uint32),
         ("guard_trips", ctypes.c_uint32),
+        ("preagg", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
         ("pool_high_water", ctypes.c_uint64),
         ("pool_bytes", ctypes.c_uint64),
         ("update_launches", ctypes.c_uint64),

@@ -71,7 +71,8 @@ struct Ctrl {
   unsigned long long rows;        // rows appended by the flush kernel
   unsigned long long any_ovf;     // number of overflow events in the last launch (saturating use)
   unsigned long long side_n[2];   // records with the reserved key values kEmpty, kClosed
-  unsigned long long pad[2];
+  unsigned long long sample_dups;  // output of the skew sampling kernel
+  unsigned long long pad;
   unsigned long long side[2][kMaxAggs];  // their side groups' aggregates
 };
 
@@ -96,9 +97,13 @@ hipError_t launch_words_init(hipStream_t s, uint64_t *words, uint64_t nwords, ui
 hipError_t launch_u32_fill(hipStream_t s, uint32_t *p, uint64_t n, uint32_t value);
 hipError_t launch_ctrl_init(hipStream_t s, Ctrl *c, const KSpec &ks);
 // input_kind: 0 = raw records (record layout), 1 = state records (key + na words)
+// preagg: 1 = use the workgroup hot-key cache (skewed inputs)
 hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint64_t n, const KSpec &ks,
                          const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint32_t *ovf, uint64_t *arena,
-                         Ctrl *ctrl, KSpill spill, int grid_hint);
+                         Ctrl *ctrl, KSpill spill, int preagg);
+// Duplicate count among `ns` evenly spaced records of a raw batch (ns <= 4096).
+hipError_t launch_sample_dups(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t ns,
+                              unsigned long long *out);
 hipError_t launch_flush(hipStream_t s, const uint64_t *arena, uint64_t nslots, const KSpec &ks, uint64_t *out_keys,
                         const OutCols &out_cols, uint64_t out_cap, Ctrl *ctrl);
 hipError_t launch_u64_set(hipStream_t s, unsigned long long *p, uint32_t n, unsigned long long v);

@@ -170,6 +170,69 @@ __device__ __forceinline__ void block_copy(uint32_t *dst, const uint32_t *src, u
   for (uint32_t w = threadIdx.x; w < bytes / 4; w += blockDim.x) dst[w] = src[w];
 }
 
+// Fold one contribution into an LDS accumulator (the workgroup's hot-key cache).
+__device__ __forceinline__ void fold_lds(uint64_t *acc, uint32_t stride, const KSpec &ks, const uint64_t *vals) {
+#pragma unroll
+  for (int a = 0; a < kMaxAggs; ++a) {
+    if (a >= (int)ks.na) break;
+    const uint32_t d = ks.agg[a];
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(acc + (uint64_t)a * stride);
+    switch (desc_op(d)) {
+      case OP_COUNT:
+      case OP_SUM: atomicAdd(w, (unsigned long long)vals[a]); break;
+      case OP_MIN:
+        if (type_signed(desc_type(d))) atomicMin(reinterpret_cast<long long *>(w), (long long)vals[a]);
+        else atomicMin(w, (unsigned long long)vals[a]);
+        break;
+      default:
+        if (type_signed(desc_type(d))) atomicMax(reinterpret_cast<long long *>(w), (long long)vals[a]);
+        else atomicMax(w, (unsigned long long)vals[a]);
+        break;
+    }
+  }
+}
+
+// Probe a partition's table for `key`; insert it while the partition has room.
+// Returns the slot index in the arena, or ~0 when the key is not resident (the
+// record must be spilled).
+//
+// Linear probing over at most kProbeLimit slots.  A slot changes once, from
+// kEmpty to a key or to kClosed, and every observation of kEmpty is confirmed by
+// a CAS.  While the partition has room the CAS inserts the key; once its group
+// count reached `cap` the CAS closes the slot instead.  kClosed ends every probe
+// that reaches it, so no key is ever inserted behind it: a record that meets
+// kClosed (or finds no empty slot within the limit) before its key can conclude
+// that the key is not resident and never will be.  A key is therefore either
+// resident for all of its records or spilled for all of them.
+__device__ __forceinline__ uint64_t find_or_insert(uint64_t key, uint64_t hs, const PartMeta &pm, uint32_t p,
+                                                  uint32_t W, uint32_t *cnt, uint64_t *arena) {
+  uint64_t idx = mulhi64(hs, pm.nslots);
+  const uint32_t lim = pm.nslots < kProbeLimit ? pm.nslots : kProbeLimit;
+  for (uint32_t t = 0; t < lim; ++t) {
+    const uint64_t s = pm.base + idx;
+    uint64_t *slot = arena + s * W;
+    uint64_t sk = relaxed_load(slot);
+    if (sk == kEmpty) {
+      const bool full = __hip_atomic_load(cnt + p * kCntStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= pm.cap;
+      const uint64_t desired = full ? kClosed : key;
+      unsigned long long expect = kEmpty;
+      __hip_atomic_compare_exchange_strong(reinterpret_cast<unsigned long long *>(slot), &expect,
+                                           (unsigned long long)desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      if (expect == kEmpty) {
+        if (!full) __hip_atomic_fetch_add(cnt + p * kCntStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sk = desired;
+      } else {
+        sk = expect;
+      }
+    }
+    if (sk == key) return s;
+    if (sk == kClosed) break;
+    idx = (idx + 1 == pm.nslots) ? 0 : idx + 1;
+  }
+  return ~0ULL;
+}
+
 // Main pass: every record is routed to its partition's table or to the spill run.
 //
 // The block works on tiles of blockDim.x consecutive records.  A tile is first
@@ -178,10 +241,19 @@ __device__ __forceinline__ void block_copy(uint32_t *dst, const uint32_t *src, u
 // spilled run in host memory), then each thread routes one record.  Spilled
 // records are gathered in an LDS stage and written out in one piece, with one
 // atomic reservation on the run counter per stage flush.
-template <int KIND>
+//
+// PREAGG: a per-workgroup hot-key cache in LDS pre-aggregates repeated keys
+// (early aggregation, Sec. 4.2; the skewed datasets of Sec. 7.4).  It is
+// write-through: a key enters the cache only after one of its records was
+// folded into its resident global slot, and the cache entry remembers that
+// slot.  Later records of the key in this workgroup fold into LDS; at the end
+// the entry's partial state is added to the slot with one set of atomics.  A
+// key whose record spilled is never cached, so the cache never needs to spill.
+template <int KIND, int PREAGG>
 __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, uint64_t n, KSpec ks, KLevel lv,
                                                 const PartMeta *__restrict__ meta, uint32_t *cnt, uint32_t *ovf,
-                                                uint64_t *arena, Ctrl *ctrl, KSpill spill, uint32_t stage_cap) {
+                                                uint64_t *arena, Ctrl *ctrl, KSpill spill, uint32_t stage_cap,
+                                                uint32_t cache_n) {
   extern __shared__ uint4 lds4[];
   __shared__ uint32_t s_n;
   __shared__ unsigned long long s_base;
@@ -189,10 +261,22 @@ __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, 
   const uint32_t in_bytes = KIND == 0 ? ks.rb : 8 * W;
   uint8_t *tile = reinterpret_cast<uint8_t *>(lds4);
   uint8_t *stage = tile + blockDim.x * in_bytes;
+  // hot-key cache: keys[cache_n], acc[na][cache_n], slot[cache_n], hits[cache_n]
+  uint64_t *c_key = reinterpret_cast<uint64_t *>(stage + ((stage_cap * in_bytes + 7u) & ~7u));
+  uint64_t *c_acc = c_key + cache_n;
+  uint32_t *c_slot = reinterpret_cast<uint32_t *>(c_acc + (uint64_t)ks.na * cache_n);
+  uint32_t *c_hits = c_slot + cache_n;
   uint8_t *region = KIND == 0 ? spill.raw : spill.state;
   unsigned long long *ctr = KIND == 0 ? &ctrl->raw_ctr : &ctrl->state_ctr;
   const uint32_t tid = threadIdx.x;
   if (tid == 0) s_n = 0;
+  if (PREAGG) {
+    for (uint32_t e = tid; e < cache_n; e += blockDim.x) {
+      c_key[e] = kEmpty;
+      c_hits[e] = 0;
+      for (uint32_t a = 0; a < ks.na; ++a) c_acc[(uint64_t)a * cache_n + e] = identity_of(ks.agg[a]);
+    }
+  }
   __syncthreads();
   for (uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x; t0 < n; t0 += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t nt = (uint32_t)((n - t0) < blockDim.x ? (n - t0) : blockDim.x);
@@ -215,51 +299,46 @@ __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, 
         const uint64_t h0 = fmix64(key ^ kSeed0);
         const uint32_t p = lv.fan_mask ? (uint32_t)(h0 >> lv.digit_shift) & lv.fan_mask : 0u;
         const PartMeta pm = meta[p];
-        if (pm.spilled) {
-          to_spill = true;
-        } else {
-          const uint64_t hs = lv.level == 0 ? (h0 << lv.slot_shift) : fmix64(key ^ lv.seed_slot);
-          uint64_t idx = mulhi64(hs, pm.nslots);
-          bool done = false;
-          // Linear probing over at most kProbeLimit slots.  A slot changes
-          // once, from kEmpty to a key or to kClosed, and every observation of
-          // kEmpty is confirmed by a CAS.  While the partition has room the CAS
-          // inserts the key; once its group count reached `cap` the CAS closes
-          // the slot instead.  kClosed ends every probe that reaches it, so no
-          // key is ever inserted behind it: a record that meets kClosed (or
-          // finds no empty slot within the limit) before its key can conclude
-          // that the key is not resident and never will be, and spill.  A key is
-          // therefore either resident for all of its records or spilled for all.
-          const uint32_t lim = pm.nslots < kProbeLimit ? pm.nslots : kProbeLimit;
-          for (uint32_t t = 0; t < lim; ++t) {
-            uint64_t *slot = arena + (pm.base + idx) * W;
-            uint64_t sk = relaxed_load(slot);
-            if (sk == kEmpty) {
-              const bool full = __hip_atomic_load(cnt + p * kCntStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= pm.cap;
-              const uint64_t desired = full ? kClosed : key;
-              unsigned long long expect = kEmpty;
-              __hip_atomic_compare_exchange_strong(reinterpret_cast<unsigned long long *>(slot), &expect,
-                                                   (unsigned long long)desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-              if (expect == kEmpty) {
-                if (!full) __hip_atomic_fetch_add(cnt + p * kCntStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                sk = desired;
-              } else {
-                sk = expect;
-              }
-            }
-            if (sk == key) {
-              fold_global(slot + 1, ks, vals);
+        bool done = false;
+        uint32_t ce = 0;
+        if (PREAGG && !pm.spilled) {
+          // look the key up in the cache (two probes)
+          ce = (uint32_t)(h0 >> 20) & (cache_n - 1);
+          for (int t = 0; t < 2 && !done; ++t) {
+            const uint32_t e = (ce + t) & (cache_n - 1);
+            if (c_key[e] == key) {
+              fold_lds(c_acc + e, cache_n, ks, vals);
+              atomicAdd(&c_hits[e], 1u);
               done = true;
-              break;
             }
-            if (sk == kClosed) break;
-            idx = (idx + 1 == pm.nslots) ? 0 : idx + 1;
           }
-          if (!done) {
+        }
+        if (!done) {
+          if (pm.spilled) {
             to_spill = true;
-            __hip_atomic_store(ovf + p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctrl->any_ovf, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+            const uint64_t hs = lv.level == 0 ? (h0 << lv.slot_shift) : fmix64(key ^ lv.seed_slot);
+            const uint64_t s = find_or_insert(key, hs, pm, p, W, cnt, arena);
+            if (s != ~0ULL) {
+              fold_global(arena + s * W + 1, ks, vals);
+              if (PREAGG) {
+                // remember the resident key in the cache
+                for (int t = 0; t < 2; ++t) {
+                  const uint32_t e = (ce + t) & (cache_n - 1);
+                  if (c_key[e] != kEmpty) continue;
+                  const unsigned long long prev =
+                      atomicCAS(reinterpret_cast<unsigned long long *>(c_key + e), (unsigned long long)kEmpty,
+                                (unsigned long long)key);
+                  // the winner records the slot; it is read only after the block's last barrier
+                  if (prev == kEmpty) c_slot[e] = (uint32_t)s;
+                  if (prev == kEmpty || prev == key) break;
+                }
+              }
+            } else {
+              to_spill = true;
+              __hip_atomic_store(ovf + p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              __hip_atomic_store(&ctrl->any_ovf, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
           }
         }
       }
@@ -285,6 +364,45 @@ __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, 
       __syncthreads();
     }
   }
+  if (PREAGG) {
+    // add the cached partial states to their resident slots
+    for (uint32_t e = tid; e < cache_n; e += blockDim.x) {
+      if (c_key[e] == kEmpty || c_hits[e] == 0) continue;
+      uint64_t vals[kMaxAggs];
+#pragma unroll
+      for (int a = 0; a < kMaxAggs; ++a)
+        if (a < (int)ks.na) vals[a] = c_acc[(uint64_t)a * cache_n + e];
+      fold_global(arena + (uint64_t)c_slot[e] * W + 1, ks, vals);
+    }
+  }
+}
+
+// Distinct keys in a strided sample of a batch: one block inserts `ns` sampled
+// keys into an LDS set and counts the records whose key was already present.
+// The host turns the hot-key cache on when the sample shows repeated keys.
+__global__ void __launch_bounds__(256) k_sample_dups(const uint8_t *__restrict__ in, uint64_t n, KSpec ks, uint32_t ns,
+                                                     unsigned long long *out) {
+  __shared__ unsigned long long set[8192];
+  __shared__ uint32_t dups;
+  for (uint32_t i = threadIdx.x; i < 8192; i += blockDim.x) set[i] = kEmpty;
+  if (threadIdx.x == 0) dups = 0;
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < ns; j += blockDim.x) {
+    const uint64_t i = (uint64_t)j * n / ns;
+    const uint64_t key = read_key(in + i * ks.rb, ks);
+    uint32_t e = (uint32_t)(fmix64(key ^ kSeed0) >> 51);
+    for (int t = 0; t < 64; ++t) {
+      const unsigned long long prev = atomicCAS(&set[e], (unsigned long long)kEmpty, (unsigned long long)key);
+      if (prev == kEmpty) break;
+      if (prev == key) {
+        atomicAdd(&dups, 1u);
+        break;
+      }
+      e = (e + 1) & 8191;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *out = dups;
 }
 
 __global__ void k_table_init(uint64_t *arena, uint64_t nslots, KSpec ks) {
@@ -500,7 +618,7 @@ hipError_t launch_ctrl_init(hipStream_t s, Ctrl *c, const KSpec &ks) {
 
 hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint64_t n, const KSpec &ks,
                          const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint32_t *ovf, uint64_t *arena,
-                         Ctrl *ctrl, KSpill spill, int grid_hint) {
+                         Ctrl *ctrl, KSpill spill, int preagg) {
   if (n == 0) return hipSuccess;
   const uint32_t in_bytes = input_kind == 0 ? ks.rb : 8 * (1 + ks.na);
   // block size: the tile (block * in_bytes) and a stage of at least twice the tile fit 48 KB of LDS
@@ -508,16 +626,32 @@ hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint6
   while (block > 64 && 3ull * block * in_bytes > 49152) block -= 64;
   const uint32_t stage_bytes = std::max<uint32_t>(2 * block * in_bytes, 16384);
   const uint32_t stage_cap = stage_bytes / in_bytes;
-  const size_t lds = (size_t)block * in_bytes + stage_bytes;
+  size_t lds = (size_t)block * in_bytes + (((size_t)stage_cap * in_bytes + 7) & ~(size_t)7);
+  // hot-key cache: 16 + 8 * na bytes per entry, at most 32 KB, a power of two entries
+  uint32_t cache_n = 0;
+  if (preagg) {
+    cache_n = 4096;
+    while (cache_n > 64 && (size_t)cache_n * (16 + 8 * ks.na) > 32768) cache_n >>= 1;
+    lds += (size_t)cache_n * (16 + 8 * ks.na);
+  }
   // about four tiles per block: enough blocks that the last wave of blocks is a
   // small tail, few enough that stage flushes stay rare
-  const int blocks = grid_for(n, block * 4, grid_hint > 0 ? grid_hint : 1 << 20);
-  if (input_kind == 0)
-    hipLaunchKernelGGL(k_update<0>, dim3(blocks), dim3(block), lds, s, in, n, ks, lv, meta, cnt, ovf, arena, ctrl,
-                       spill, stage_cap);
-  else
-    hipLaunchKernelGGL(k_update<1>, dim3(blocks), dim3(block), lds, s, in, n, ks, lv, meta, cnt, ovf, arena, ctrl,
-                       spill, stage_cap);
+  const int blocks = grid_for(n, block * 4, 1 << 20);
+#define AGGX_LAUNCH_UPDATE(K, P)                                                                                      \
+  hipLaunchKernelGGL((k_update<K, P>), dim3(blocks), dim3(block), lds, s, in, n, ks, lv, meta, cnt, ovf, arena, ctrl, \
+                     spill, stage_cap, cache_n)
+  if (input_kind == 0) {
+    if (preagg) AGGX_LAUNCH_UPDATE(0, 1); else AGGX_LAUNCH_UPDATE(0, 0);
+  } else {
+    if (preagg) AGGX_LAUNCH_UPDATE(1, 1); else AGGX_LAUNCH_UPDATE(1, 0);
+  }
+#undef AGGX_LAUNCH_UPDATE
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_dups(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t ns,
+                              unsigned long long *out) {
+  hipLaunchKernelGGL(k_sample_dups, dim3(1), dim3(256), 0, s, in, n, ks, ns, out);
   return hipGetLastError();
 }
 

@@ -222,6 +222,7 @@ struct agg_handle {
   void *r_block = nullptr;
   uint64_t r_block_bytes = 0;
 
+  int preagg = -1;  // hot-key cache in the update kernel: -1 undecided, 0 off, 1 on
   int state = H_OPEN;
   agg_stats st{};
   uint64_t lvl_in = 0;  // records + states fed to the current level (for the shrink guard)
@@ -271,7 +272,7 @@ agg_status validate(const agg_spec *s) {
   if (wide && s->record_bytes % 8) return AGG_E_INVALID;
   if (s->fanout_bits > (uint32_t)kMaxFanBits) return AGG_E_INVALID;
   if (s->load_pct != 0 && (s->load_pct < 10 || s->load_pct > 95)) return AGG_E_INVALID;
-  if (s->policy > AGG_POLICY_PREPART || s->reserved != 0) return AGG_E_INVALID;
+  if (s->policy > AGG_POLICY_PREPART || s->preagg > 2) return AGG_E_INVALID;
   if (s->device_workspace && (s->workspace_bytes < s->budget_bytes || ((uintptr_t)s->device_workspace & 255)))
     return AGG_E_BUDGET;
   if (s->device_workspace && s->budget_bytes == 0) return AGG_E_INVALID;
@@ -529,7 +530,7 @@ agg_status run_stream(agg_handle *h, const uint8_t *in, uint64_t n, int kind) {
     KSpill sp = spill_target(h, kind == 0 ? dst : nullptr, kind == 0 ? nullptr : dst);
     HCK(h, hipEventRecord(h->ev0, h->stream));
     HCK(h, launch_update(h->stream, kind, in + off * in_bytes, c, h->ks, lv, h->d_meta, h->d_cnt, h->d_ovf,
-                         h->d_arena, h->d_ctrl, sp, 0));
+                         h->d_arena, h->d_ctrl, sp, h->preagg > 0 && h->plan.arena_slots < (1ull << 32)));
     HCK(h, hipEventRecord(h->ev1, h->stream));
     agg_status s = read_ctrl(h);
     if (s) return s;
@@ -828,6 +829,7 @@ agg_status agg_create(const agg_spec *spec, agg_handle **out) {
   h->spec = *spec;
   h->ks = make_kspec(*spec);
   h->W8 = 8 * (1 + spec->n_aggs);
+  if (spec->preagg) h->preagg = spec->preagg == 1 ? 1 : 0;
   (void)hipGetDevice(&h->device);
   if (spec->stream) {
     h->stream = (hipStream_t)spec->stream;
@@ -899,6 +901,16 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     h->st.partitions = h->plan.F;
     h->st.partitions_spilled = h->plan.planned_spilled;
   }
+  if (h->preagg < 0) {
+    // Early aggregation pays off when keys repeat within a workgroup's share of
+    // the input: look for repeated keys in an evenly spaced sample of the batch.
+    const uint32_t ns = (uint32_t)std::min<uint64_t>(n, 4096);
+    HCK(h, launch_sample_dups(h->stream, (const uint8_t *)d_records, n, h->ks, ns, &h->d_ctrl->sample_dups));
+    agg_status s = read_ctrl(h);
+    if (s) return s;
+    h->preagg = ns >= 256 && h->h_ctrl->sample_dups * 20 > ns ? 1 : 0;
+  }
+  h->st.preagg = (uint32_t)h->preagg;
   h->st.records_in += n;
   return run_stream(h, (const uint8_t *)d_records, n, 0);
 }

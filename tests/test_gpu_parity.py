@@ -116,8 +116,31 @@ def test_sorted_all_unique_single_key():
 def test_composite_zipf_scaled():
     wl = workloads.zipf_composite().scaled(3_000_000, 300_000)
     rec = wl.generate()
-    k, c, _ = run_lib(rec, **lib_spec_args(wl), budget=8 * MIB, est_groups=wl.d)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=8 * MIB, est_groups=wl.d)
     check_against_oracle(rec, oracle_spec(wl), k, c, "zipf composite")
+    assert st["preagg"] == 1, "skewed input should switch the hot-key cache on"
+
+
+@pytest.mark.parametrize("policy", ["destage", "prepart"])
+@pytest.mark.parametrize("s_exp,preagg", [(0.5, "on"), (1.2, "auto"), (0.0, "on"), (1.2, "off")])
+def test_zipf_hot_key_cache_with_spill(policy, s_exp, preagg):
+    """Hot-key pre-aggregation together with overflow, spill and recursion (the cache forced on
+    also for mild and no skew, and off for strong skew, so both kernel paths see every case)."""
+    wl = workloads.Workload("zipf-spill", "R16", 1_500_000, 300_000, datagen.ZIPF if s_exp else datagen.UNIFORM,
+                            s_exp, -10**6, 10**6, workloads.AGGS_R16_ALL, 3 * MIB, workloads.SEED_BASE + 11)
+    rec = wl.generate()
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=wl.budget, est_groups=wl.d // 4, policy=policy,
+                       preagg=preagg)
+    check_against_oracle(rec, oracle_spec(wl), k, c, f"zipf {s_exp} {policy} {preagg}")
+    assert st["preagg"] == (0 if preagg == "off" else 1) and st["levels"] >= 2
+
+
+def test_uniform_large_keys_space_keeps_cache_off():
+    wl = workloads.uniform_spill().scaled(1_000_000, 900_000)
+    rec = wl.generate()
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d)
+    check_against_oracle(rec, oracle_spec(wl), k, c, "uniform no cache")
+    assert st["preagg"] == 0
 
 
 def test_sum_wraps():
@@ -138,3 +161,14 @@ def test_full_size_uniform_spill():
     k, c, st = run_lib(rec, **lib_spec_args(wl), budget=wl.budget, est_groups=wl.d)
     check_sampled(rec, wl, k, c)
     assert st["pool_high_water"] <= wl.budget
+
+
+@pytest.mark.slow
+def test_full_size_zipf_composite():
+    """500M R24 records, 50M Zipf(1.0) composite keys, 4 GiB budget: sampled rows + invariants."""
+    wl = workloads.zipf_composite()
+    rec = wl.generate()
+    print("case: full zipf1-500M-50M-4GiB", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=wl.budget, est_groups=wl.d)
+    check_sampled(rec, wl, k, c)
+    assert st["pool_high_water"] <= wl.budget and st["preagg"] == 1
