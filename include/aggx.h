@@ -74,6 +74,14 @@ typedef enum agg_policy {
                               key is resident are aggregated, the others are spilled raw */
 } agg_policy;
 
+/* Aggregation engines (both compute the same rows). */
+typedef enum agg_engine {
+  AGG_ENGINE_AUTO = 0,    /* LDS engine when it applies, else HBM tables */
+  AGG_ENGINE_TABLES = 1,  /* per-partition open-addressing tables in HBM, 64-bit atomics, chunked input */
+  AGG_ENGINE_LDS = 2      /* radix-partition the batch, then one workgroup aggregates each partition in an
+                             LDS table; needs the budget to hold the partitioned batch (else falls back) */
+} agg_engine;
+
 #define AGG_MAX_AGGS 8
 #define AGG_MAX_LEVELS 8
 
@@ -98,6 +106,8 @@ typedef struct agg_spec {
   uint32_t preagg;           /* workgroup pre-aggregation of repeated keys (early aggregation, Sec. 4.2):
                                 0 = automatic (on when a sample of the first batch shows repeated keys),
                                 1 = always on, 2 = always off */
+  uint32_t engine;           /* agg_engine */
+  uint32_t reserved;         /* must be 0 */
 } agg_spec;
 
 typedef struct agg_handle agg_handle;
@@ -126,7 +136,7 @@ typedef struct agg_stats {
   uint32_t partitions_spilled;  /* level-0 partitions spilled (planned or overflowed) */
   uint32_t guard_trips;         /* levels whose spilled output kept more than 80% of their input */
   uint32_t preagg;              /* 1 if the workgroup hot-key cache was used (skew seen in a sample) */
-  uint32_t reserved0;
+  uint32_t engine;              /* engine used for the first batch: 1 HBM tables, 2 LDS */
   uint64_t pool_high_water;     /* peak bytes of the working budget in use */
   uint64_t pool_bytes;          /* size of the working budget actually reserved */
   /* Device time of the two main kernels, measured with HIP events recorded on
@@ -139,6 +149,8 @@ typedef struct agg_stats {
   double update_ms_l0;
   uint64_t flush_launches;      /* launches of the kernel that writes result rows */
   double flush_ms;
+  uint64_t lds_launches;        /* launches of the LDS-engine aggregation kernel */
+  double lds_ms;
 } agg_stats;
 
 /* Validate and copy `spec`, reserve the working budget (or adopt the caller's

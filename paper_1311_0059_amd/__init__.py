@@ -38,7 +38,7 @@ def _check(rc: int, what: str):
 
 def make_spec(record_bytes: int, keys, aggs, budget: int = 0, est_groups: int = 0, workspace=None,
               stream=None, fanout_bits: int = 0, load_pct: int = 0, policy: str = "destage",
-              preagg: str = "auto") -> N.Spec:
+              preagg: str = "auto", engine: str = "auto") -> N.Spec:
     """keys: [(offset, type)]; aggs: [(op, offset, type)]; types "u32","u64","i32","i64";
     ops "COUNT","SUM","MIN","MAX".  workspace: optional device tensor of >= budget bytes."""
     s = N.Spec()
@@ -63,6 +63,7 @@ def make_spec(record_bytes: int, keys, aggs, budget: int = 0, est_groups: int = 
     s.load_pct = load_pct
     s.policy = N.POLICIES[policy]
     s.preagg = {"auto": 0, "on": 1, "off": 2}[preagg]
+    s.engine = {"auto": 0, "tables": 1, "lds": 2}[engine]
     return s
 
 

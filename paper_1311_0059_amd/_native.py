@@ -40,6 +40,8 @@ class Spec(ctypes.Structure):
         ("load_pct", ctypes.c_uint32),
         ("policy", ctypes.c_uint32),
         ("preagg", ctypes.c_uint32),
+        ("engine", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -61,7 +63,7 @@ class Stats(ctypes.Structure):
         ("partitions_spilled", ctypes.c_uint32),
         ("guard_trips", ctypes.c_uint32),
         ("preagg", ctypes.c_uint32),
-        ("reserved0", ctypes.c_uint32),
+        ("engine", ctypes.c_uint32),
         ("pool_high_water", ctypes.c_uint64),
         ("pool_bytes", ctypes.c_uint64),
         ("update_launches", ctypes.c_uint64),
@@ -72,6 +74,8 @@ class Stats(ctypes.Structure):
         ("update_ms_l0", ctypes.c_double),
         ("flush_launches", ctypes.c_uint64),
         ("flush_ms", ctypes.c_double),
+        ("lds_launches", ctypes.c_uint64),
+        ("lds_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

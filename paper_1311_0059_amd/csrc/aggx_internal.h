@@ -71,8 +71,8 @@ struct Ctrl {
   unsigned long long rows;        // rows appended by the flush kernel
   unsigned long long any_ovf;     // number of overflow events in the last launch (saturating use)
   unsigned long long side_n[2];   // records with the reserved key values kEmpty, kClosed
-  unsigned long long sample_dups;  // output of the skew sampling kernel
-  unsigned long long pad;
+  unsigned long long sample_dups;  // skew sampling: repeated keys in the sample
+  unsigned long long sample_max;   // skew sampling: most samples sharing one key
   unsigned long long side[2][kMaxAggs];  // their side groups' aggregates
 };
 
@@ -101,7 +101,7 @@ hipError_t launch_ctrl_init(hipStream_t s, Ctrl *c, const KSpec &ks);
 hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint64_t n, const KSpec &ks,
                          const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint32_t *ovf, uint64_t *arena,
                          Ctrl *ctrl, KSpill spill, int preagg);
-// Duplicate count among `ns` evenly spaced records of a raw batch (ns <= 4096).
+// Repeated keys and the largest key multiplicity among `ns` evenly spaced records (ns <= 2048).
 hipError_t launch_sample_dups(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t ns,
                               unsigned long long *out);
 hipError_t launch_flush(hipStream_t s, const uint64_t *arena, uint64_t nslots, const KSpec &ks, uint64_t *out_keys,
@@ -115,5 +115,21 @@ hipError_t launch_digit_hist(hipStream_t s, int kind, const uint8_t *in, uint64_
                              uint32_t mask, unsigned long long *hist);
 hipError_t launch_digit_scatter(hipStream_t s, int kind, const uint8_t *in, uint64_t n, const KSpec &ks,
                                 uint32_t shift, uint32_t mask, unsigned long long *cursor, uint8_t *out);
+// Partition-first LDS engine.
+hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
+                             uint32_t mask, uint64_t chunk, uint32_t *totals);
+hipError_t launch_part_offsets(hipStream_t s, const uint32_t *totals, uint32_t F, unsigned long long *offsets,
+                               unsigned long long *cursors);
+hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
+                               uint32_t mask, uint64_t chunk, unsigned long long *cursors, uint8_t *out);
+hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long long *offsets, uint32_t F,
+                          const KSpec &ks, uint32_t slot_shift, uint32_t nslots, uint32_t cap, uint32_t lds_bytes,
+                          uint32_t stage_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys, const OutCols &out_cols,
+                          uint64_t out_cap);
+hipError_t launch_merge_rows(hipStream_t s, const uint64_t *keys, const OutCols &cols, uint64_t n, const KSpec &ks,
+                             const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint64_t *arena, Ctrl *ctrl,
+                             KSpill spill);
+// Largest dynamic LDS the LDS-aggregation kernel can be launched with (bytes).
+uint32_t lds_agg_max_bytes();
 uint64_t hll_seed();
 }  // namespace aggx

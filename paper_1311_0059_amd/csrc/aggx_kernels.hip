@@ -18,220 +18,13 @@
 // SUM, signed/unsigned min/max).  MIN/MAX first read the current value and
 // skip the atomic when it cannot change the result: a stale read is never
 // below (MIN) / above (MAX) the true value, so skipping is always safe.
-#include "aggx_internal.h"
+#include "aggx_device.h"
 
 #include <algorithm>
 
 namespace aggx {
 
-// MurmurHash3 64-bit finalizer (Appleby), a bijection on 64-bit words.
-__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
-  k ^= k >> 33;
-  k *= 0xff51afd7ed558ccdULL;
-  k ^= k >> 33;
-  k *= 0xc4ceb9fe1a85ec53ULL;
-  k ^= k >> 33;
-  return k;
-}
-
-constexpr uint32_t kProbeLimit = 4096;
-constexpr uint64_t kSeed0 = 0x5851f42d4c957f2dULL;    // digit hash h0 = fmix64(key ^ kSeed0)
-constexpr uint64_t kSeedHll = 0x2545f4914f6cdd1dULL;  // distinct-count sketch hash
 uint64_t hll_seed() { return kSeedHll; }
-
-__device__ __forceinline__ uint32_t ld32(const uint8_t *p) { return *reinterpret_cast<const uint32_t *>(p); }
-__device__ __forceinline__ uint64_t ld64(const uint8_t *p) { return *reinterpret_cast<const uint64_t *>(p); }
-
-__device__ __forceinline__ uint64_t read_field(const uint8_t *rec, uint32_t off, uint32_t type) {
-  switch (type) {
-    case T_U32: return (uint64_t)ld32(rec + off);
-    case T_I32: return (uint64_t)(int64_t)(int32_t)ld32(rec + off);
-    default: return ld64(rec + off);
-  }
-}
-
-__device__ __forceinline__ uint64_t read_key(const uint8_t *rec, const KSpec &ks) {
-  if (ks.nk == 2) return ((uint64_t)ld32(rec + ks.koff0) << 32) | (uint64_t)ld32(rec + ks.koff1);
-  return read_field(rec, ks.koff0, ks.ktype0);
-}
-
-__device__ __forceinline__ uint64_t identity_of(uint32_t d) {
-  switch (desc_op(d)) {
-    case OP_MIN: return type_signed(desc_type(d)) ? (uint64_t)INT64_MAX : ~0ULL;
-    case OP_MAX: return type_signed(desc_type(d)) ? (uint64_t)INT64_MIN : 0ULL;
-    default: return 0ULL;
-  }
-}
-
-__device__ __forceinline__ uint64_t relaxed_load(const uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Fold one contribution (a raw record read as a state with count 1, or a
-// spilled state) into the aggregates starting at `acc`.
-__device__ __forceinline__ void fold_global(uint64_t *acc, const KSpec &ks, const uint64_t *vals) {
-#pragma unroll
-  for (int a = 0; a < kMaxAggs; ++a) {
-    if (a >= (int)ks.na) break;
-    const uint32_t d = ks.agg[a];
-    uint64_t *w = acc + a;
-    const uint64_t v = vals[a];
-    switch (desc_op(d)) {
-      case OP_COUNT:
-      case OP_SUM:
-        __hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(w), (unsigned long long)v, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      case OP_MIN:
-        if (type_signed(desc_type(d))) {
-          if ((int64_t)v < (int64_t)relaxed_load(w))
-            __hip_atomic_fetch_min(reinterpret_cast<long long *>(w), (long long)v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          if (v < relaxed_load(w))
-            __hip_atomic_fetch_min(reinterpret_cast<unsigned long long *>(w), (unsigned long long)v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        break;
-      default:  // OP_MAX
-        if (type_signed(desc_type(d))) {
-          if ((int64_t)v > (int64_t)relaxed_load(w))
-            __hip_atomic_fetch_max(reinterpret_cast<long long *>(w), (long long)v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          if (v > relaxed_load(w))
-            __hip_atomic_fetch_max(reinterpret_cast<unsigned long long *>(w), (unsigned long long)v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        break;
-    }
-  }
-}
-
-// HyperLogLog register update (Flajolet, Fusy, Gandouet, Meunier, 2007).
-__device__ __forceinline__ void hll_add(uint32_t *regs, uint64_t key) {
-  uint64_t x = fmix64(key ^ kSeedHll);
-  uint32_t j = (uint32_t)(x >> (64 - kHllBits));
-  uint64_t w = (x << kHllBits) | (1ULL << (kHllBits - 1));
-  uint32_t rho = (uint32_t)__builtin_clzll(w) + 1;
-  if (rho > __hip_atomic_load(regs + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
-    __hip_atomic_fetch_max(regs + j, rho, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint64_t lanemask_lt() {
-  const uint32_t lane = __lane_id();
-  return lane == 0 ? 0ULL : (~0ULL >> (64 - lane));
-}
-
-// Append the record/state of every lane with `want` set to a spill region, in
-// one atomic per wave.  Must be reached by every lane of the wave.
-__device__ __forceinline__ void spill_append(bool want, const uint8_t *src, uint32_t bytes, uint8_t *region,
-                                             unsigned long long *ctr, uint32_t *hll, uint64_t key) {
-  const uint64_t mask = __ballot(want);
-  if (mask == 0) return;
-  const int leader = __ffsll((unsigned long long)mask) - 1;
-  unsigned long long base = 0;
-  if ((int)__lane_id() == leader)
-    base = __hip_atomic_fetch_add(ctr, (unsigned long long)__popcll(mask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  base = __shfl(base, leader);
-  if (want) {
-    const unsigned long long pos = base + (unsigned long long)__popcll(mask & lanemask_lt());
-    uint32_t *dst = reinterpret_cast<uint32_t *>(region + pos * bytes);
-    const uint32_t *s = reinterpret_cast<const uint32_t *>(src);
-    for (uint32_t i = 0; i < bytes / 4; ++i) dst[i] = s[i];
-    hll_add(hll, key);
-  }
-}
-
-// Input readers: raw records (record layout) or spilled states (key + na words).
-template <int KIND>
-__device__ __forceinline__ uint64_t in_key(const uint8_t *rec, const KSpec &ks) {
-  if (KIND == 0) return read_key(rec, ks);
-  return ld64(rec);
-}
-
-template <int KIND>
-__device__ __forceinline__ void in_vals(const uint8_t *rec, const KSpec &ks, uint64_t *vals) {
-#pragma unroll
-  for (int a = 0; a < kMaxAggs; ++a) {
-    if (a >= (int)ks.na) break;
-    const uint32_t d = ks.agg[a];
-    if (KIND == 0)
-      vals[a] = desc_op(d) == OP_COUNT ? 1ULL : read_field(rec, desc_off(d), desc_type(d));
-    else
-      vals[a] = ld64(rec + 8 + 8 * a);
-  }
-}
-
-__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
-
-// Copy `bytes` (a multiple of 4) between two regions with all threads of the block.
-__device__ __forceinline__ void block_copy(uint32_t *dst, const uint32_t *src, uint32_t bytes) {
-  for (uint32_t w = threadIdx.x; w < bytes / 4; w += blockDim.x) dst[w] = src[w];
-}
-
-// Fold one contribution into an LDS accumulator (the workgroup's hot-key cache).
-__device__ __forceinline__ void fold_lds(uint64_t *acc, uint32_t stride, const KSpec &ks, const uint64_t *vals) {
-#pragma unroll
-  for (int a = 0; a < kMaxAggs; ++a) {
-    if (a >= (int)ks.na) break;
-    const uint32_t d = ks.agg[a];
-    unsigned long long *w = reinterpret_cast<unsigned long long *>(acc + (uint64_t)a * stride);
-    switch (desc_op(d)) {
-      case OP_COUNT:
-      case OP_SUM: atomicAdd(w, (unsigned long long)vals[a]); break;
-      case OP_MIN:
-        if (type_signed(desc_type(d))) atomicMin(reinterpret_cast<long long *>(w), (long long)vals[a]);
-        else atomicMin(w, (unsigned long long)vals[a]);
-        break;
-      default:
-        if (type_signed(desc_type(d))) atomicMax(reinterpret_cast<long long *>(w), (long long)vals[a]);
-        else atomicMax(w, (unsigned long long)vals[a]);
-        break;
-    }
-  }
-}
-
-// Probe a partition's table for `key`; insert it while the partition has room.
-// Returns the slot index in the arena, or ~0 when the key is not resident (the
-// record must be spilled).
-//
-// Linear probing over at most kProbeLimit slots.  A slot changes once, from
-// kEmpty to a key or to kClosed, and every observation of kEmpty is confirmed by
-// a CAS.  While the partition has room the CAS inserts the key; once its group
-// count reached `cap` the CAS closes the slot instead.  kClosed ends every probe
-// that reaches it, so no key is ever inserted behind it: a record that meets
-// kClosed (or finds no empty slot within the limit) before its key can conclude
-// that the key is not resident and never will be.  A key is therefore either
-// resident for all of its records or spilled for all of them.
-__device__ __forceinline__ uint64_t find_or_insert(uint64_t key, uint64_t hs, const PartMeta &pm, uint32_t p,
-                                                  uint32_t W, uint32_t *cnt, uint64_t *arena) {
-  uint64_t idx = mulhi64(hs, pm.nslots);
-  const uint32_t lim = pm.nslots < kProbeLimit ? pm.nslots : kProbeLimit;
-  for (uint32_t t = 0; t < lim; ++t) {
-    const uint64_t s = pm.base + idx;
-    uint64_t *slot = arena + s * W;
-    uint64_t sk = relaxed_load(slot);
-    if (sk == kEmpty) {
-      const bool full = __hip_atomic_load(cnt + p * kCntStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= pm.cap;
-      const uint64_t desired = full ? kClosed : key;
-      unsigned long long expect = kEmpty;
-      __hip_atomic_compare_exchange_strong(reinterpret_cast<unsigned long long *>(slot), &expect,
-                                           (unsigned long long)desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-      if (expect == kEmpty) {
-        if (!full) __hip_atomic_fetch_add(cnt + p * kCntStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sk = desired;
-      } else {
-        sk = expect;
-      }
-    }
-    if (sk == key) return s;
-    if (sk == kClosed) break;
-    idx = (idx + 1 == pm.nslots) ? 0 : idx + 1;
-  }
-  return ~0ULL;
-}
 
 // Main pass: every record is routed to its partition's table or to the spill run.
 //
@@ -377,32 +170,41 @@ __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, 
   }
 }
 
-// Distinct keys in a strided sample of a batch: one block inserts `ns` sampled
-// keys into an LDS set and counts the records whose key was already present.
-// The host turns the hot-key cache on when the sample shows repeated keys.
+// Repeated keys in a strided sample of a batch: one block inserts `ns` sampled
+// keys into an LDS set, counts the records whose key was already present, and
+// the largest number of samples that share one key.  The host turns the
+// hot-key cache on when keys repeat, and keeps skewed inputs (one key holding
+// a large share) away from the partition-per-workgroup engine.
 __global__ void __launch_bounds__(256) k_sample_dups(const uint8_t *__restrict__ in, uint64_t n, KSpec ks, uint32_t ns,
                                                      unsigned long long *out) {
-  __shared__ unsigned long long set[8192];
-  __shared__ uint32_t dups;
-  for (uint32_t i = threadIdx.x; i < 8192; i += blockDim.x) set[i] = kEmpty;
-  if (threadIdx.x == 0) dups = 0;
+  __shared__ unsigned long long set[4096];
+  __shared__ uint32_t cnt[4096];
+  __shared__ uint32_t dups, maxc;
+  for (uint32_t i = threadIdx.x; i < 4096; i += blockDim.x) {
+    set[i] = kEmpty;
+    cnt[i] = 0;
+  }
+  if (threadIdx.x == 0) dups = maxc = 0;
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < ns; j += blockDim.x) {
     const uint64_t i = (uint64_t)j * n / ns;
     const uint64_t key = read_key(in + i * ks.rb, ks);
-    uint32_t e = (uint32_t)(fmix64(key ^ kSeed0) >> 51);
-    for (int t = 0; t < 64; ++t) {
+    uint32_t e = (uint32_t)(fmix64(key ^ kSeed0) >> 52);
+    for (int t = 0; t < 4096; ++t) {
       const unsigned long long prev = atomicCAS(&set[e], (unsigned long long)kEmpty, (unsigned long long)key);
-      if (prev == kEmpty) break;
-      if (prev == key) {
-        atomicAdd(&dups, 1u);
+      if (prev == kEmpty || prev == key) {
+        if (prev == key) atomicAdd(&dups, 1u);
+        atomicMax(&maxc, atomicAdd(&cnt[e], 1u) + 1);
         break;
       }
-      e = (e + 1) & 8191;
+      e = (e + 1) & 4095;
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) *out = dups;
+  if (threadIdx.x == 0) {
+    out[0] = dups;
+    out[1] = maxc;
+  }
 }
 
 __global__ void k_table_init(uint64_t *arena, uint64_t nslots, KSpec ks) {
@@ -437,33 +239,6 @@ __global__ void k_ctrl_init(Ctrl *c, KSpec ks) {
       for (int a = 0; a < kMaxAggs; ++a) c->side[g][a] = a < (int)ks.na ? identity_of(ks.agg[a]) : 0;
     }
   }
-}
-
-// Exclusive prefix sum over the block (blockDim.x a multiple of 64, at most 1024).
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *total, uint32_t *scratch) {
-  const uint32_t lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o);
-    if (lane >= (uint32_t)o) x += y;
-  }
-  if (lane == 63) scratch[wid] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (uint32_t w = 0; w < nw; ++w) {
-      const uint32_t t = scratch[w];
-      scratch[w] = acc;
-      acc += t;
-    }
-    scratch[16] = acc;
-  }
-  __syncthreads();
-  const uint32_t r = scratch[wid] + x - v;
-  *total = scratch[16];
-  __syncthreads();
-  return r;
 }
 
 constexpr uint32_t kFlushPerThread = 16;
@@ -581,13 +356,6 @@ __global__ void __launch_bounds__(256) k_digit_scatter(const uint8_t *__restrict
   }
 }
 
-static int grid_for(uint64_t items, int per_block, int max_blocks) {
-  uint64_t b = (items + per_block - 1) / per_block;
-  if (b < 1) b = 1;
-  if (b > (uint64_t)max_blocks) b = max_blocks;
-  return (int)b;
-}
-
 hipError_t launch_table_init(hipStream_t s, uint64_t *arena, uint64_t nslots, const KSpec &ks) {
   if (nslots == 0) return hipSuccess;
   hipLaunchKernelGGL(k_table_init, dim3(grid_for(nslots, 256, 8192)), dim3(256), 0, s, arena, nslots, ks);
@@ -616,6 +384,27 @@ hipError_t launch_ctrl_init(hipStream_t s, Ctrl *c, const KSpec &ks) {
   return hipGetLastError();
 }
 
+// Blocks of k_update that fit on the device at once (occupancy x compute units).
+static int resident_blocks(uint32_t block, size_t lds, int preagg, int kind) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 1024;
+    cus = prop.multiProcessorCount;
+  }
+  int per_cu = 0;
+  hipError_t e;
+  if (kind == 0)
+    e = preagg ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_update<0, 1>, block, lds)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_update<0, 0>, block, lds);
+  else
+    e = preagg ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_update<1, 1>, block, lds)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_update<1, 0>, block, lds);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  return per_cu * cus;
+}
+
 hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint64_t n, const KSpec &ks,
                          const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint32_t *ovf, uint64_t *arena,
                          Ctrl *ctrl, KSpill spill, int preagg) {
@@ -634,9 +423,14 @@ hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint6
     while (cache_n > 64 && (size_t)cache_n * (16 + 8 * ks.na) > 32768) cache_n >>= 1;
     lds += (size_t)cache_n * (16 + 8 * ks.na);
   }
-  // about four tiles per block: enough blocks that the last wave of blocks is a
-  // small tail, few enough that stage flushes stay rare
-  const int blocks = grid_for(n, block * 4, 1 << 20);
+  // With the hot-key cache: a persistent grid of as many blocks as the chip
+  // holds at once, each striding over many tiles, so that every block's cache
+  // aggregates over a large share of the input.  Without it: about four tiles
+  // per block (measured faster for the atomic-bound path: more blocks in
+  // flight hide the latency of the update atomics).
+  const int blocks = preagg ? std::max(1, std::min(grid_for(n, block, 1 << 20),
+                                                   resident_blocks(block, lds, preagg, input_kind)))
+                            : grid_for(n, block * 4, 1 << 20);
 #define AGGX_LAUNCH_UPDATE(K, P)                                                                                      \
   hipLaunchKernelGGL((k_update<K, P>), dim3(blocks), dim3(block), lds, s, in, n, ks, lv, meta, cnt, ovf, arena, ctrl, \
                      spill, stage_cap, cache_n)

@@ -223,6 +223,8 @@ struct agg_handle {
   uint64_t r_block_bytes = 0;
 
   int preagg = -1;  // hot-key cache in the update kernel: -1 undecided, 0 off, 1 on
+  int engine = 0;   // 0 undecided, 1 HBM tables, 2 partition-first with LDS tables
+  int hot_key = 0;  // the sample showed one key with a large share of the records
   int state = H_OPEN;
   agg_stats st{};
   uint64_t lvl_in = 0;  // records + states fed to the current level (for the shrink guard)
@@ -272,7 +274,7 @@ agg_status validate(const agg_spec *s) {
   if (wide && s->record_bytes % 8) return AGG_E_INVALID;
   if (s->fanout_bits > (uint32_t)kMaxFanBits) return AGG_E_INVALID;
   if (s->load_pct != 0 && (s->load_pct < 10 || s->load_pct > 95)) return AGG_E_INVALID;
-  if (s->policy > AGG_POLICY_PREPART || s->preagg > 2) return AGG_E_INVALID;
+  if (s->policy > AGG_POLICY_PREPART || s->preagg > 2 || s->engine > AGG_ENGINE_LDS) return AGG_E_INVALID;
   if (s->device_workspace && (s->workspace_bytes < s->budget_bytes || ((uintptr_t)s->device_workspace & 255)))
     return AGG_E_BUDGET;
   if (s->device_workspace && s->budget_bytes == 0) return AGG_E_INVALID;
@@ -629,6 +631,139 @@ agg_status append_side_rows(agg_handle *h) {
   return AGG_OK;
 }
 
+// ---- partition-first engine with LDS tables --------------------------------
+struct LdsPlan {
+  uint32_t b = 0, F = 1, nslots = 0, cap = 0, lds_bytes = 0, stage_bytes = 0;
+  uint64_t buf_bytes = 0, need = 0;
+};
+
+constexpr uint32_t kLdsBlock = 512;
+constexpr double kLdsLoad = 0.75;
+
+// Can the batch be aggregated partition by partition in LDS?  Each partition's
+// expected groups (plus four standard deviations) must fit one workgroup's LDS
+// table, with at most 2^12 partitions; the working budget must hold the
+// partitioned copy of the batch and the partition counters.
+bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
+  const uint32_t rb = h->ks.rb;
+  lp->lds_bytes = lds_agg_max_bytes();
+  lp->stage_bytes = 2 * kLdsBlock * rb;
+  if (lp->lds_bytes < lp->stage_bytes + 256 * h->W8) return false;
+  lp->nslots = (lp->lds_bytes - lp->stage_bytes) / h->W8;
+  lp->cap = (uint32_t)(lp->nslots * kLdsLoad);
+  // enough partitions to give every compute unit work, but at least ~256 records each
+  uint32_t b = 0;
+  while (b < 8 && ((uint64_t)kLdsBlock << (b + 1)) <= n) ++b;
+  for (;; ++b) {
+    if (b > (uint32_t)kMaxFanBits) return false;
+    const double g = G / (double)(1u << b);
+    if (g + 4.0 * std::sqrt(g) + 16.0 <= lp->cap) break;
+  }
+  lp->b = b;
+  lp->F = 1u << b;
+  lp->buf_bytes = round_up(n * rb, 256);
+  lp->need = lp->buf_bytes + 2ull * lp->F * 128 + 8ull * (lp->F + 1);
+  return h->unlimited || lp->need <= h->arena_cap_bytes;
+}
+
+agg_status grow_unlimited_pool(agg_handle *h, uint64_t arena_need) {
+  if (arena_need <= h->arena_cap_bytes) return AGG_OK;
+  const uint64_t bytes = round_up(kOverhead + round_up(arena_need, 1 << 20), 2 << 20);
+  uint8_t *np = nullptr;
+  if (!dev_get(bytes, (void **)&np)) return AGG_E_NOMEM;
+  HCK(h, hipMemcpyAsync(np, h->pool, kCtrlBytes + kHllBytes, hipMemcpyDeviceToDevice, h->stream));
+  HCK(h, hipStreamSynchronize(h->stream));
+  dev_put(h->pool, h->pool_bytes);
+  h->pool = np;
+  h->pool_bytes = bytes;
+  h->st.pool_bytes = bytes;
+  carve(h);
+  return AGG_OK;
+}
+
+// Radix-partition the batch into the arena, aggregate each partition in LDS
+// and write its groups to the result; records of partitions whose LDS table
+// filled up go to the spill run.
+agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &lp) {
+  if (h->unlimited) {
+    agg_status s = grow_unlimited_pool(h, lp.need);
+    if (s) return s;
+  }
+  uint8_t *arena = reinterpret_cast<uint8_t *>(h->d_arena);
+  uint8_t *buf = arena;
+  uint32_t *totals = reinterpret_cast<uint32_t *>(arena + lp.buf_bytes);
+  unsigned long long *cursors = reinterpret_cast<unsigned long long *>(arena + lp.buf_bytes + 128ull * lp.F);
+  unsigned long long *offsets = cursors + (uint64_t)lp.F * (kCntStride / 2);
+  h->st.pool_high_water = std::max(h->st.pool_high_water, kOverhead + lp.need);
+  const uint32_t shift = lp.b ? 64 - lp.b : 0, mask = lp.F - 1;
+  // per-block chunks of about 4096 records (at least one block per 2 partitions)
+  const uint64_t chunk = std::max<uint64_t>(1024, std::min<uint64_t>(4096, n / 256 + 1));
+  HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)lp.F * kCntStride, 0));
+  HCK(h, launch_part_count(h->stream, in, n, h->ks, shift, mask, chunk, totals));
+  HCK(h, launch_part_offsets(h->stream, totals, lp.F, offsets, cursors));
+  HCK(h, launch_part_scatter(h->stream, in, n, h->ks, shift, mask, chunk, cursors, buf));
+  uint8_t *dst = nullptr;
+  if (!h->next.reserve(n * h->ks.rb, &dst)) return AGG_E_NOMEM;
+  // rows per partition: at most its slot count (the group limit is checked with
+  // a plain LDS read, so concurrent inserts may pass it by up to one block)
+  agg_status s = ensure_result_cap(h, h->r_rows + std::min<uint64_t>(n, (uint64_t)lp.F * lp.nslots) + 1);
+  if (s) return s;
+  HCK(h, launch_u64_set(h->stream, &h->d_ctrl->raw_ctr, 1, 0));
+  HCK(h, launch_u64_set(h->stream, &h->d_ctrl->rows, 1, 0));
+  OutCols oc{};
+  for (uint32_t a = 0; a < h->spec.n_aggs; ++a) oc.c[a] = h->r_cols[a] + h->r_rows;
+  HCK(h, hipEventRecord(h->ev0, h->stream));
+  HCK(h, launch_lds_agg(h->stream, buf, offsets, lp.F, h->ks, lp.b, lp.nslots, lp.cap, lp.lds_bytes, lp.stage_bytes,
+                        h->d_ctrl, spill_target(h, dst, nullptr), h->r_keys + h->r_rows, oc, h->r_cap - h->r_rows));
+  HCK(h, hipEventRecord(h->ev1, h->stream));
+  s = read_ctrl(h);
+  if (s) return s;
+  float ms = 0.f;
+  HCK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  h->st.lds_launches += 1;
+  h->st.lds_ms += ms;
+  h->next.commit(dst, h->h_ctrl->raw_ctr, h->ks.rb, false);
+  h->st.records_spilled += h->h_ctrl->raw_ctr;
+  h->st.bytes_spilled_d2h += h->h_ctrl->raw_ctr * h->ks.rb;
+  if (h->h_ctrl->rows > h->r_cap - h->r_rows) return AGG_E_INTERNAL;
+  h->r_rows += h->h_ctrl->rows;
+  h->st.partitions = lp.F;
+  h->used_bits = std::max(h->used_bits, lp.b);
+  return AGG_OK;
+}
+
+// A second batch after the LDS path: the rows written so far become grouping
+// states in freshly planned HBM tables, and the query continues there.
+agg_status demote_lds(agg_handle *h, uint64_t n_next) {
+  const double G = h->spec.est_groups ? (double)h->spec.est_groups : (double)(h->r_rows + n_next);
+  agg_status s = make_plan(h, 0, G, 0);
+  if (s) return s;
+  h->used_bits = std::max(h->used_bits, h->plan.fan_bits);
+  s = start_level(h);
+  if (s) return s;
+  uint8_t *dst = nullptr;
+  if (!h->next.reserve(std::max<uint64_t>(h->r_rows, 1) * h->W8, &dst)) return AGG_E_NOMEM;
+  KLevel lv;
+  lv.level = 0;
+  lv.digit_shift = h->plan.digit_shift;
+  lv.fan_mask = h->plan.F - 1;
+  lv.slot_shift = h->plan.fan_bits;
+  lv.seed_slot = h->plan.seed_slot;
+  OutCols oc{};
+  for (uint32_t a = 0; a < h->spec.n_aggs; ++a) oc.c[a] = h->r_cols[a];
+  HCK(h, launch_u64_set(h->stream, &h->d_ctrl->state_ctr, 1, 0));
+  HCK(h, launch_merge_rows(h->stream, h->r_keys, oc, h->r_rows, h->ks, lv, h->d_meta, h->d_cnt, h->d_arena,
+                           h->d_ctrl, spill_target(h, nullptr, dst)));
+  s = read_ctrl(h);
+  if (s) return s;
+  h->next.commit(dst, h->h_ctrl->state_ctr, h->W8, true);
+  h->st.states_spilled += h->h_ctrl->state_ctr;
+  h->st.bytes_spilled_d2h += h->h_ctrl->state_ctr * h->W8;
+  h->r_rows = 0;
+  h->engine = 1;
+  return handle_overflow(h);
+}
+
 // Run the pieces of a run set through the current level: states first, then raw records.
 agg_status run_pieces(agg_handle *h, const std::vector<RunPiece> &state, const std::vector<RunPiece> &raw) {
   agg_status s = AGG_OK;
@@ -713,7 +848,7 @@ agg_status hybrid_pass(agg_handle *h, uint32_t depth, double G, uint32_t consume
 }
 
 agg_status finish_impl(agg_handle *h) {
-  if (!h->planned) {
+  if (!h->planned && h->engine != 2) {
     agg_status s = make_plan(h, 0, h->spec.est_groups ? (double)h->spec.est_groups : 1.0, 0);
     if (s) return s;
     h->used_bits = h->plan.fan_bits;
@@ -726,8 +861,10 @@ agg_status finish_impl(agg_handle *h) {
   // level 0 is complete: estimate the distinct keys of what was spilled
   double G = h->next.empty() ? 0.0 : read_hll(h, &s);
   if (s) return s;
-  s = flush_level(h, G * 1.1);
-  if (s) return s;
+  if (h->engine != 2) {
+    s = flush_level(h, G * 1.1);
+    if (s) return s;
+  }
   h->st.resident_groups_l0 = h->r_rows;
   h->st.levels = 1;
   const double lam = h->spec.load_pct ? h->spec.load_pct / 100.0 : kDefaultLoad;
@@ -869,7 +1006,10 @@ agg_status agg_create(const agg_spec *spec, agg_handle **out) {
     agg_destroy(h);
     return AGG_E_DEVICE;
   }
-  if (spec->est_groups) {
+  if (spec->engine == AGG_ENGINE_TABLES && spec->est_groups) {
+    // tables requested: plan and clear them now, outside the first consume
+    h->engine = 1;
+    h->st.engine = 1;
     s = make_plan(h, 0, (double)spec->est_groups, 0);
     h->used_bits = h->plan.fan_bits;
     if (!s) s = start_level(h);
@@ -890,28 +1030,51 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
   if (h->state != H_OPEN) return AGG_E_STATE;
   if (n == 0) return AGG_OK;
   if (!d_records || ((uintptr_t)d_records & (h->ks.rb % 8 ? 3 : 7))) return AGG_E_INVALID;
+  if (h->engine == 0) {
+    // Early aggregation pays off when keys repeat within a workgroup's share of
+    // the input: look for repeated keys in an evenly spaced sample of the batch.
+    const uint32_t ns = (uint32_t)std::min<uint64_t>(n, 2048);  // the sampler's set has 4096 slots
+    HCK(h, launch_sample_dups(h->stream, (const uint8_t *)d_records, n, h->ks, ns, &h->d_ctrl->sample_dups));
+    agg_status s = read_ctrl(h);
+    if (s) return s;
+    // repeated keys in more than 5% of the sample: pre-aggregate; one key in more
+    // than 2% of it: a hot key that would unbalance a partition-per-workgroup pass
+    if (h->preagg < 0) h->preagg = ns >= 256 && h->h_ctrl->sample_dups * 20 > ns ? 1 : 0;
+    h->hot_key = ns >= 256 && h->h_ctrl->sample_max * 50 > ns;
+  }
+  h->st.preagg = (uint32_t)h->preagg;
+  h->st.records_in += n;
+  if (h->engine == 0) {
+    // First batch: partition-first with LDS tables when the input shows no
+    // repeated-key skew (skew would unbalance the partitions) and the budget
+    // holds the partitioned batch; otherwise per-partition HBM tables.
+    LdsPlan lp;
+    const double G = h->spec.est_groups ? (double)h->spec.est_groups : (double)n;
+    if (h->spec.engine != AGG_ENGINE_TABLES && (h->spec.engine == AGG_ENGINE_LDS || !h->hot_key) &&
+        n * h->ks.rb <= (1ull << 30) && lds_plan(h, n, G, &lp)) {
+      h->engine = 2;
+      h->st.engine = 2;
+      return run_lds(h, (const uint8_t *)d_records, n, lp);
+    }
+    h->engine = 1;
+    h->st.engine = 1;
+  } else if (h->engine == 2) {
+    agg_status s = demote_lds(h, n);
+    if (s) return s;
+  }
   if (!h->planned) {
     // no estimate of the distinct keys: plan for what the budget can hold
     // (unlimited budget: for as many groups as this batch has records)
-    double G = h->unlimited ? (double)n : (double)h->arena_cap_bytes * kDefaultLoad / h->W8;
+    double G = h->spec.est_groups ? (double)h->spec.est_groups
+               : h->unlimited     ? (double)n
+                                  : (double)h->arena_cap_bytes * kDefaultLoad / h->W8;
     agg_status s = make_plan(h, 0, G, 0);
-    h->used_bits = h->plan.fan_bits;
+    h->used_bits = std::max(h->used_bits, h->plan.fan_bits);
     if (!s) s = start_level(h);
     if (s) return s;
     h->st.partitions = h->plan.F;
     h->st.partitions_spilled = h->plan.planned_spilled;
   }
-  if (h->preagg < 0) {
-    // Early aggregation pays off when keys repeat within a workgroup's share of
-    // the input: look for repeated keys in an evenly spaced sample of the batch.
-    const uint32_t ns = (uint32_t)std::min<uint64_t>(n, 4096);
-    HCK(h, launch_sample_dups(h->stream, (const uint8_t *)d_records, n, h->ks, ns, &h->d_ctrl->sample_dups));
-    agg_status s = read_ctrl(h);
-    if (s) return s;
-    h->preagg = ns >= 256 && h->h_ctrl->sample_dups * 20 > ns ? 1 : 0;
-  }
-  h->st.preagg = (uint32_t)h->preagg;
-  h->st.records_in += n;
   return run_stream(h, (const uint8_t *)d_records, n, 0);
 }
 

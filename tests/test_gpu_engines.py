@@ -1,0 +1,96 @@
+"""GPU parity of the partition-first LDS engine and of the engine choice.
+
+Every case compares all rows with the CPU oracle.  The LDS engine is forced on
+for the edge-case layouts, driven into LDS-table overflow (spill + recursion)
+by an underestimated group count, continued with more batches (its rows are
+then merged into HBM tables), and refused when the budget cannot hold the
+partitioned batch.
+"""
+import numpy as np
+import pytest
+
+import datagen
+from datagen import workloads
+from tests.gpu_util import assert_rows_equal, check_against_oracle, lib_spec_args, run_lib
+from tests.test_oracle import SPEC_MIX, SPEC_R16, SPEC_R24, _pool, _rand_mix, _rand_r16, _rand_r24
+from tests.wl import oracle_spec
+
+pytestmark = pytest.mark.gpu
+MIB = 1 << 20
+
+
+def _lib_args(spec):
+    return dict(record_bytes=spec["record_bytes"], keys=spec["keys"], aggs=spec["aggs"])
+
+
+@pytest.mark.parametrize("n,d", [(1_000_000, 10_000), (777_777, 123_457), (513, 500), (70_000, 1)])
+def test_lds_engine_exact(n, d):
+    wl = workloads.uniform_small().scaled(n, d)
+    rec = wl.generate()
+    print(f"case: lds n={n} d={d}", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d, engine="lds")
+    check_against_oracle(rec, oracle_spec(wl), k, c, f"lds {n} {d}")
+    assert st["engine"] == 2 and st["levels"] == 1
+
+
+@pytest.mark.parametrize("layout", ["R16", "R24", "MIX"])
+def test_lds_engine_edge_layouts(layout):
+    rng = np.random.default_rng(99)
+    gen, spec = {"R16": (_rand_r16, SPEC_R16), "R24": (_rand_r24, SPEC_R24), "MIX": (_rand_mix, SPEC_MIX)}[layout]
+    for case in range(8):
+        n = int(rng.integers(1, 5000))
+        rec = gen(rng, n, _pool(rng, int(rng.integers(1, 60))))
+        k, c, st = run_lib(rec, **_lib_args(spec), est_groups=int(rng.integers(1, 100)), engine="lds")
+        check_against_oracle(rec, spec, k, c, f"lds {layout} {case}")
+        assert st["engine"] == 2
+
+
+@pytest.mark.parametrize("scale", [50, 400])
+def test_lds_overflow_spills_and_recurses(scale):
+    """An estimate far below the true group count gives too few partitions: LDS tables fill,
+    new keys spill raw and are re-aggregated at the next level."""
+    wl = workloads.uniform_spill().scaled(1_500_000, 1_200_000)
+    rec = wl.generate()
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d // scale, engine="lds")
+    check_against_oracle(rec, oracle_spec(wl), k, c, f"lds overflow /{scale}")
+    assert st["engine"] == 2 and st["levels"] >= 2 and st["records_spilled"] > 0
+
+
+@pytest.mark.parametrize("budget", [0, 64 * MIB])
+def test_lds_then_more_batches(budget):
+    """Rows of the first (LDS) batch become states in HBM tables when more batches come."""
+    wl = workloads.uniform_spill().scaled(900_000, 90_000)
+    rec = wl.generate()
+    a = run_lib(rec, **lib_spec_args(wl), budget=budget, est_groups=wl.d, batches=5, engine="lds")
+    check_against_oracle(rec, oracle_spec(wl), a[0], a[1], "lds + batches")
+    assert a[2]["engine"] == 2
+
+
+def test_lds_refused_when_budget_cannot_hold_batch():
+    wl = workloads.uniform_spill().scaled(1_000_000, 100_000)
+    rec = wl.generate()
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=8 * MIB, est_groups=wl.d, engine="lds")
+    check_against_oracle(rec, oracle_spec(wl), k, c, "lds refused")
+    assert st["engine"] == 1
+
+
+def test_automatic_engine_choice():
+    wl = workloads.uniform_small()
+    rec = wl.generate()
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d)
+    check_against_oracle(rec, oracle_spec(wl), k, c, "auto uniform")
+    assert st["engine"] == 2, "uniform keys with an ample budget should take the LDS engine"
+    hh = workloads.heavy_hitter(400_000, 5_000)
+    rec = hh.generate()
+    k, c, st = run_lib(rec, **lib_spec_args(hh), est_groups=hh.d)
+    check_against_oracle(rec, oracle_spec(hh), k, c, "auto heavy hitter")
+    assert st["engine"] == 1 and st["preagg"] == 1, "a heavy hitter should take HBM tables with the hot-key cache"
+
+
+def test_engines_agree():
+    wl = workloads.uniform_spill().scaled(500_000, 60_000)
+    rec = wl.generate()
+    a = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d, engine="lds")
+    b = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d, engine="tables")
+    assert a[2]["engine"] == 2 and b[2]["engine"] == 1
+    assert_rows_equal(a[0], a[1], b[0], b[1], "lds vs tables")
