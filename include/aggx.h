@@ -13,7 +13,7 @@
  *     hash tables, partitions that overflow the budget are spilled, and the
  *     spilled partitions are re-aggregated recursively with a new hash digit
  *     per level (Sec. 4.3, Fig. "General Hybrid-hash algorithm structure",
- *     Phases 1 and 2; Sec. 4.3.3 Dynamic Destaging; Sec. 7.7 per-level hash
+ *     Phases 1 and 2; Sec. 4.3.3 Dynamic Destaging; Sec. 6.7 per-level hash
  *     seeds);
  *   - the number of distinct keys G is an optional input (Sec. 4.3, Formula
  *     (1) and the text after it), used only to plan partitions.

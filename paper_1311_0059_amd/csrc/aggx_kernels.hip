@@ -9,7 +9,7 @@
 //     key that finds its partition full is spilled raw, and its partition is
 //     flagged so that the host applies the spill policy;
 //   - Murmur hashing with a separate hash per level keeps adjacent levels
-//     uncorrelated (Sec. 7.7).  The partition digit of every level is a
+//     uncorrelated (Sec. 6.7, "Hash Implementation Issues").  The partition digit of every level is a
 //     disjoint bit field of one bijective 64-bit hash h0, so recursion always
 //     terminates; slots use an independently seeded hash per level.
 //
@@ -36,7 +36,7 @@ uint64_t hll_seed() { return kSeedHll; }
 // atomic reservation on the run counter per stage flush.
 //
 // PREAGG: a per-workgroup hot-key cache in LDS pre-aggregates repeated keys
-// (early aggregation, Sec. 4.2; the skewed datasets of Sec. 7.4).  It is
+// (early aggregation, Sec. 4.2; the skewed datasets of Sec. 6.4).  It is
 // write-through: a key enters the cache only after one of its records was
 // folded into its resident global slot, and the cache entry remembers that
 // slot.  Later records of the key in this workgroup fold into LDS; at the end

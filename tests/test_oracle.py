@@ -118,7 +118,7 @@ def test_sum_wraps_modulo_2_64():
 
 
 def test_heavy_hitter_closed_form():
-    """The paper's heavy-hitter set (Sec. 7.4): one key gets n-(d-1) records, all others one each."""
+    """The paper's heavy-hitter set (Sec. 6.4, "Aggregating Skewed Data"): one key gets n-(d-1) records, all others one each."""
     wl = workloads.heavy_hitter(20_000, 500)
     rec = wl.generate()
     k, cols = oracle.groupby(rec, oracle_spec(wl))
@@ -147,7 +147,7 @@ def test_all_unique_and_single_key():
 
 
 def test_sorted_input_equals_unsorted():
-    """The paper's sorted-uniform set (Sec. 7.4) holds the same rows as its unsorted permutation."""
+    """The paper's sorted-uniform set (Sec. 6.4) holds the same rows as its unsorted permutation."""
     rec = datagen.r16(99, 50_000, 2_000)
     srt = rec[np.argsort(rec["key"], kind="stable")]
     a = oracle.groupby(rec, SPEC_R16)
