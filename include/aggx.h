@@ -185,6 +185,56 @@ const char *agg_strerror(agg_status s);
  * given): the working set below which AGG_E_BUDGET is returned. */
 uint64_t agg_min_budget(const agg_spec *spec);
 
+/* ---- Batched mode ---------------------------------------------------------
+ * Many independent GROUP BY instances with one record layout and aggregate
+ * list, run in one persistent launch captured in a hipGraph.  The paper
+ * motivates budgets per query by several operations running at once (Sec. 1,
+ * Sec. 3.2); here the instances share the device in one launch.  Instances
+ * with few groups are aggregated whole by one workgroup in LDS; larger ones
+ * are radix-partitioned and aggregated per partition in LDS.  Fan-out,
+ * records per partition and the one-workgroup threshold are chosen by a
+ * built-in autotuner (timed trial runs at agg_batch_create, cached per shape).
+ * Results are bit-identical to running each instance alone. */
+typedef struct agg_instance {
+  const void *d_records;  /* device pointer, packed records (alignment as for agg_consume); borrowed until
+                             agg_batch_destroy */
+  uint64_t n;             /* records */
+  uint64_t est_groups;    /* distinct keys expected (0 = unknown: n is assumed) */
+} agg_instance;
+
+typedef struct agg_batch agg_batch;
+
+typedef struct agg_batch_stats {
+  uint32_t instances;
+  uint32_t solo_instances;        /* aggregated whole by one workgroup */
+  uint32_t partitioned_instances;
+  uint32_t recomputed_instances;  /* LDS overflow, reserved key values or too many groups: run alone */
+  uint64_t items;                 /* work items of the persistent launch */
+  uint64_t partitions;            /* partitions over all partitioned instances */
+  uint64_t records;               /* total input records */
+  uint32_t tuned_candidate;       /* autotuner choice */
+  uint32_t blocks;                /* persistent workgroups */
+  double last_run_ms;             /* device time of the last graph launch (HIP events) */
+  double tune_ms[4];              /* trial-run times of the autotuner's candidates (0: not run) */
+} agg_batch_stats;
+
+/* Plan the batch (spec's record layout and aggregates; spec budget must be 0
+ * and est_groups/workspace unused), allocate its device buffers, autotune,
+ * and capture the launch in a hipGraph.  The instance array is copied; the
+ * record buffers are borrowed until agg_batch_destroy. */
+agg_status agg_batch_create(const agg_spec *spec, const agg_instance *inst, uint32_t n_inst, agg_batch **out);
+
+/* Launch the graph on the spec's stream and wait; instances flagged by the
+ * launch are recomputed alone.  Can be called again (same inputs re-read). */
+agg_status agg_batch_run(agg_batch *b);
+
+/* Rows of instance i of the last run (device memory owned by the batch). */
+agg_status agg_batch_result(const agg_batch *b, uint32_t i, agg_result *out);
+
+agg_status agg_batch_get_stats(const agg_batch *b, agg_batch_stats *out);
+
+void agg_batch_destroy(agg_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,7 @@ import torch  # noqa: F401  (must be loaded before the native library)
 
 from . import _native as N
 
-__all__ = ["AggError", "GroupBy", "make_spec", "load_library", "min_budget", "EXPORTS"]
+__all__ = ["AggError", "GroupBy", "Batch", "make_spec", "load_library", "min_budget", "EXPORTS"]
 
 EXPORTS = N.EXPORTS
 
@@ -145,6 +145,71 @@ class GroupBy:
         if self._h:
             self._lib.agg_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _copy_rows(res, na: int, device: str):
+    n = int(res.n_rows)
+    keys = torch.empty(n, dtype=torch.int64, device="cuda")
+    cols = torch.empty((na, n), dtype=torch.int64, device="cuda")
+    if n:
+        rt = _hip_rt()
+        torch.cuda.synchronize()
+        _check(rt.hipMemcpy(keys.data_ptr(), res.d_keys, n * 8, 3), "hipMemcpy")
+        for a in range(na):
+            _check(rt.hipMemcpy(cols[a].data_ptr(), res.d_cols[a], n * 8, 3), "hipMemcpy")
+    return keys.to(device), cols.to(device)
+
+
+class Batch:
+    """Many independent instances in one persistent launch (agg_batch_*)."""
+
+    def __init__(self, spec: N.Spec, instances):
+        """instances: iterable of (device pointer, n records, estimated groups or 0)."""
+        self._lib = load_library()
+        self._spec = spec
+        inst = list(instances)
+        arr = (N.Instance * max(len(inst), 1))()
+        for i, (ptr, n, est) in enumerate(inst):
+            arr[i].d_records = ptr
+            arr[i].n = n
+            arr[i].est_groups = est
+        self._n = len(inst)
+        self._b = ctypes.c_void_p()
+        _check(self._lib.agg_batch_create(ctypes.byref(spec), arr, len(inst), ctypes.byref(self._b)),
+               "agg_batch_create")
+
+    def run(self):
+        _check(self._lib.agg_batch_run(self._b), "agg_batch_run")
+
+    def result(self, i: int) -> N.Result:
+        res = N.Result()
+        _check(self._lib.agg_batch_result(self._b, i, ctypes.byref(res)), "agg_batch_result")
+        return res
+
+    def rows(self, i: int, device: str = "cpu"):
+        return _copy_rows(self.result(i), self._spec.n_aggs, device)
+
+    def stats(self) -> dict:
+        st = N.BatchStats()
+        _check(self._lib.agg_batch_get_stats(self._b, ctypes.byref(st)), "agg_batch_get_stats")
+        return st.as_dict()
+
+    def close(self):
+        if self._b:
+            self._lib.agg_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
 
     def __enter__(self):
         return self

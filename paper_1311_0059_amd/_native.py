@@ -82,9 +82,35 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("d_records", ctypes.c_void_p), ("n", ctypes.c_uint64), ("est_groups", ctypes.c_uint64)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [
+        ("instances", ctypes.c_uint32),
+        ("solo_instances", ctypes.c_uint32),
+        ("partitioned_instances", ctypes.c_uint32),
+        ("recomputed_instances", ctypes.c_uint32),
+        ("items", ctypes.c_uint64),
+        ("partitions", ctypes.c_uint64),
+        ("records", ctypes.c_uint64),
+        ("tuned_candidate", ctypes.c_uint32),
+        ("blocks", ctypes.c_uint32),
+        ("last_run_ms", ctypes.c_double),
+        ("tune_ms", ctypes.c_double * 4),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "tune_ms"}
+        d["tune_ms"] = list(self.tune_ms)
+        return d
+
+
 # every symbol include/aggx.h declares
 EXPORTS = ["agg_create", "agg_consume", "agg_finish", "agg_get_stats", "agg_destroy", "agg_strerror",
-           "agg_min_budget"]
+           "agg_min_budget", "agg_batch_create", "agg_batch_run", "agg_batch_result", "agg_batch_get_stats",
+           "agg_batch_destroy"]
 
 _lib = None
 
@@ -112,5 +138,16 @@ def load(path: str = LIB_PATH):
     lib.agg_strerror.restype = ctypes.c_char_p
     lib.agg_min_budget.argtypes = [ctypes.POINTER(Spec)]
     lib.agg_min_budget.restype = u64
+    lib.agg_batch_create.argtypes = [ctypes.POINTER(Spec), ctypes.POINTER(Instance), ctypes.c_uint32,
+                                     ctypes.POINTER(vp)]
+    lib.agg_batch_create.restype = ctypes.c_int
+    lib.agg_batch_run.argtypes = [vp]
+    lib.agg_batch_run.restype = ctypes.c_int
+    lib.agg_batch_result.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(Result)]
+    lib.agg_batch_result.restype = ctypes.c_int
+    lib.agg_batch_get_stats.argtypes = [vp, ctypes.POINTER(BatchStats)]
+    lib.agg_batch_get_stats.restype = ctypes.c_int
+    lib.agg_batch_destroy.argtypes = [vp]
+    lib.agg_batch_destroy.restype = None
     _lib = lib
     return lib

@@ -88,6 +88,44 @@ struct KSpill {
   uint32_t *hll;      // sketch of distinct keys in the spilled data
 };
 
+// ---- batched mode (one persistent launch over many instances) ----
+enum : uint32_t { IT_COUNT = 0, IT_SOLO = 1, IT_OFFS = 2, IT_SCATTER = 3, IT_AGG = 4 };
+
+struct BItem {
+  uint32_t type;  // IT_*
+  uint32_t inst;  // instance index
+  uint64_t lo, hi;  // record range (count, scatter) or partition index in lo (agg)
+};
+
+struct BInst {
+  const uint8_t *in;   // the instance's records
+  uint64_t n;
+  uint8_t *buf;        // partition buffer (partitioned instances)
+  uint32_t b;          // partition digit bits (0: solo)
+  uint32_t nchunks;    // count / scatter items of the instance
+  uint64_t pbase;      // first entry of the instance in the per-partition arrays
+  uint64_t out_base;   // first row of the instance in the output columns
+  uint64_t out_cap;    // rows reserved for it
+};
+
+struct BParams {
+  KSpec ks;
+  uint32_t nslots, cap;      // LDS table slots and group limit per workgroup
+  const BItem *items;
+  uint32_t n_items;
+  uint32_t n_inst;
+  const BInst *inst;
+  uint64_t n_parts;          // entries of totals / cursors (offsets has n_parts + n_inst)
+  uint32_t *head, *err;
+  uint32_t spin_limit;
+  uint32_t *cnt_done, *offs_done, *scat_done, *ovf;
+  unsigned long long *rows;
+  uint32_t *totals;
+  unsigned long long *cursors, *offsets;
+  uint64_t *out_keys;
+  OutCols out_cols;
+};
+
 }  // namespace aggx
 
 // Launch wrappers (defined in aggx_kernels.hip, called by the runtime).
@@ -131,5 +169,9 @@ hipError_t launch_merge_rows(hipStream_t s, const uint64_t *keys, const OutCols 
                              KSpill spill);
 // Largest dynamic LDS the LDS-aggregation kernel can be launched with (bytes).
 uint32_t lds_agg_max_bytes();
+// Batched mode.
+hipError_t batch_lds_setup(uint32_t lds_bytes);
+int batch_resident_blocks(uint32_t block, uint32_t lds_bytes);
+hipError_t launch_batch(hipStream_t s, const BParams &P, uint32_t blocks, uint32_t block, uint32_t lds_bytes);
 uint64_t hll_seed();
 }  // namespace aggx
