@@ -235,6 +235,62 @@ agg_status agg_batch_get_stats(const agg_batch *b, agg_batch_stats *out);
 
 void agg_batch_destroy(agg_batch *b);
 
+/* ---- Served mode -----------------------------------------------------------
+ * A request loop over one device memory pool.  The paper's platform gives each
+ * query a strict memory budget so that several run at once (Sec. 1, Sec. 3.2).
+ * Requests are admitted in arrival order when their budget fits the free part
+ * of the pool and one of max_inflight workers is free; each admitted request
+ * runs on its own stream with its workspace carved from the pool, so requests
+ * admitted while others run overlap on the device (continuous batching).  The
+ * pool range is returned as soon as the request's agg_finish completed.  Every
+ * request's rows equal those of running it alone. */
+typedef struct agg_server agg_server;
+
+typedef struct agg_server_config {
+  uint64_t pool_bytes;    /* device pool shared by the admitted requests' budgets (>= 1 MiB) */
+  uint32_t max_inflight;  /* requests running at once (worker threads and streams), 1..64 */
+  uint32_t reserved;      /* must be 0 */
+} agg_server_config;
+
+typedef struct agg_request_info {
+  agg_status status;
+  uint32_t reserved;
+  double queue_ms;        /* submit -> admitted */
+  double run_ms;          /* admitted -> finished */
+  double latency_ms;      /* submit -> finished */
+  uint64_t pool_offset;   /* where its workspace was carved */
+  agg_stats stats;        /* the request's own counters */
+} agg_request_info;
+
+typedef struct agg_server_stats {
+  uint32_t queued, running, peak_running, reserved;
+  uint64_t pool_bytes, pool_in_use, pool_peak;
+} agg_server_stats;
+
+/* Allocate the pool and start the workers (on the current device). */
+agg_status agg_server_create(const agg_server_config *cfg, agg_server **out);
+
+/* Queue a request; returns at once with a ticket.  spec->budget_bytes is the
+ * request's memory budget (required; it is carved from the pool), and
+ * spec->device_workspace and spec->stream must be NULL (the server sets them).
+ * d_records (device, n records) is borrowed until the request finished.
+ * Thread-safe.  AGG_E_BUDGET if the budget exceeds the pool. */
+agg_status agg_server_submit(agg_server *s, const agg_spec *spec, const void *d_records, uint64_t n,
+                             uint64_t *ticket);
+
+/* Block until the request finished; *out gets its rows (owned by the server
+ * until agg_server_release) and *info its timings.  Either may be NULL. */
+agg_status agg_server_wait(agg_server *s, uint64_t ticket, agg_result *out, agg_request_info *info);
+
+/* Free a finished request's rows (waits for it first). */
+agg_status agg_server_release(agg_server *s, uint64_t ticket);
+
+agg_status agg_server_get_stats(const agg_server *s, agg_server_stats *out);
+
+/* Stop the workers (queued requests that were not admitted are dropped) and
+ * free everything.  Call after waiting for the requests whose rows you need. */
+void agg_server_destroy(agg_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,7 @@ import torch  # noqa: F401  (must be loaded before the native library)
 
 from . import _native as N
 
-__all__ = ["AggError", "GroupBy", "Batch", "make_spec", "load_library", "min_budget", "EXPORTS"]
+__all__ = ["AggError", "GroupBy", "Batch", "Server", "make_spec", "load_library", "min_budget", "EXPORTS"]
 
 EXPORTS = N.EXPORTS
 
@@ -210,6 +210,65 @@ class Batch:
         if self._b:
             self._lib.agg_batch_destroy(self._b)
             self._b = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Served mode (agg_server_*): submit requests, the native loop admits them by budget."""
+
+    def __init__(self, pool_bytes: int, max_inflight: int = 8):
+        self._lib = load_library()
+        cfg = N.ServerConfig()
+        cfg.pool_bytes = pool_bytes
+        cfg.max_inflight = max_inflight
+        self._s = ctypes.c_void_p()
+        _check(self._lib.agg_server_create(ctypes.byref(cfg), ctypes.byref(self._s)), "agg_server_create")
+        self._na = {}
+
+    def submit(self, spec: N.Spec, ptr: int, n: int) -> int:
+        t = ctypes.c_uint64()
+        _check(self._lib.agg_server_submit(self._s, ctypes.byref(spec), ctypes.c_void_p(ptr), n, ctypes.byref(t)),
+               "agg_server_submit")
+        self._na[t.value] = spec.n_aggs
+        return t.value
+
+    def wait(self, ticket: int):
+        """(result, info dict) once the request finished."""
+        res, info = N.Result(), N.RequestInfo()
+        rc = self._lib.agg_server_wait(self._s, ticket, ctypes.byref(res), ctypes.byref(info))
+        _check(rc, "agg_server_wait")
+        d = {"queue_ms": info.queue_ms, "run_ms": info.run_ms, "latency_ms": info.latency_ms,
+             "pool_offset": info.pool_offset, "stats": info.stats.as_dict()}
+        return res, d
+
+    def rows(self, ticket: int, device: str = "cpu"):
+        res, _ = self.wait(ticket)
+        return _copy_rows(res, self._na[ticket], device)
+
+    def release(self, ticket: int):
+        _check(self._lib.agg_server_release(self._s, ticket), "agg_server_release")
+        self._na.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = N.ServerStats()
+        _check(self._lib.agg_server_get_stats(self._s, ctypes.byref(st)), "agg_server_get_stats")
+        return st.as_dict()
+
+    def close(self):
+        if self._s:
+            self._lib.agg_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
 
     def __enter__(self):
         return self

@@ -107,10 +107,30 @@ class BatchStats(ctypes.Structure):
         return d
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("reserved", ctypes.c_uint32), ("queue_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double), ("pool_offset", ctypes.c_uint64),
+                ("stats", Stats)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_uint32), ("running", ctypes.c_uint32), ("peak_running", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("pool_bytes", ctypes.c_uint64), ("pool_in_use", ctypes.c_uint64),
+                ("pool_peak", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 # every symbol include/aggx.h declares
 EXPORTS = ["agg_create", "agg_consume", "agg_finish", "agg_get_stats", "agg_destroy", "agg_strerror",
            "agg_min_budget", "agg_batch_create", "agg_batch_run", "agg_batch_result", "agg_batch_get_stats",
-           "agg_batch_destroy"]
+           "agg_batch_destroy", "agg_server_create", "agg_server_submit", "agg_server_wait",
+           "agg_server_release", "agg_server_get_stats", "agg_server_destroy"]
 
 _lib = None
 
@@ -149,5 +169,17 @@ def load(path: str = LIB_PATH):
     lib.agg_batch_get_stats.restype = ctypes.c_int
     lib.agg_batch_destroy.argtypes = [vp]
     lib.agg_batch_destroy.restype = None
+    lib.agg_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.agg_server_create.restype = ctypes.c_int
+    lib.agg_server_submit.argtypes = [vp, ctypes.POINTER(Spec), vp, u64, ctypes.POINTER(u64)]
+    lib.agg_server_submit.restype = ctypes.c_int
+    lib.agg_server_wait.argtypes = [vp, u64, ctypes.POINTER(Result), ctypes.POINTER(RequestInfo)]
+    lib.agg_server_wait.restype = ctypes.c_int
+    lib.agg_server_release.argtypes = [vp, u64]
+    lib.agg_server_release.restype = ctypes.c_int
+    lib.agg_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.agg_server_get_stats.restype = ctypes.c_int
+    lib.agg_server_destroy.argtypes = [vp]
+    lib.agg_server_destroy.restype = None
     _lib = lib
     return lib

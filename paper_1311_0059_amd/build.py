@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libaggx.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["aggx_kernels.hip", "aggx_lds.hip", "aggx_batch.hip", "aggx_runtime.cpp", "aggx_batch_rt.cpp"]
+SOURCES = ["aggx_kernels.hip", "aggx_lds.hip", "aggx_batch.hip", "aggx_runtime.cpp", "aggx_batch_rt.cpp", "aggx_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950", "-mcode-object-version=5",
          # no packed fp32 instructions anywhere (this library has no fp32 math)
@@ -38,7 +38,7 @@ def build(verbose: bool = False) -> str:
             print(msgs)
         objs.append(obj)
     tmp = OUT + ".tmp"
-    r = subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs],
+    r = subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-pthread", "-o", tmp, *objs],
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

@@ -20,6 +20,7 @@ def run_lib(records: np.ndarray, record_bytes: int, keys, aggs, batches: int = 1
     raw = np.ascontiguousarray(records).view(np.uint8).reshape(-1)
     n = raw.size // record_bytes
     dev = torch.from_numpy(raw.copy()).to("cuda") if raw.size else torch.empty(16, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()  # the library works on its own stream
     spec = P.make_spec(record_bytes, keys, aggs, **kw)
     with P.GroupBy(spec) as g:
         bounds = np.linspace(0, n, batches + 1).astype(np.int64)

@@ -28,6 +28,7 @@ def _upload(recs):
     for r, o in zip(recs, offs):
         host[o:o + r.size * 16] = r.view(np.uint8)
     dev = torch.from_numpy(host).to("cuda")
+    torch.cuda.synchronize()
     return dev, offs
 
 
