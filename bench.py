@@ -32,6 +32,7 @@ WORKLOADS = {
     "uniform-small": "uniform_small",
     "zipf-composite": "zipf_composite",
     "batched": "batched_mix",
+    "served": "served_mix",
 }
 
 
@@ -44,6 +45,11 @@ def parse():
     ap.add_argument("--policy", default="destage", choices=["destage", "prepart"])
     ap.add_argument("--cpu-sample", type=int, default=48_000_000,
                     help="records of the input the CPU oracle is timed on (0 = skip)")
+    ap.add_argument("--requests", type=int, default=400, help="served: requests in the trace")
+    ap.add_argument("--load", type=float, default=0.8, help="served: offered load vs the plain path's capacity")
+    ap.add_argument("--inflight", type=int, default=8, help="served: requests running at once")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy kernel (counter calibration for the traffic figure)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -68,8 +74,16 @@ def main():
     import paper_1311_0059_amd as P
     from datagen import workloads
 
+    if args.calibrate_copy:
+        return calibrate_copy(args)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "served":
+        # The served trace with all requests queued at once and eight in flight
+        # ended in a host heap-corruption abort whose cause is not yet found; the
+        # workload stays disabled until it is (the served-mode GPU tests still run).
+        sys.exit("bench.py: the served workload is disabled: its concurrent warm-up aborted with a host "
+                 "heap corruption that is still being diagnosed")
     wl = getattr(workloads, WORKLOADS[args.workload])()
     log(args, f"[bench] generating {wl.name}: {wl.n} records x {wl.record_bytes} B, {wl.d} keys")
     t = time.perf_counter()
@@ -115,16 +129,21 @@ def main():
     # dominant kernel: the level-0 aggregation/routing kernel; its algorithmic bytes are the
     # records it reads plus the grouping states it leaves in the resident tables
     if agg["update_launches_l0"]:
-        kname = "aggx::k_update (level 0)"
+        kname = f"k_update<0, {1 if agg['preagg'] else 0}>"
         l0_bytes = agg["update_records_l0"] * wl.record_bytes + agg["resident_groups_l0"] * W8
         l0_ms = agg["update_ms_l0"]
         launches = max(1, agg["update_launches_l0"])
     else:  # the partition-first LDS engine ran: its aggregation kernel reads the partitioned batch
-        kname = "aggx::k_lds_agg"
+        kname = "k_lds_agg"
         l0_bytes = wl.n * args.steps * wl.record_bytes + agg["resident_groups_l0"] * W8
         l0_ms = agg["lds_ms"]
         launches = max(1, agg["lds_launches"])
     achieved = (l0_bytes / launches) / (l0_ms / launches * 1e-3) / 1e9 if l0_ms > 0 else 0.0
+    # HBM traffic per launch from the committed rocprofv3 counter summary of this kernel and
+    # workload, used only while the kernel sources are the ones it was measured on
+    from paper_1311_0059_amd import profiling
+    tsum = os.path.join(ROOT, "profiles", f"{kname.split('<')[0]}_{wl.name}_traffic.md")
+    traffic = profiling.read_traffic(tsum, kname)
     roofline = {
         "bound": "hbm",
         "kernel": kname,
@@ -132,7 +151,7 @@ def main():
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBPS, 4),
-        "traffic": None,
+        "traffic": None if traffic is None else int(traffic),
         "avg_launch_ms": round(l0_ms / launches, 4),
         "launches_per_step": launches / args.steps,
         "bytes_per_launch": int(l0_bytes / launches),
@@ -199,6 +218,23 @@ def main():
     }
     if rank == 0:
         print(json.dumps(out), flush=True)
+
+
+def calibrate_copy(args):
+    """A plain streaming kernel of known traffic: 1 GiB read and 1 GiB written per launch
+    (bitwise NOT of int64), three launches.  Its FETCH_SIZE / WRITE_SIZE readings give the
+    factors that turn those counters into bytes."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.arange(n, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.bitwise_not(a, out=b)
+    torch.cuda.synchronize()
+    ok = bool((b[:1024] == ~a[:1024]).all().item())
+    print(json.dumps({"calibration": "bitwise_not int64", "bytes_read": n * 8, "bytes_written": n * 8,
+                      "launches": 3, "ok": ok}), flush=True)
 
 
 def bench_batched(args):
@@ -269,6 +305,109 @@ def bench_batched(args):
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
                      "avg_launch_ms": round(kernel_ms, 4), "bytes_per_launch": int(alg)},
         "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args):
+    """Poisson stream of requests (sizes log-uniform 1e4-5e7, distinct 1-50%, Zipf s in [0, 1.2],
+    budgets log-uniform 16 MiB-2 GiB) against a 64 GiB pool.  The same trace runs (1) on the
+    plain path -- one query at a time, FIFO, back to back, to measure its capacity -- then
+    with Poisson arrivals at `--load` x that capacity (2) on the plain path (one request
+    admitted at a time) and (3) served (memory admission, `--inflight` concurrent requests).
+    Latency = finish - arrival; records/s = total records / (last finish - first arrival)."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_1311_0059_amd as P
+    from datagen import workloads
+
+    reqs = workloads.served_mix(args.requests)
+    rb = 16
+    offs, total = [], 0
+    for w in reqs:
+        offs.append(total)
+        total += (w.n * rb + 255) // 256 * 256
+    n_total = sum(w.n for w in reqs)
+    log(args, f"[bench] generating {len(reqs)} requests: {n_total} records, {total / 1e9:.1f} GB")
+    dev = torch.empty(total, dtype=torch.uint8, device="cuda")
+    host = np.empty(max(w.n for w in reqs) * rb, dtype=np.uint8)
+    for w, o in zip(reqs, offs):  # one request at a time through one host buffer
+        w.generate(out=host[:w.n * rb].view(workloads.R16))
+        dev[o:o + w.n * rb].copy_(torch.from_numpy(host[:w.n * rb]))
+        torch.cuda.synchronize()
+    del host
+    log(args, "[bench] uploaded")
+    specs = [P.make_spec(rb, [(0, "u64")], w.aggs, budget=w.budget, est_groups=w.d) for w in reqs]
+    pool = 64 << 30
+
+    def run_trace(inflight, arrivals):
+        """Submit request i at arrivals[i] (seconds from start); return per-request latency (ms), makespan (s)."""
+        with P.Server(pool_bytes=pool, max_inflight=inflight) as srv:
+            t0 = time.perf_counter()
+            tickets = [None] * len(reqs)
+            sub_t = [0.0] * len(reqs)
+
+            def submitter():
+                for i, w in enumerate(reqs):
+                    dt = arrivals[i] - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                    sub_t[i] = time.perf_counter() - t0
+                    tickets[i] = srv.submit(specs[i], dev.data_ptr() + offs[i], w.n)
+
+            th = threading.Thread(target=submitter)
+            th.start()
+            th.join()
+            lat, rows_ok, runs = [], True, []
+            for i, w in enumerate(reqs):
+                res, info = srv.wait(tickets[i])
+                lat.append(info["latency_ms"])
+                runs.append(info["run_ms"])
+                rows_ok &= int(res.n_rows) == w.d
+            makespan = time.perf_counter() - t0
+            st = srv.stats()
+            for t in tickets:
+                srv.release(t)
+        return np.array(lat), makespan, rows_ok, st, np.array(runs)
+
+    zeros = [0.0] * len(reqs)
+    log(args, f"[bench] warm-up: all requests at t=0, {args.inflight} in flight")
+    run_trace(args.inflight, zeros)  # warm-up (caches, code, pinned segments)
+    log(args, "[bench] plain path, back to back")
+    _, plain_busy, ok0, _, service = run_trace(1, zeros)
+    log(args, "[bench] served, back to back")
+    _, served_busy, ok3, _, _ = run_trace(args.inflight, zeros)
+    cap_rps = len(reqs) / plain_busy
+    gaps = np.array([w.extra["gap"] for w in reqs]) / (args.load * cap_rps)
+    arrivals = list(np.cumsum(gaps) - gaps[0])
+    log(args, f"[bench] plain capacity {cap_rps:.1f} req/s ({plain_busy:.2f}s back to back); load {args.load}")
+    log(args, "[bench] plain path, Poisson arrivals")
+    lat_p, span_p, ok1, _, _ = run_trace(1, arrivals)
+    log(args, "[bench] served, Poisson arrivals")
+    lat_s, span_s, ok2, st_s, _ = run_trace(args.inflight, arrivals)
+    pct = lambda a, q: float(np.percentile(a, q))
+    out = {
+        "metric": METRIC, "value": round(n_total / span_s, 1), "unit": "records/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": round(1000 * span_s, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"served-{len(reqs)}-requests", "records": n_total, "pool_bytes": pool,
+                   "inflight": args.inflight, "offered_load": args.load,
+                   "arrivals": "Poisson at offered_load x plain-path capacity"},
+        "served": {"p50_ms": round(pct(lat_s, 50), 3), "p99_ms": round(pct(lat_s, 99), 3),
+                   "records_per_s": round(n_total / span_s, 1), "makespan_s": round(span_s, 3),
+                   "peak_running": st_s["peak_running"], "pool_peak_bytes": st_s["pool_peak"]},
+        "plain": {"p50_ms": round(pct(lat_p, 50), 3), "p99_ms": round(pct(lat_p, 99), 3),
+                  "records_per_s": round(n_total / span_p, 1), "makespan_s": round(span_p, 3),
+                  "back_to_back_s": round(plain_busy, 3),
+                  "service_p50_ms": round(pct(service, 50), 3), "service_p99_ms": round(pct(service, 99), 3)},
+        "capacity": {"plain_records_per_s": round(n_total / plain_busy, 1),
+                     "served_records_per_s": round(n_total / served_busy, 1),
+                     "note": "all requests queued at t=0"},
+        "rows_ok": bool(ok0 and ok1 and ok2 and ok3),
+        "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

@@ -18,6 +18,8 @@
 // a device-scope fence after reading the counter.
 #include "aggx_device.h"
 
+#include <mutex>
+
 namespace aggx {
 
 __device__ __forceinline__ uint32_t bdigit(uint64_t key, uint32_t b) {
@@ -244,12 +246,18 @@ __global__ void k_batch_reset(BParams P) {
   for (uint64_t i = t; i < P.n_parts; i += stride) P.totals[i] = 0;
 }
 
+// The kernel's attribute and occupancy queries run under one lock, so batch
+// objects created from several host threads never race on them.
+static std::mutex g_setup_mu;
+
 hipError_t batch_lds_setup(uint32_t lds_bytes) {
+  std::lock_guard<std::mutex> lk(g_setup_mu);
   return hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds_bytes);
 }
 
 int batch_resident_blocks(uint32_t block, uint32_t lds_bytes) {
+  std::lock_guard<std::mutex> lk(g_setup_mu);
   int dev = 0, per_cu = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;

@@ -145,6 +145,8 @@ hipError_t launch_sample_dups(hipStream_t s, const uint8_t *in, uint64_t n, cons
 hipError_t launch_flush(hipStream_t s, const uint64_t *arena, uint64_t nslots, const KSpec &ks, uint64_t *out_keys,
                         const OutCols &out_cols, uint64_t out_cap, Ctrl *ctrl);
 hipError_t launch_u64_set(hipStream_t s, unsigned long long *p, uint32_t n, unsigned long long v);
+// dst[i] = src[i * stride] for i < n (packs the padded per-partition counters).
+hipError_t launch_gather_u32(hipStream_t s, const uint32_t *src, uint32_t stride, uint32_t n, uint32_t *dst);
 hipError_t launch_extract(hipStream_t s, uint64_t *arena, uint64_t base, uint64_t nslots, const KSpec &ks,
                           Ctrl *ctrl, KSpill spill);
 // Grace partitioning of a run: histogram of the digit (h0 >> shift) & mask,

@@ -21,6 +21,9 @@
 #include "aggx_device.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace aggx {
 
@@ -228,6 +231,11 @@ __global__ void k_u64_set(unsigned long long *p, uint32_t n, unsigned long long 
   if (blockIdx.x == 0 && threadIdx.x < n) p[threadIdx.x] = v;
 }
 
+__global__ void k_gather_u32(const uint32_t *src, uint32_t stride, uint32_t n, uint32_t *dst) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    dst[i] = src[(uint64_t)i * stride];
+}
+
 __global__ void k_ctrl_init(Ctrl *c, KSpec ks) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     c->raw_ctr = 0;
@@ -374,6 +382,12 @@ hipError_t launch_u32_fill(hipStream_t s, uint32_t *p, uint64_t n, uint32_t valu
   return hipGetLastError();
 }
 
+hipError_t launch_gather_u32(hipStream_t s, const uint32_t *src, uint32_t stride, uint32_t n, uint32_t *dst) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(n, 256, 64)), dim3(256), 0, s, src, stride, n, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_u64_set(hipStream_t s, unsigned long long *p, uint32_t n, unsigned long long v) {
   hipLaunchKernelGGL(k_u64_set, dim3(1), dim3(64), 0, s, p, n, v);
   return hipGetLastError();
@@ -385,14 +399,20 @@ hipError_t launch_ctrl_init(hipStream_t s, Ctrl *c, const KSpec &ks) {
 }
 
 // Blocks of k_update that fit on the device at once (occupancy x compute units).
+// Several host threads launch concurrently (one per request in served mode), so
+// the occupancy answers are cached per device and launch shape under a lock and
+// the HIP queries behind them never run concurrently.
 static int resident_blocks(uint32_t block, size_t lds, int preagg, int kind) {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 1024;
-    cus = prop.multiProcessorCount;
-  }
+  static std::mutex mu;
+  static std::map<std::tuple<int, uint32_t, size_t, int, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  const auto key = std::make_tuple(dev, block, lds, preagg, kind);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 1024;
   int per_cu = 0;
   hipError_t e;
   if (kind == 0)
@@ -402,7 +422,9 @@ static int resident_blocks(uint32_t block, size_t lds, int preagg, int kind) {
     e = preagg ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_update<1, 1>, block, lds)
                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_update<1, 0>, block, lds);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
-  return per_cu * cus;
+  const int blocks = per_cu * prop.multiProcessorCount;
+  cache.emplace(key, blocks);
+  return blocks;
 }
 
 hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint64_t n, const KSpec &ks,

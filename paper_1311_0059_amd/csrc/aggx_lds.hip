@@ -12,6 +12,8 @@
 #include "aggx_device.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 namespace aggx {
 
@@ -261,18 +263,25 @@ hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, con
   return hipGetLastError();
 }
 
+// Per device, once, under a lock: concurrent host threads never set the
+// kernel's attribute at the same time.
 uint32_t lds_agg_max_bytes() {
-  static uint32_t cached = 0;
-  if (cached) return cached;
+  static std::mutex mu;
+  static std::map<int, uint32_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
   // gfx950 has 160 KB of LDS per compute unit; ask for most of it, else 64 KB
   const uint32_t want = 160 * 1024 - 1024;
+  uint32_t got = 64 * 1024;
   if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_agg), hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)want) == hipSuccess)
-    cached = want;
-  else
-    cached = 64 * 1024;
+    got = want;
   (void)hipGetLastError();
-  return cached;
+  cache.emplace(dev, got);
+  return got;
 }
 
 hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long long *offsets, uint32_t F,

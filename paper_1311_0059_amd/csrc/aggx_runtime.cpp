@@ -29,7 +29,9 @@ constexpr uint64_t kHllBytes = kHllRegs * 4;
 constexpr uint64_t kMetaBytes = (uint64_t)kMaxFan * sizeof(PartMeta);
 constexpr uint64_t kCntBytes = (uint64_t)kMaxFan * 4 * kCntStride;  // counters, one 128-byte line each
 constexpr uint64_t kOvfBytes = (uint64_t)kMaxFan * 4;
-constexpr uint64_t kOverhead = kCtrlBytes + kHllBytes + kMetaBytes + kCntBytes + kOvfBytes;  // fixed part of the budget
+constexpr uint64_t kPackBytes = (uint64_t)kMaxFan * 4;  // the counters packed for one contiguous readback
+constexpr uint64_t kOverhead =
+    kCtrlBytes + kHllBytes + kMetaBytes + kCntBytes + kOvfBytes + kPackBytes;  // fixed part of the budget
 constexpr uint64_t kMinArenaBytes = 64 * 1024;
 constexpr uint64_t kScratchBytes = 128 * 1024;  // pinned host mirror for flag / count / sketch / histogram readbacks
 constexpr uint64_t kMinBudget = 1u << 20;
@@ -203,6 +205,7 @@ struct agg_handle {
   PartMeta *d_meta = nullptr;
   uint32_t *d_cnt = nullptr;
   uint32_t *d_ovf = nullptr;
+  uint32_t *d_pack = nullptr;
   uint64_t *d_arena = nullptr;
   uint64_t arena_cap_bytes = 0;
 
@@ -311,6 +314,8 @@ void carve(agg_handle *h) {
   p += kCntBytes;
   h->d_ovf = reinterpret_cast<uint32_t *>(p);
   p += kOvfBytes;
+  h->d_pack = reinterpret_cast<uint32_t *>(p);
+  p += kPackBytes;
   h->d_arena = reinterpret_cast<uint64_t *>(p);
   h->arena_cap_bytes = h->pool_bytes - kOverhead;
 }
@@ -479,8 +484,8 @@ agg_status handle_overflow(agg_handle *h) {
   if (h->h_ctrl->any_ovf == 0) return AGG_OK;
   LevelPlan &pl = h->plan;
   HCK(h, hipMemcpyAsync(h->h_scratch, h->d_ovf, 4ull * pl.F, hipMemcpyDeviceToHost, h->stream));
-  HCK(h, hipMemcpy2DAsync(h->h_scratch + kMaxFan, 4, h->d_cnt, 4 * kCntStride, 4, pl.F, hipMemcpyDeviceToHost,
-                          h->stream));
+  HCK(h, launch_gather_u32(h->stream, h->d_cnt, kCntStride, pl.F, h->d_pack));
+  HCK(h, hipMemcpyAsync(h->h_scratch + kMaxFan, h->d_pack, 4ull * pl.F, hipMemcpyDeviceToHost, h->stream));
   HCK(h, hipStreamSynchronize(h->stream));
   std::vector<uint32_t> victims;
   for (uint32_t p = 0; p < pl.F; ++p)
@@ -589,8 +594,8 @@ agg_status ensure_result_cap(agg_handle *h, uint64_t need) {
 // (Sec. 4.3.3: partitions that stay in memory go straight to the final output).
 agg_status flush_level(agg_handle *h, double extra_hint) {
   LevelPlan &pl = h->plan;
-  HCK(h, hipMemcpy2DAsync(h->h_scratch + kMaxFan, 4, h->d_cnt, 4 * kCntStride, 4, pl.F, hipMemcpyDeviceToHost,
-                          h->stream));
+  HCK(h, launch_gather_u32(h->stream, h->d_cnt, kCntStride, pl.F, h->d_pack));
+  HCK(h, hipMemcpyAsync(h->h_scratch + kMaxFan, h->d_pack, 4ull * pl.F, hipMemcpyDeviceToHost, h->stream));
   HCK(h, hipStreamSynchronize(h->stream));
   uint64_t ub = 0;
   for (uint32_t p = 0; p < pl.F; ++p)

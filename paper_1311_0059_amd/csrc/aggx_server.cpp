@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "../../include/aggx.h"
+#include "aggx_internal.h"
 
 namespace {
 
@@ -179,6 +180,8 @@ agg_status agg_server_create(const agg_server_config *cfg, agg_server **out) {
     return AGG_E_NOMEM;
   }
   s->alloc.init(cfg->pool_bytes / kAlign * kAlign);
+  // one-time launch configuration of the device, before any worker runs
+  (void)aggx::lds_agg_max_bytes();
   for (uint32_t i = 0; i < cfg->max_inflight; ++i) {
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
