@@ -129,7 +129,7 @@ def main():
     # dominant kernel: the level-0 aggregation/routing kernel; its algorithmic bytes are the
     # records it reads plus the grouping states it leaves in the resident tables
     if agg["update_launches_l0"]:
-        kname = f"k_update<0, {1 if agg['preagg'] else 0}>"
+        kname = "k_owner_update" if agg["engine"] // args.steps == 3 else f"k_update<0, {1 if agg['preagg'] else 0}>"
         l0_bytes = agg["update_records_l0"] * wl.record_bytes + agg["resident_groups_l0"] * W8
         l0_ms = agg["update_ms_l0"]
         launches = max(1, agg["update_launches_l0"])
@@ -209,6 +209,7 @@ def main():
             "update_ms_l0": round(agg["update_ms_l0"] / args.steps, 3),
             "flush_ms": round(agg["flush_ms"] / args.steps, 3),
             "lds_ms": round(agg["lds_ms"] / args.steps, 3),
+            "partition_ms": round(agg["partition_ms"] / args.steps, 3),
             "engine": agg["engine"] // args.steps,
             "preagg": agg["preagg"] // args.steps,
             "pool_high_water": agg["pool_high_water"] // args.steps,

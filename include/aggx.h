@@ -74,12 +74,16 @@ typedef enum agg_policy {
                               key is resident are aggregated, the others are spilled raw */
 } agg_policy;
 
-/* Aggregation engines (both compute the same rows). */
+/* Aggregation engines (all compute the same rows). */
 typedef enum agg_engine {
-  AGG_ENGINE_AUTO = 0,    /* LDS engine when it applies, else HBM tables */
+  AGG_ENGINE_AUTO = 0,    /* LDS engine when it applies; else owner-computed HBM tables for large batches
+                             without a dominant key; else HBM tables with atomics */
   AGG_ENGINE_TABLES = 1,  /* per-partition open-addressing tables in HBM, 64-bit atomics, chunked input */
-  AGG_ENGINE_LDS = 2      /* radix-partition the batch, then one workgroup aggregates each partition in an
+  AGG_ENGINE_LDS = 2,     /* radix-partition the batch, then one workgroup aggregates each partition in an
                              LDS table; needs the budget to hold the partitioned batch (else falls back) */
+  AGG_ENGINE_OWNER = 3    /* the same HBM tables, updated without atomics: sub-chunks of the batch are
+                             radix-partitioned into a buffer carved from the budget, and one workgroup owns
+                             each partition's table while it folds that partition's records in */
 } agg_engine;
 
 #define AGG_MAX_AGGS 8
@@ -136,7 +140,7 @@ typedef struct agg_stats {
   uint32_t partitions_spilled;  /* level-0 partitions spilled (planned or overflowed) */
   uint32_t guard_trips;         /* levels whose spilled output kept more than 80% of their input */
   uint32_t preagg;              /* 1 if the workgroup hot-key cache was used (skew seen in a sample) */
-  uint32_t engine;              /* engine used for the first batch: 1 HBM tables, 2 LDS */
+  uint32_t engine;              /* engine used for the first batch: 1 HBM tables, 2 LDS, 3 owner-computed */
   uint64_t pool_high_water;     /* peak bytes of the working budget in use */
   uint64_t pool_bytes;          /* size of the working budget actually reserved */
   /* Device time of the two main kernels, measured with HIP events recorded on
@@ -151,6 +155,9 @@ typedef struct agg_stats {
   double flush_ms;
   uint64_t lds_launches;        /* launches of the LDS-engine aggregation kernel */
   double lds_ms;
+  double partition_ms;          /* owner-computed engine: its partition pipeline (count, offsets,
+                                   scatter, owner update) per chunk; the owner-update kernel alone
+                                   is counted in the update_* figures */
 } agg_stats;
 
 /* Validate and copy `spec`, reserve the working budget (or adopt the caller's

@@ -76,6 +76,7 @@ class Stats(ctypes.Structure):
         ("flush_ms", ctypes.c_double),
         ("lds_launches", ctypes.c_uint64),
         ("lds_ms", ctypes.c_double),
+        ("partition_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

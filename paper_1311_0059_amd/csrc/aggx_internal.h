@@ -169,6 +169,13 @@ hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long
 hipError_t launch_merge_rows(hipStream_t s, const uint64_t *keys, const OutCols &cols, uint64_t n, const KSpec &ks,
                              const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint64_t *arena, Ctrl *ctrl,
                              KSpill spill);
+// Owner-computed table update: one workgroup per partition of the partitioned
+// sub-chunk `buf` (ranges from `offsets`), no atomics on the aggregates.
+hipError_t launch_owner_update(hipStream_t s, const uint8_t *buf, const unsigned long long *offsets, uint32_t F,
+                               const KSpec &ks, const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint32_t *ovf,
+                               uint64_t *arena, Ctrl *ctrl, KSpill spill);
+// Dynamic LDS bytes of the owner-update kernel for this record layout.
+uint32_t owner_lds_bytes(const KSpec &ks, uint32_t *stage_cap);
 // Largest dynamic LDS the LDS-aggregation kernel can be launched with (bytes).
 uint32_t lds_agg_max_bytes();
 // Batched mode.

@@ -40,6 +40,10 @@ constexpr uint64_t kPinnedSegment = 256ull << 20;   // pinned spill memory is ta
 constexpr double kDefaultLoad = 0.70;               // planned table load
 constexpr double kMaxLoad = 0.90;                   // groups a table may take before it is full
 constexpr uint64_t kGroupsPerPartition = 16384;     // automatic fan-out target
+constexpr double kPlanMaxLoad = 0.88;               // highest load the plan accepts to keep every partition resident
+constexpr uint64_t kOwnerBufMax = 64ull << 20;      // owner engine: partition buffer per sub-chunk (bytes)
+constexpr uint64_t kOwnerBufMin = 1ull << 20;
+constexpr uint32_t kOwnerMaxSub = 16;               // sub-chunks per host synchronisation
 
 uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -226,7 +230,12 @@ struct agg_handle {
   uint64_t r_block_bytes = 0;
 
   int preagg = -1;  // hot-key cache in the update kernel: -1 undecided, 0 off, 1 on
-  int engine = 0;   // 0 undecided, 1 HBM tables, 2 partition-first with LDS tables
+  int engine = 0;   // 0 undecided, 1 HBM tables, 2 partition-first with LDS tables, 3 owner-computed tables
+  // owner engine: bytes at the top of the arena for the partition buffer and its
+  // counters (level 0 only), records per sub-chunk, and timing events
+  uint64_t owner_reserve = 0;
+  uint64_t owner_m = 0;
+  hipEvent_t ev_own[2 * kOwnerMaxSub] = {};
   int hot_key = 0;  // the sample showed one key with a large share of the records
   int state = H_OPEN;
   agg_stats st{};
@@ -277,7 +286,7 @@ agg_status validate(const agg_spec *s) {
   if (wide && s->record_bytes % 8) return AGG_E_INVALID;
   if (s->fanout_bits > (uint32_t)kMaxFanBits) return AGG_E_INVALID;
   if (s->load_pct != 0 && (s->load_pct < 10 || s->load_pct > 95)) return AGG_E_INVALID;
-  if (s->policy > AGG_POLICY_PREPART || s->preagg > 2 || s->engine > AGG_ENGINE_LDS) return AGG_E_INVALID;
+  if (s->policy > AGG_POLICY_PREPART || s->preagg > 2 || s->engine > AGG_ENGINE_OWNER) return AGG_E_INVALID;
   if (s->device_workspace && (s->workspace_bytes < s->budget_bytes || ((uintptr_t)s->device_workspace & 255)))
     return AGG_E_BUDGET;
   if (s->device_workspace && s->budget_bytes == 0) return AGG_E_INVALID;
@@ -367,6 +376,9 @@ agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_
   const double lam = h->spec.load_pct ? h->spec.load_pct / 100.0 : kDefaultLoad;
   const uint64_t W8 = h->W8;
   const uint32_t bits_left = 64 - consumed_bits;
+  // table bytes: the arena minus, at level 0 of the owner engine, its buffer area
+  const uint64_t reserve = level == 0 ? h->owner_reserve : 0;
+  uint64_t cap_bytes = h->arena_cap_bytes > reserve ? (h->arena_cap_bytes - reserve) / 256 * 256 : 0;
   uint32_t b;
   if (h->spec.fanout_bits) {
     b = h->spec.fanout_bits;
@@ -375,8 +387,10 @@ agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_
     if (!h->unlimited) {
       // at least one partition's table must fit the arena
       const double need = G * W8 / lam;
-      while (b < (uint32_t)kMaxFanBits && need / (double)(1u << b) > 0.9 * (double)h->arena_cap_bytes) ++b;
+      while (b < (uint32_t)kMaxFanBits && need / (double)(1u << b) > 0.9 * (double)cap_bytes) ++b;
     }
+    // the owner engine runs one workgroup per partition: enough of them to fill the device
+    if (level == 0 && h->owner_reserve) b = std::max<uint32_t>(b, 8);
     b = std::min<uint32_t>(b, kMaxFanBits);
   }
   b = std::min(b, bits_left);
@@ -392,10 +406,10 @@ agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_
   uint64_t slots = slots_need;
   if (h->unlimited) {
     const uint64_t need = (uint64_t)pl.F * slots * W8;
-    if (need > h->arena_cap_bytes) {
+    if (need + reserve > h->arena_cap_bytes) {
       // grow the library-owned pool (unlimited budget); the control block and
       // the sketch carry over (the side group accumulates across levels)
-      const uint64_t bytes = round_up(kOverhead + round_up(need, 1 << 20), 2 << 20);
+      const uint64_t bytes = round_up(kOverhead + round_up(round_up(need, 256) + reserve, 1 << 20), 2 << 20);
       uint8_t *np = nullptr;
       if (!dev_get(bytes, (void **)&np)) return AGG_E_NOMEM;
       HCK(h, hipMemcpyAsync(np, h->pool, kCtrlBytes + kHllBytes, hipMemcpyDeviceToDevice, h->stream));
@@ -408,15 +422,23 @@ agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_
     }
   } else {
     const uint64_t per = slots * W8;
-    T = std::min<uint64_t>(pl.F, h->arena_cap_bytes / per);
+    T = std::min<uint64_t>(pl.F, cap_bytes / per);
+    // Every partition still fits at a load of up to kPlanMaxLoad: keep them all
+    // resident rather than spilling some from the start (a spilled record costs
+    // a host round trip; a fuller table only lengthens probes).  An explicit
+    // load factor in the spec is taken as given.
+    if (T < pl.F && !h->spec.load_pct) {
+      const uint64_t tight = (uint64_t)std::ceil(cap_need / kPlanMaxLoad) + 1;
+      if ((uint64_t)pl.F * tight * W8 <= cap_bytes) T = pl.F;
+    }
     if (T == 0) {
       T = 1;
-      slots = std::max<uint64_t>(8, h->arena_cap_bytes / W8);
+      slots = std::max<uint64_t>(8, cap_bytes / W8);
     } else if (T == pl.F) {
-      // spread the spare budget over all tables, down to a load of one half
-      const uint64_t spread = h->arena_cap_bytes / ((uint64_t)pl.F * W8);
+      // spread the budget over all tables, down to a load of one half
+      const uint64_t spread = cap_bytes / ((uint64_t)pl.F * W8);
       const uint64_t half = (uint64_t)std::ceil(cap_need / 0.5) + 1;
-      slots = std::max(slots, std::min(spread, half));
+      slots = std::min(spread, std::max(slots, half));
     }
   }
   if (slots > 0xffffffffULL) slots = 0xffffffffULL;
@@ -734,6 +756,94 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   h->r_rows += h->h_ctrl->rows;
   h->st.partitions = lp.F;
   h->used_bits = std::max(h->used_bits, lp.b);
+  return AGG_OK;
+}
+
+// ---- owner-computed HBM tables ---------------------------------------------
+// Reserve the top of the arena for the partition buffer of one sub-chunk and
+// the partition counters, cursors and offsets (sized for the largest fan-out).
+// Returns false when the budget is too small to give the buffer a useful size.
+bool owner_setup(agg_handle *h) {
+  uint32_t stage_cap = 0;
+  if (owner_lds_bytes(h->ks, &stage_cap) > 64 * 1024) return false;
+  const uint64_t aux = round_up(2ull * kMaxFan * 128 + 8ull * (kMaxFan + 1), 256);
+  uint64_t buf = h->unlimited ? kOwnerBufMax : std::min(kOwnerBufMax, h->arena_cap_bytes / 16);
+  buf = buf / (256ull * h->ks.rb) * (256ull * h->ks.rb);  // whole records, 256-byte aligned
+  if (buf < kOwnerBufMin) return false;
+  if (h->owner_reserve == 0) {
+    for (uint32_t i = 0; i < 2 * kOwnerMaxSub; ++i)
+      if (hipEventCreate(&h->ev_own[i]) != hipSuccess) return false;
+  }
+  h->owner_reserve = buf + aux;
+  h->owner_m = buf / h->ks.rb;
+  return true;
+}
+
+// Level 0 of the owner engine: per chunk of up to kOwnerMaxSub sub-chunks,
+// each sub-chunk is radix-partitioned into the buffer (count, offsets,
+// scatter) and folded into the tables by k_owner_update; the host syncs once
+// per chunk to collect the spill count and apply the spill policy.
+agg_status run_owner_stream(agg_handle *h, const uint8_t *in, uint64_t n) {
+  const LevelPlan &pl = h->plan;
+  const uint64_t rb = h->ks.rb, m = h->owner_m;
+  const uint64_t area_off = (h->arena_cap_bytes - h->owner_reserve) / 256 * 256;
+  uint8_t *area = reinterpret_cast<uint8_t *>(h->d_arena) + area_off;
+  if ((uint64_t)pl.arena_slots * h->W8 > area_off) return AGG_E_INTERNAL;  // tables must stay below the area
+  uint8_t *buf = area;
+  uint32_t *totals = reinterpret_cast<uint32_t *>(area + m * rb);
+  unsigned long long *cursors = reinterpret_cast<unsigned long long *>(area + m * rb + 128ull * kMaxFan);
+  unsigned long long *offsets = cursors + (uint64_t)kMaxFan * (kCntStride / 2);
+  const uint32_t shift = pl.fan_bits ? pl.digit_shift : 0, mask = pl.F - 1;
+  KLevel lv;
+  lv.level = 0;
+  lv.digit_shift = pl.digit_shift;
+  lv.fan_mask = pl.F - 1;
+  lv.slot_shift = pl.fan_bits;
+  lv.seed_slot = pl.seed_slot;
+  const uint64_t group = m * kOwnerMaxSub;
+  for (uint64_t off = 0; off < n; off += group) {
+    const uint64_t g = std::min(group, n - off);
+    uint8_t *dst = nullptr;
+    if (!h->next.reserve(g * rb, &dst)) return AGG_E_NOMEM;
+    HCK(h, launch_u64_set(h->stream, &h->d_ctrl->raw_ctr, 1, 0));
+    const KSpill sp = spill_target(h, dst, nullptr);
+    HCK(h, hipEventRecord(h->ev0, h->stream));
+    uint32_t subs = 0;
+    for (uint64_t so = 0; so < g; so += m, ++subs) {
+      const uint64_t c = std::min(m, g - so);
+      const uint8_t *src = in + (off + so) * rb;
+      const uint64_t chunk = std::max<uint64_t>(1024, std::min<uint64_t>(4096, c / 256 + 1));
+      HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)pl.F * kCntStride, 0));
+      HCK(h, launch_part_count(h->stream, src, c, h->ks, shift, mask, chunk, totals));
+      HCK(h, launch_part_offsets(h->stream, totals, pl.F, offsets, cursors));
+      HCK(h, launch_part_scatter(h->stream, src, c, h->ks, shift, mask, chunk, cursors, buf));
+      HCK(h, hipEventRecord(h->ev_own[2 * subs], h->stream));
+      HCK(h, launch_owner_update(h->stream, buf, offsets, pl.F, h->ks, lv, h->d_meta, h->d_cnt, h->d_ovf,
+                                 h->d_arena, h->d_ctrl, sp));
+      HCK(h, hipEventRecord(h->ev_own[2 * subs + 1], h->stream));
+    }
+    HCK(h, hipEventRecord(h->ev1, h->stream));
+    agg_status s = read_ctrl(h);
+    if (s) return s;
+    float ms = 0.f;
+    HCK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->st.partition_ms += ms;
+    for (uint32_t i = 0; i < subs; ++i) {
+      HCK(h, hipEventElapsedTime(&ms, h->ev_own[2 * i], h->ev_own[2 * i + 1]));
+      h->st.update_ms += ms;
+      h->st.update_ms_l0 += ms;
+    }
+    h->st.update_launches += subs;
+    h->st.update_launches_l0 += subs;
+    h->st.update_records += g;
+    h->st.update_records_l0 += g;
+    const uint64_t got = h->h_ctrl->raw_ctr;
+    h->next.commit(dst, got, rb, false);
+    h->st.records_spilled += got;
+    h->st.bytes_spilled_d2h += got * rb;
+    s = handle_overflow(h);
+    if (s) return s;
+  }
   return AGG_OK;
 }
 
@@ -1055,14 +1165,24 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     // holds the partitioned batch; otherwise per-partition HBM tables.
     LdsPlan lp;
     const double G = h->spec.est_groups ? (double)h->spec.est_groups : (double)n;
-    if (h->spec.engine != AGG_ENGINE_TABLES && (h->spec.engine == AGG_ENGINE_LDS || !h->hot_key) &&
-        n * h->ks.rb <= (1ull << 30) && lds_plan(h, n, G, &lp)) {
+    if ((h->spec.engine == AGG_ENGINE_AUTO || h->spec.engine == AGG_ENGINE_LDS) &&
+        (h->spec.engine == AGG_ENGINE_LDS || !h->hot_key) && n * h->ks.rb <= (1ull << 30) &&
+        lds_plan(h, n, G, &lp)) {
       h->engine = 2;
       h->st.engine = 2;
       return run_lds(h, (const uint8_t *)d_records, n, lp);
     }
-    h->engine = 1;
-    h->st.engine = 1;
+    // Owner-computed tables when asked for.  (Not yet chosen automatically: on
+    // the 200M-record uniform workload it measured slower than the atomic
+    // tables, its probes at high table load being latency-bound.)
+    const bool want_owner = h->spec.engine == AGG_ENGINE_OWNER;
+    if (want_owner && !h->planned && owner_setup(h)) {
+      h->engine = 3;
+      h->st.engine = 3;
+    } else {
+      h->engine = 1;
+      h->st.engine = 1;
+    }
   } else if (h->engine == 2) {
     agg_status s = demote_lds(h, n);
     if (s) return s;
@@ -1080,6 +1200,7 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     h->st.partitions = h->plan.F;
     h->st.partitions_spilled = h->plan.planned_spilled;
   }
+  if (h->engine == 3) return run_owner_stream(h, (const uint8_t *)d_records, n);
   return run_stream(h, (const uint8_t *)d_records, n, 0);
 }
 
@@ -1116,6 +1237,8 @@ void agg_destroy(agg_handle *h) {
   if (h->r_block) dev_put(h->r_block, h->r_block_bytes);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
+  for (auto &e : h->ev_own)
+    if (e) (void)hipEventDestroy(e);
   if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
   if (h->h_scratch) (void)hipHostFree(h->h_scratch);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);

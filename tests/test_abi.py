@@ -73,3 +73,30 @@ def test_null_arguments():
     assert lib.agg_consume(None, None, 0) == -1
     assert lib.agg_finish(None, None) == -1
     lib.agg_destroy(None)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors have the sizes and field offsets the C header gives its structs."""
+    import ctypes
+    import subprocess
+    from paper_1311_0059_amd import _native as N
+    pairs = {"agg_spec": N.Spec, "agg_result": N.Result, "agg_stats": N.Stats, "agg_instance": N.Instance,
+             "agg_batch_stats": N.BatchStats, "agg_server_config": N.ServerConfig,
+             "agg_request_info": N.RequestInfo, "agg_server_stats": N.ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{ROOT}/include/aggx.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            cf = "in" if fname == "in_" else fname
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        cname, field, val = line.split()
+        py = pairs[cname]
+        got = ctypes.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert got == int(val), f"{cname}.{field}: ctypes {got} vs C {val}"
