@@ -667,6 +667,13 @@ struct LdsPlan {
 constexpr uint32_t kLdsBlock = 512;
 constexpr double kLdsLoad = 0.75;
 
+// Records per block of the partition count/scatter kernels: about 256 blocks
+// per launch.  Each block adds its LDS histogram to the global per-partition
+// counters with one atomic per non-empty partition, and those atomics contend
+// on the same F counters; fewer, larger blocks keep them few (and make each
+// block's runs per partition longer for the scatter's writes).
+uint64_t part_chunk(uint64_t n) { return std::max<uint64_t>(1024, (n + 255) / 256); }
+
 // Can the batch be aggregated partition by partition in LDS?  Each partition's
 // expected groups (plus four standard deviations) must fit one workgroup's LDS
 // table, with at most 2^12 partitions; the working budget must hold the
@@ -723,8 +730,7 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   unsigned long long *offsets = cursors + (uint64_t)lp.F * (kCntStride / 2);
   h->st.pool_high_water = std::max(h->st.pool_high_water, kOverhead + lp.need);
   const uint32_t shift = lp.b ? 64 - lp.b : 0, mask = lp.F - 1;
-  // per-block chunks of about 4096 records (at least one block per 2 partitions)
-  const uint64_t chunk = std::max<uint64_t>(1024, std::min<uint64_t>(4096, n / 256 + 1));
+  const uint64_t chunk = part_chunk(n);
   HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)lp.F * kCntStride, 0));
   HCK(h, launch_part_count(h->stream, in, n, h->ks, shift, mask, chunk, totals));
   HCK(h, launch_part_offsets(h->stream, totals, lp.F, offsets, cursors));
@@ -812,7 +818,7 @@ agg_status run_owner_stream(agg_handle *h, const uint8_t *in, uint64_t n) {
     for (uint64_t so = 0; so < g; so += m, ++subs) {
       const uint64_t c = std::min(m, g - so);
       const uint8_t *src = in + (off + so) * rb;
-      const uint64_t chunk = std::max<uint64_t>(1024, std::min<uint64_t>(4096, c / 256 + 1));
+      const uint64_t chunk = part_chunk(c);
       HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)pl.F * kCntStride, 0));
       HCK(h, launch_part_count(h->stream, src, c, h->ks, shift, mask, chunk, totals));
       HCK(h, launch_part_offsets(h->stream, totals, pl.F, offsets, cursors));
