@@ -26,6 +26,23 @@ __device__ __forceinline__ uint32_t bdigit(uint64_t key, uint32_t b) {
   return b ? (uint32_t)(fmix64(key ^ kSeed0) >> (64 - b)) : 0u;
 }
 
+// LDS histogram of the partition digit over records [lo, hi), four records per
+// thread per step so that their key loads are in flight together (one block
+// per compute unit leaves few waves to hide load latency otherwise).
+__device__ __forceinline__ void count_digits(const uint8_t *in, uint64_t lo, uint64_t hi, const KSpec &ks, uint32_t b,
+                                             uint32_t *lh) {
+  const uint64_t B = blockDim.x;
+  uint64_t i = lo + threadIdx.x;
+  for (; i + 3 * B < hi; i += 4 * B) {
+    uint64_t k[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) k[u] = read_key(in + (i + u * B) * ks.rb, ks);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) atomicAdd(&lh[bdigit(k[u], b)], 1u);
+  }
+  for (; i < hi; i += B) atomicAdd(&lh[bdigit(read_key(in + i * ks.rb, ks), b)], 1u);
+}
+
 // Wait (thread 0) until *ctr >= target; returns false if the spin limit hit.
 __device__ bool wait_for(uint32_t *ctr, uint32_t target, uint32_t limit, uint32_t *err) {
   uint32_t spins = 0;
@@ -62,21 +79,13 @@ __device__ void lds_aggregate(const uint8_t *in, uint64_t lo, uint64_t hi, const
   if (tid == 0) *s_groups = 0;
   __syncthreads();
   bool bad = false;
-  for (uint64_t i = lo + tid; i < hi; i += blockDim.x) {
-    const uint8_t *rec = in + i * ks.rb;
-    uint64_t vals[kMaxAggs];
-    const uint64_t key = read_key(rec, ks);
-    in_vals<0>(rec, ks, vals);
-    if (key >= kClosed) {
-      bad = true;
-      continue;
-    }
+  // insert one record's key (or find it) and fold its values; false if it found no room
+  auto fold_one = [&](uint64_t key, const uint64_t *vals) -> bool {
     uint32_t idx = (uint32_t)mulhi64(fmix64(key ^ kSeed0) << slot_shift, nslots);
-    bool done = false;
     for (uint32_t t = 0; t < nslots; ++t) {
       unsigned long long sk = t_key[idx];
       if (sk == kEmpty) {
-        if (*s_groups >= P.cap) break;
+        if (*s_groups >= P.cap) return false;
         sk = atomicCAS(reinterpret_cast<unsigned long long *>(t_key + idx), (unsigned long long)kEmpty,
                        (unsigned long long)key);
         if (sk == kEmpty) {
@@ -86,12 +95,21 @@ __device__ void lds_aggregate(const uint8_t *in, uint64_t lo, uint64_t hi, const
       }
       if (sk == key) {
         fold_lds(t_acc + idx, nslots, ks, vals);
-        done = true;
-        break;
+        return true;
       }
       idx = idx + 1 == nslots ? 0 : idx + 1;
     }
-    bad |= !done;
+    return false;
+  };
+  for (uint64_t i = lo + tid; i < hi; i += blockDim.x) {
+    const uint8_t *rec = in + i * ks.rb;
+    uint64_t vals[kMaxAggs];
+    const uint64_t key = read_key(rec, ks);
+    in_vals<0>(rec, ks, vals);
+    if (key >= kClosed)
+      bad = true;
+    else
+      bad |= !fold_one(key, vals);
   }
   if (bad) __hip_atomic_store(P.ovf + inst, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
@@ -148,7 +166,7 @@ __global__ void __launch_bounds__(1024) k_batch(BParams P) {
       case IT_COUNT: {
         for (uint32_t d = tid; d < F; d += blockDim.x) lh[d] = 0;
         __syncthreads();
-        for (uint64_t i = it.lo + tid; i < it.hi; i += blockDim.x) atomicAdd(&lh[bdigit(read_key(I.in + i * ks.rb, ks), I.b)], 1u);
+        count_digits(I.in, it.lo, it.hi, ks, I.b, lh);
         __syncthreads();
         for (uint32_t d = tid; d < F; d += blockDim.x)
           if (lh[d]) __hip_atomic_fetch_add(P.totals + I.pbase + d, lh[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -184,7 +202,7 @@ __global__ void __launch_bounds__(1024) k_batch(BParams P) {
         unsigned long long *lbase = reinterpret_cast<unsigned long long *>(lh + 4096);
         for (uint32_t d = tid; d < F; d += blockDim.x) lh[d] = 0;
         __syncthreads();
-        for (uint64_t i = it.lo + tid; i < it.hi; i += blockDim.x) atomicAdd(&lh[bdigit(read_key(I.in + i * ks.rb, ks), I.b)], 1u);
+        count_digits(I.in, it.lo, it.hi, ks, I.b, lh);
         __syncthreads();
         for (uint32_t d = tid; d < F; d += blockDim.x) {
           if (lh[d])
@@ -194,7 +212,22 @@ __global__ void __launch_bounds__(1024) k_batch(BParams P) {
         }
         __syncthreads();
         const uint32_t words = ks.rb / 4;
-        for (uint64_t i = it.lo + tid; i < it.hi; i += blockDim.x) {
+        const uint64_t B = blockDim.x;
+        uint64_t i = it.lo + tid;
+        // four records per thread per step, so that their loads are in flight together
+        for (; i + 3 * B < it.hi; i += 4 * B) {
+          uint32_t dg[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) dg[u] = bdigit(read_key(I.in + (i + u * B) * ks.rb, ks), I.b);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t r = atomicAdd(&lh[dg[u]], 1u);
+            uint32_t *dst = reinterpret_cast<uint32_t *>(I.buf + (lbase[dg[u]] + r) * ks.rb);
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(I.in + (i + u * B) * ks.rb);
+            for (uint32_t w = 0; w < words; ++w) dst[w] = src[w];
+          }
+        }
+        for (; i < it.hi; i += B) {
           const uint8_t *rec = I.in + i * ks.rb;
           const uint32_t d = bdigit(read_key(rec, ks), I.b);
           const uint32_t r = atomicAdd(&lh[d], 1u);
