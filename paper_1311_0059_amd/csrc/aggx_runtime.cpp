@@ -233,6 +233,7 @@ struct agg_handle {
   int engine = 0;   // 0 undecided, 1 HBM tables, 2 partition-first with LDS tables, 3 owner-computed tables
   // owner engine: bytes at the top of the arena for the partition buffer and its
   // counters (level 0 only), records per sub-chunk, and timing events
+  uint64_t plan_hint_n = 0;  // records of the first batch (known when level 0 is planned at the first consume)
   uint64_t owner_reserve = 0;
   uint64_t owner_m = 0;
   hipEvent_t ev_own[2 * kOwnerMaxSub] = {};
@@ -379,6 +380,15 @@ agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_
   // table bytes: the arena minus, at level 0 of the owner engine, its buffer area
   const uint64_t reserve = level == 0 ? h->owner_reserve : 0;
   uint64_t cap_bytes = h->arena_cap_bytes > reserve ? (h->arena_cap_bytes - reserve) / 256 * 256 : 0;
+  // The estimate may be low.  A first batch of n records can hold up to n
+  // groups: plan level 0 for at least min(n, what the budget holds at the
+  // default load), so an underestimate does not leave the tables (and the
+  // fan-out) too small -- a group that finds no room costs a spill, a larger
+  // table only its initialisation and flush scan.
+  if (level == 0 && !h->unlimited && h->plan_hint_n) {
+    const double fits = (double)cap_bytes * kDefaultLoad / W8;
+    G = std::max(G, std::min((double)h->plan_hint_n, fits));
+  }
   uint32_t b;
   if (h->spec.fanout_bits) {
     b = h->spec.fanout_bits;
@@ -431,6 +441,12 @@ agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_
       const uint64_t tight = (uint64_t)std::ceil(cap_need / kPlanMaxLoad) + 1;
       if ((uint64_t)pl.F * tight * W8 <= cap_bytes) T = pl.F;
     }
+    // Pre-Partitioning (Sec. 4.3.4) keeps in memory whatever keys fit and spills
+    // only the misses, so it needs no estimate to decide what is resident: every
+    // partition starts resident.  (Dynamic Destaging keeps the partitions that
+    // Formula (1) says do not fit spilled from the start: with fixed per-partition
+    // tables, destaging one partition frees no room for the others.)
+    if (level == 0 && h->spec.policy == AGG_POLICY_PREPART && cap_bytes / ((uint64_t)pl.F * W8) >= 8) T = pl.F;
     if (T == 0) {
       T = 1;
       slots = std::max<uint64_t>(8, cap_bytes / W8);
@@ -1194,6 +1210,7 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     if (s) return s;
   }
   if (!h->planned) {
+    h->plan_hint_n = n;
     // no estimate of the distinct keys: plan for what the budget can hold
     // (unlimited budget: for as many groups as this batch has records)
     double G = h->spec.est_groups ? (double)h->spec.est_groups
