@@ -34,6 +34,7 @@ WORKLOADS = {
     "batched": "batched_mix",
     "served": "served_mix",
     "g-sweep": "uniform_spill",
+    "uniform-sorted": "uniform_spill",
 }
 
 
@@ -95,6 +96,27 @@ def main():
     log(args, f"[bench] generated in {time.perf_counter() - t:.1f}s, checksum {datagen.checksum(raw[: 1 << 24])}")
     dev = torch.empty(raw.size, dtype=torch.uint8, device="cuda")
     dev.copy_(torch.from_numpy(raw))
+    if args.workload == "uniform-sorted":
+        # the same records in non-decreasing key order (the paper's sorted dataset), sorted on the
+        # device before timing; int64 order of key ^ 2^63 is the unsigned order of the key
+        assert wl.record_bytes == 16
+        words = dev.view(torch.int64).view(-1, 2)
+        flip = torch.tensor(-(1 << 63), dtype=torch.int64, device="cuda")
+        keys, vals = words[:, 0].contiguous(), words[:, 1].contiguous()
+        perm = torch.argsort(keys ^ flip)
+        # gather the two 1-D columns and interleave them (a row gather of the whole
+        # 3.2 GB two-column tensor returned wrong rows on this torch build)
+        sk, sv = keys[perm], vals[perm]
+        out = torch.stack([sk, sv], dim=1).contiguous()
+        ok = bool(((out[1:, 0] ^ flip) >= (out[:-1, 0] ^ flip)).all().item())
+        ok &= int(out[:, 0].sum().item()) == int(keys.sum().item()) and int(out[:, 1].sum().item()) == int(vals.sum().item())
+        if not ok:
+            sys.exit("bench.py: building the sorted input on the device failed its checks")
+        dev = out.view(torch.uint8).view(-1)
+        del words, keys, vals, perm, sk, sv
+        host = dev.cpu().numpy().view(workloads.R16) if args.cpu_sample > 0 else host
+        wl = workloads.Workload(wl.name + "-sorted", wl.layout, wl.n, wl.d, wl.dist, wl.s, wl.lo, wl.hi, wl.aggs,
+                                wl.budget, wl.seed, "sorted by key")
     workspace = torch.empty(wl.budget, dtype=torch.uint8, device="cuda") if wl.budget else None
     torch.cuda.synchronize()
     spec = P.make_spec(wl.record_bytes, wl.key_fields, wl.aggs, budget=wl.budget, est_groups=wl.d,
@@ -131,7 +153,12 @@ def main():
     alg_bytes_step = wl.n * wl.record_bytes + wl.d * W8
     # dominant kernel: the level-0 aggregation/routing kernel; its algorithmic bytes are the
     # records it reads plus the grouping states it leaves in the resident tables
-    if agg["update_launches_l0"]:
+    if agg["engine"] // args.steps == 4:  # sorted runs: the check/count pass and the run reduction
+        kname = "k_run_heads+k_run_reduce"
+        l0_bytes = wl.n * args.steps * wl.record_bytes + agg["resident_groups_l0"] * W8
+        l0_ms = agg["sorted_ms"]
+        launches = args.steps
+    elif agg["update_launches_l0"]:
         kname = "k_owner_update" if agg["engine"] // args.steps == 3 else f"k_update<0, {1 if agg['preagg'] else 0}>"
         l0_bytes = agg["update_records_l0"] * wl.record_bytes + agg["resident_groups_l0"] * W8
         l0_ms = agg["update_ms_l0"]
@@ -213,6 +240,7 @@ def main():
             "flush_ms": round(agg["flush_ms"] / args.steps, 3),
             "lds_ms": round(agg["lds_ms"] / args.steps, 3),
             "partition_ms": round(agg["partition_ms"] / args.steps, 3),
+            "sorted_ms": round(agg["sorted_ms"] / args.steps, 3),
             "engine": agg["engine"] // args.steps,
             "preagg": agg["preagg"] // args.steps,
             "pool_high_water": agg["pool_high_water"] // args.steps,

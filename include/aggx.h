@@ -81,9 +81,13 @@ typedef enum agg_engine {
   AGG_ENGINE_TABLES = 1,  /* per-partition open-addressing tables in HBM, 64-bit atomics, chunked input */
   AGG_ENGINE_LDS = 2,     /* radix-partition the batch, then one workgroup aggregates each partition in an
                              LDS table; needs the budget to hold the partitioned batch (else falls back) */
-  AGG_ENGINE_OWNER = 3    /* the same HBM tables, updated without atomics: sub-chunks of the batch are
+  AGG_ENGINE_OWNER = 3,   /* the same HBM tables, updated without atomics: sub-chunks of the batch are
                              radix-partitioned into a buffer carved from the budget, and one workgroup owns
                              each partition's table while it folds that partition's records in */
+  AGG_ENGINE_SORTED = 4   /* for a first batch whose keys are in non-decreasing order: every run of equal
+                             keys becomes one row, no tables (verified in full; a batch that is not sorted
+                             takes the engine AUTO would choose).  AUTO tries it when an evenly spaced
+                             sample of the batch is sorted.  Needs at most 7 aggregates */
 } agg_engine;
 
 #define AGG_MAX_AGGS 8
@@ -140,7 +144,8 @@ typedef struct agg_stats {
   uint32_t partitions_spilled;  /* level-0 partitions spilled (planned or overflowed) */
   uint32_t guard_trips;         /* levels whose spilled output kept more than 80% of their input */
   uint32_t preagg;              /* 1 if the workgroup hot-key cache was used (skew seen in a sample) */
-  uint32_t engine;              /* engine used for the first batch: 1 HBM tables, 2 LDS, 3 owner-computed */
+  uint32_t engine;              /* engine used for the first batch: 1 HBM tables, 2 LDS, 3 owner-computed,
+                                   4 sorted runs */
   uint64_t pool_high_water;     /* peak bytes of the working budget in use */
   uint64_t pool_bytes;          /* size of the working budget actually reserved */
   /* Device time of the two main kernels, measured with HIP events recorded on
@@ -158,6 +163,7 @@ typedef struct agg_stats {
   double partition_ms;          /* owner-computed engine: its partition pipeline (count, offsets,
                                    scatter, owner update) per chunk; the owner-update kernel alone
                                    is counted in the update_* figures */
+  double sorted_ms;             /* sorted-run engine: its check, scan and run-reduction kernels */
 } agg_stats;
 
 /* Validate and copy `spec`, reserve the working budget (or adopt the caller's

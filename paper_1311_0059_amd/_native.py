@@ -77,6 +77,7 @@ class Stats(ctypes.Structure):
         ("lds_launches", ctypes.c_uint64),
         ("lds_ms", ctypes.c_double),
         ("partition_ms", ctypes.c_double),
+        ("sorted_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

@@ -73,6 +73,8 @@ struct Ctrl {
   unsigned long long side_n[2];   // records with the reserved key values kEmpty, kClosed
   unsigned long long sample_dups;  // skew sampling: repeated keys in the sample
   unsigned long long sample_max;   // skew sampling: most samples sharing one key
+  unsigned long long sample_unsorted;  // skew sampling: 1 if the sampled keys are not in non-decreasing order
+  unsigned long long unsorted;     // sorted-run path: 1 if the batch is not in non-decreasing key order
   unsigned long long side[2][kMaxAggs];  // their side groups' aggregates
 };
 
@@ -139,7 +141,8 @@ hipError_t launch_ctrl_init(hipStream_t s, Ctrl *c, const KSpec &ks);
 hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint64_t n, const KSpec &ks,
                          const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint32_t *ovf, uint64_t *arena,
                          Ctrl *ctrl, KSpill spill, int preagg);
-// Repeated keys and the largest key multiplicity among `ns` evenly spaced records (ns <= 2048).
+// Among `ns` evenly spaced records (ns <= 2048): repeated keys, the largest key
+// multiplicity, and whether the sampled keys are out of order (out[0..2]).
 hipError_t launch_sample_dups(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t ns,
                               unsigned long long *out);
 hipError_t launch_flush(hipStream_t s, const uint64_t *arena, uint64_t nslots, const KSpec &ks, uint64_t *out_keys,
@@ -176,6 +179,19 @@ hipError_t launch_owner_update(hipStream_t s, const uint8_t *buf, const unsigned
                                uint64_t *arena, Ctrl *ctrl, KSpill spill);
 // Dynamic LDS bytes of the owner-update kernel for this record layout.
 uint32_t owner_lds_bytes(const KSpec &ks, uint32_t *stage_cap);
+// Sorted-run path (input in non-decreasing key order): per tile of kRunTile
+// records, count the records that start a run of a non-reserved key and flag a
+// descent; exclusive scan of the tile counts into tile_base (total -> ctrl->rows);
+// then fold every run into its row (rows of runs that cross a tile boundary by
+// atomics, so they must hold identity values first: launch_rows_init).
+constexpr uint32_t kRunTile = 1024;
+hipError_t launch_run_heads(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t *tile_heads,
+                            Ctrl *ctrl);
+hipError_t launch_run_scan(hipStream_t s, const uint32_t *tile_heads, uint64_t tiles, unsigned long long *tile_base,
+                           Ctrl *ctrl);
+hipError_t launch_rows_init(hipStream_t s, const KSpec &ks, const OutCols &cols, uint64_t n);
+hipError_t launch_run_reduce(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, const uint32_t *tile_heads,
+                             const unsigned long long *tile_base, Ctrl *ctrl, uint64_t *out_keys, const OutCols &cols);
 // Largest dynamic LDS the LDS-aggregation kernel can be launched with (bytes).
 uint32_t lds_agg_max_bytes();
 // Batched mode.

@@ -203,10 +203,20 @@ __global__ void __launch_bounds__(256) k_sample_dups(const uint8_t *__restrict__
       e = (e + 1) & 4095;
     }
   }
+  // is the sample in non-decreasing key order?
+  __shared__ uint32_t descents;
+  if (threadIdx.x == 0) descents = 0;
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j + 1 < ns; j += blockDim.x) {
+    const uint64_t a = read_key(in + ((uint64_t)j * n / ns) * ks.rb, ks);
+    const uint64_t b = read_key(in + ((uint64_t)(j + 1) * n / ns) * ks.rb, ks);
+    if (b < a) atomicAdd(&descents, 1u);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     out[0] = dups;
     out[1] = maxc;
+    out[2] = descents ? 1 : 0;
   }
 }
 

@@ -238,6 +238,7 @@ struct agg_handle {
   uint64_t owner_m = 0;
   hipEvent_t ev_own[2 * kOwnerMaxSub] = {};
   int hot_key = 0;  // the sample showed one key with a large share of the records
+  int sample_sorted = 0;  // the sampled keys were in non-decreasing order
   int state = H_OPEN;
   agg_stats st{};
   uint64_t lvl_in = 0;  // records + states fed to the current level (for the shrink guard)
@@ -287,7 +288,7 @@ agg_status validate(const agg_spec *s) {
   if (wide && s->record_bytes % 8) return AGG_E_INVALID;
   if (s->fanout_bits > (uint32_t)kMaxFanBits) return AGG_E_INVALID;
   if (s->load_pct != 0 && (s->load_pct < 10 || s->load_pct > 95)) return AGG_E_INVALID;
-  if (s->policy > AGG_POLICY_PREPART || s->preagg > 2 || s->engine > AGG_ENGINE_OWNER) return AGG_E_INVALID;
+  if (s->policy > AGG_POLICY_PREPART || s->preagg > 2 || s->engine > AGG_ENGINE_SORTED) return AGG_E_INVALID;
   if (s->device_workspace && (s->workspace_bytes < s->budget_bytes || ((uintptr_t)s->device_workspace & 255)))
     return AGG_E_BUDGET;
   if (s->device_workspace && s->budget_bytes == 0) return AGG_E_INVALID;
@@ -781,6 +782,52 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   return AGG_OK;
 }
 
+// ---- sorted runs ------------------------------------------------------------
+// First batch in non-decreasing key order: check it in full while counting the
+// runs per tile, then turn every run into one row.  *applied is false (and
+// nothing is changed) when the batch is not sorted or the path does not apply.
+agg_status run_sorted(agg_handle *h, const uint8_t *in, uint64_t n, bool *applied) {
+  *applied = false;
+  if (h->ks.na > 7 || n >= (1ull << 32)) return AGG_OK;  // LDS rows of one tile fit 64 KB; 32-bit run counts
+  const uint64_t tiles = (n + kRunTile - 1) / kRunTile;
+  const uint64_t heads_bytes = round_up(tiles * 4, 256), need = heads_bytes + tiles * 8;
+  if (h->unlimited) {
+    agg_status s = grow_unlimited_pool(h, need);
+    if (s) return s;
+  } else if (need > h->arena_cap_bytes) {
+    return AGG_OK;
+  }
+  uint32_t *tile_heads = reinterpret_cast<uint32_t *>(h->d_arena);
+  unsigned long long *tile_base = reinterpret_cast<unsigned long long *>(reinterpret_cast<uint8_t *>(h->d_arena) +
+                                                                         heads_bytes);
+  HCK(h, hipEventRecord(h->ev0, h->stream));
+  HCK(h, launch_u64_set(h->stream, &h->d_ctrl->unsorted, 1, 0));
+  HCK(h, launch_run_heads(h->stream, in, n, h->ks, tile_heads, h->d_ctrl));
+  HCK(h, launch_run_scan(h->stream, tile_heads, tiles, tile_base, h->d_ctrl));
+  agg_status s = read_ctrl(h);
+  if (s) return s;
+  if (h->h_ctrl->unsorted) return AGG_OK;  // not sorted after all: the hash engines take the batch
+  const uint64_t R = h->h_ctrl->rows;
+  s = ensure_result_cap(h, h->r_rows + R + 1);
+  if (s) return s;
+  OutCols oc{};
+  for (uint32_t a = 0; a < h->spec.n_aggs; ++a) oc.c[a] = h->r_cols[a] + h->r_rows;
+  HCK(h, launch_rows_init(h->stream, h->ks, oc, R));
+  HCK(h, launch_run_reduce(h->stream, in, n, h->ks, tile_heads, tile_base, h->d_ctrl, h->r_keys + h->r_rows, oc));
+  HCK(h, hipEventRecord(h->ev1, h->stream));
+  s = read_ctrl(h);
+  if (s) return s;
+  float ms = 0.f;
+  HCK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  h->st.sorted_ms += ms;
+  h->st.pool_high_water = std::max(h->st.pool_high_water, kOverhead + need);
+  h->r_rows += R;
+  h->engine = 4;
+  h->st.engine = 4;
+  *applied = true;
+  return AGG_OK;
+}
+
 // ---- owner-computed HBM tables ---------------------------------------------
 // Reserve the top of the arena for the partition buffer of one sub-chunk and
 // the partition counters, cursors and offsets (sized for the largest fan-out).
@@ -985,7 +1032,8 @@ agg_status hybrid_pass(agg_handle *h, uint32_t depth, double G, uint32_t consume
 }
 
 agg_status finish_impl(agg_handle *h) {
-  if (!h->planned && h->engine != 2) {
+  const bool rows_direct = h->engine == 2 || h->engine == 4;  // level 0 wrote its rows without tables
+  if (!h->planned && !rows_direct) {
     agg_status s = make_plan(h, 0, h->spec.est_groups ? (double)h->spec.est_groups : 1.0, 0);
     if (s) return s;
     h->used_bits = h->plan.fan_bits;
@@ -998,7 +1046,7 @@ agg_status finish_impl(agg_handle *h) {
   // level 0 is complete: estimate the distinct keys of what was spilled
   double G = h->next.empty() ? 0.0 : read_hll(h, &s);
   if (s) return s;
-  if (h->engine != 2) {
+  if (!rows_direct) {
     s = flush_level(h, G * 1.1);
     if (s) return s;
   }
@@ -1178,9 +1226,16 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     // than 2% of it: a hot key that would unbalance a partition-per-workgroup pass
     if (h->preagg < 0) h->preagg = ns >= 256 && h->h_ctrl->sample_dups * 20 > ns ? 1 : 0;
     h->hot_key = ns >= 256 && h->h_ctrl->sample_max * 50 > ns;
+    h->sample_sorted = ns >= 2 && h->h_ctrl->sample_unsorted == 0;
   }
   h->st.preagg = (uint32_t)h->preagg;
   h->st.records_in += n;
+  if (h->engine == 0 &&
+      (h->spec.engine == AGG_ENGINE_SORTED || (h->spec.engine == AGG_ENGINE_AUTO && h->sample_sorted))) {
+    bool applied = false;
+    agg_status s = run_sorted(h, (const uint8_t *)d_records, n, &applied);
+    if (s || applied) return s;
+  }
   if (h->engine == 0) {
     // First batch: partition-first with LDS tables when the input shows no
     // repeated-key skew (skew would unbalance the partitions) and the budget
@@ -1205,7 +1260,8 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
       h->engine = 1;
       h->st.engine = 1;
     }
-  } else if (h->engine == 2) {
+  } else if (h->engine == 2 || h->engine == 4) {
+    // rows of a first batch written directly (LDS or sorted runs) become states in HBM tables
     agg_status s = demote_lds(h, n);
     if (s) return s;
   }

@@ -32,7 +32,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 # the sources whose change invalidates a measured traffic figure
 KERNEL_SOURCES = ["csrc/aggx_kernels.hip", "csrc/aggx_device.h", "csrc/aggx_internal.h", "csrc/aggx_lds.hip",
-                  "csrc/aggx_owner.hip", "csrc/aggx_runtime.cpp"]
+                  "csrc/aggx_owner.hip", "csrc/aggx_sorted.hip", "csrc/aggx_runtime.cpp"]
 
 
 def sources_hash() -> str:
