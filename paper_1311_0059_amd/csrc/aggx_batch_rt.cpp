@@ -36,7 +36,7 @@ constexpr uint32_t kSpinLimit = 50u * 1000u * 1000u;  // ~ seconds of s_sleep; e
 struct Cand {
   uint64_t part_records, chunk_records, solo_max;
 };
-const Cand kCands[4] = {{16384, 16384, 65536}, {32768, 32768, 131072}, {65536, 65536, 262144}, {32768, 16384, 32768}};
+const Cand kCands[4] = {{65536, 65536, 262144}, {65536, 262144, 262144}, {65536, 1048576, 262144}, {65536, 262144, 524288}};
 
 std::mutex g_tune_mu;
 std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, uint32_t> g_tune_cache;
