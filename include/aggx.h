@@ -180,6 +180,18 @@ agg_status agg_create(const agg_spec *spec, agg_handle **out);
  * After agg_finish it returns AGG_E_STATE. */
 agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n);
 
+/* Early output (the hybrid-hash family's resident partitions go to the final
+ * output directly, Sec. 4.3): after the last agg_consume, flush level 0 and
+ * publish in *out the rows of every group whose key stayed resident there --
+ * all of its records were aggregated in memory, so the row is final.  It does
+ * not start the recursion over the spilled partitions.  The rows are in device
+ * memory owned by the handle; the pointers stay valid until the next agg_finish
+ * or agg_destroy.  agg_finish afterwards returns all rows, its first n_rows
+ * being these rows in the same order (the columns may have moved).  Rows of the
+ * two reserved key values are not among them.  After this call agg_consume
+ * returns AGG_E_STATE; calling it again returns the same rows. */
+agg_status agg_first_rows(agg_handle *h, agg_result *out);
+
 /* Finish level 0, run every recursion level over the spilled partitions, and
  * publish the rows in *out.  Blocks until the result is complete.  Calling it
  * again returns the same result. */

@@ -115,6 +115,17 @@ class GroupBy:
     def consume_ptr(self, ptr: int, n: int):
         _check(self._lib.agg_consume(self._h, ctypes.c_void_p(ptr), n), "agg_consume")
 
+    def first_result(self) -> N.Result:
+        """agg_first_rows: descriptor of the rows finished in memory at level 0 (device
+        memory owned by the handle), before the recursion over spilled partitions."""
+        res = N.Result()
+        _check(self._lib.agg_first_rows(self._h, ctypes.byref(res)), "agg_first_rows")
+        return res
+
+    def first_rows(self, device: str = "cpu"):
+        """The level-0 rows copied out: (keys as int64 view of u64, cols [n_aggs, n])."""
+        return _copy_rows(self.first_result(), self._spec.n_aggs, device)
+
     def finish(self) -> N.Result:
         res = N.Result()
         _check(self._lib.agg_finish(self._h, ctypes.byref(res)), "agg_finish")

@@ -129,7 +129,7 @@ class ServerStats(ctypes.Structure):
 
 
 # every symbol include/aggx.h declares
-EXPORTS = ["agg_create", "agg_consume", "agg_finish", "agg_get_stats", "agg_destroy", "agg_strerror",
+EXPORTS = ["agg_create", "agg_consume", "agg_first_rows", "agg_finish", "agg_get_stats", "agg_destroy", "agg_strerror",
            "agg_min_budget", "agg_batch_create", "agg_batch_run", "agg_batch_result", "agg_batch_get_stats",
            "agg_batch_destroy", "agg_server_create", "agg_server_submit", "agg_server_wait",
            "agg_server_release", "agg_server_get_stats", "agg_server_destroy"]
@@ -152,6 +152,8 @@ def load(path: str = LIB_PATH):
     lib.agg_consume.restype = ctypes.c_int
     lib.agg_finish.argtypes = [vp, ctypes.POINTER(Result)]
     lib.agg_finish.restype = ctypes.c_int
+    lib.agg_first_rows.argtypes = [vp, ctypes.POINTER(Result)]
+    lib.agg_first_rows.restype = ctypes.c_int
     lib.agg_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.agg_get_stats.restype = ctypes.c_int
     lib.agg_destroy.argtypes = [vp]

@@ -240,6 +240,8 @@ struct agg_handle {
   int hot_key = 0;  // the sample showed one key with a large share of the records
   int sample_sorted = 0;  // the sampled keys were in non-decreasing order
   int state = H_OPEN;
+  bool l0_done = false;  // level 0 flushed (agg_first_rows or agg_finish); no more batches
+  double l0_G = 0.0;     // estimated distinct keys of what level 0 spilled
   agg_stats st{};
   uint64_t lvl_in = 0;  // records + states fed to the current level (for the shrink guard)
 };
@@ -1031,7 +1033,10 @@ agg_status hybrid_pass(agg_handle *h, uint32_t depth, double G, uint32_t consume
   return flush_level(h, 0.0);
 }
 
-agg_status finish_impl(agg_handle *h) {
+// Level 0 after the last batch: flush the resident tables to rows (their groups
+// are final: a resident key never spilled a record) and estimate the distinct
+// keys of what was spilled.
+agg_status finish_level0(agg_handle *h) {
   const bool rows_direct = h->engine == 2 || h->engine == 4;  // level 0 wrote its rows without tables
   if (!h->planned && !rows_direct) {
     agg_status s = make_plan(h, 0, h->spec.est_groups ? (double)h->spec.est_groups : 1.0, 0);
@@ -1052,6 +1057,20 @@ agg_status finish_impl(agg_handle *h) {
   }
   h->st.resident_groups_l0 = h->r_rows;
   h->st.levels = 1;
+  h->l0_G = G;
+  h->l0_done = true;
+  return AGG_OK;
+}
+
+// Phase 2 and the end: re-aggregate the spilled runs level by level, then
+// append the side groups.
+agg_status finish_impl(agg_handle *h) {
+  agg_status s = AGG_OK;
+  if (!h->l0_done) {
+    s = finish_level0(h);
+    if (s) return s;
+  }
+  double G = h->l0_G;
   const double lam = h->spec.load_pct ? h->spec.load_pct / 100.0 : kDefaultLoad;
   const double cap_groups = h->unlimited ? 1e300 : (double)h->arena_cap_bytes * lam / h->W8;
   uint32_t consumed = h->used_bits;
@@ -1212,7 +1231,7 @@ agg_status agg_create(const agg_spec *spec, agg_handle **out) {
 agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
   if (!h) return AGG_E_INVALID;
   if (h->state == H_POISONED) return AGG_E_DEVICE;
-  if (h->state != H_OPEN) return AGG_E_STATE;
+  if (h->state != H_OPEN || h->l0_done) return AGG_E_STATE;
   if (n == 0) return AGG_OK;
   if (!d_records || ((uintptr_t)d_records & (h->ks.rb % 8 ? 3 : 7))) return AGG_E_INVALID;
   if (h->engine == 0) {
@@ -1297,6 +1316,24 @@ agg_status agg_finish(agg_handle *h, agg_result *out) {
   }
   memset(out, 0, sizeof(*out));
   out->n_rows = h->r_rows;
+  out->d_keys = h->r_keys;
+  for (uint32_t a = 0; a < h->spec.n_aggs; ++a) out->d_cols[a] = h->r_cols[a];
+  return AGG_OK;
+}
+
+agg_status agg_first_rows(agg_handle *h, agg_result *out) {
+  if (!h || !out) return AGG_E_INVALID;
+  if (h->state == H_POISONED) return AGG_E_DEVICE;
+  if (h->state == H_OPEN && !h->l0_done) {
+    agg_status s = finish_level0(h);
+    if (s) {
+      if (s != AGG_E_DEVICE) h->state = H_POISONED;
+      h->next.release();
+      return s;
+    }
+  }
+  memset(out, 0, sizeof(*out));
+  out->n_rows = h->st.resident_groups_l0;
   out->d_keys = h->r_keys;
   for (uint32_t a = 0; a < h->spec.n_aggs; ++a) out->d_cols[a] = h->r_cols[a];
   return AGG_OK;
