@@ -278,12 +278,13 @@ void agg_server_destroy(agg_server *s) {
   }
   for (auto &t : s->workers)
     if (t.joinable()) t.join();
+  // every request not yet released is in reqs, queued ones included
   for (auto &kv : s->reqs) {
     if (kv.second->h) agg_destroy(kv.second->h);
     delete kv.second;
   }
-  for (Req *r : s->queue)
-    if (!s->reqs.count(r->ticket)) delete r;
+  s->reqs.clear();
+  s->queue.clear();
   for (auto st : s->streams) (void)hipStreamDestroy(st);
   if (s->pool) (void)hipFree(s->pool);
   delete s;

@@ -85,3 +85,25 @@ def test_admission_waits_for_memory_and_rejects_oversize():
     wk, wc = oracle.groupby(r, SPEC)
     for k, c in rows:
         assert_rows_equal(k, c, wk, wc, "admission")
+
+
+def test_destroy_with_queued_requests():
+    """Closing a server with requests still queued frees each of them once (no
+    release needed); a new server afterwards gives the oracle's rows."""
+    import torch
+    import paper_1311_0059_amd as P
+    r = datagen.r16(11, 200_000, 20_000)
+    dev = torch.from_numpy(r.view(np.uint8).copy()).to("cuda")
+    torch.cuda.synchronize()
+    spec = P.make_spec(16, [(0, "u64")], workloads.AGGS_R16_ALL, budget=16 * MIB, est_groups=20_000)
+    for _ in range(3):
+        srv = P.Server(pool_bytes=64 * MIB, max_inflight=1)
+        for _ in range(30):
+            srv.submit(spec, dev.data_ptr(), r.size)
+        srv.close()
+    with P.Server(pool_bytes=64 * MIB, max_inflight=2) as srv:
+        t = srv.submit(spec, dev.data_ptr(), r.size)
+        k, c = _sorted_rows(*srv.rows(t))
+        srv.release(t)
+    wk, wc = oracle.groupby(r, SPEC)
+    assert_rows_equal(k, c, wk, wc, "after destroy with queued requests")
