@@ -30,6 +30,7 @@ METRIC = "input records/s + % HBM peak (bit-exact); served p50/p99 latency vs pl
 WORKLOADS = {
     "uniform-spill": "uniform_spill",
     "uniform-small": "uniform_small",
+    "uniform-inmem": "uniform_inmem",
     "zipf-composite": "zipf_composite",
     "batched": "batched_mix",
     "served": "served_mix",
@@ -244,6 +245,7 @@ def main():
             "lds_ms": round(agg["lds_ms"] / args.steps, 3),
             "partition_ms": round(agg["partition_ms"] / args.steps, 3),
             "sorted_ms": round(agg["sorted_ms"] / args.steps, 3),
+            "lds_sweeps": agg["lds_sweeps"] // args.steps,
             "engine": agg["engine"] // args.steps,
             "preagg": agg["preagg"] // args.steps,
             "pool_high_water": agg["pool_high_water"] // args.steps,

@@ -85,6 +85,12 @@ def uniform_spill() -> Workload:
                     AGGS_R16_ALL, 1 * GIB, SEED_BASE + 2)
 
 
+def uniform_inmem() -> Workload:
+    """The same 200M records as uniform_spill (same seed), with an unlimited budget: nothing spills."""
+    return Workload("uniform-200M-20M-unlimited", "R16", 200_000_000, 20_000_000, UNIFORM, 0.0, -1_000_000,
+                    1_000_000, AGGS_R16_ALL, 0, SEED_BASE + 2)
+
+
 def zipf_composite() -> Workload:
     """500M R24 records, 50M composite keys Zipf s=1.0, SUM(v1) MIN(v2) MAX(v3) COUNT, 4 GiB budget."""
     return Workload("zipf1-500M-50M-4GiB", "R24", 500_000_000, 50_000_000, ZIPF, 1.0, -1_000_000_000,

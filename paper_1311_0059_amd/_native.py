@@ -78,6 +78,8 @@ class Stats(ctypes.Structure):
         ("lds_ms", ctypes.c_double),
         ("partition_ms", ctypes.c_double),
         ("sorted_ms", ctypes.c_double),
+        ("lds_sweeps", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:

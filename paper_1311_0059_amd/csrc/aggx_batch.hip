@@ -79,13 +79,15 @@ __device__ void lds_aggregate(const uint8_t *in, uint64_t lo, uint64_t hi, const
   if (tid == 0) *s_groups = 0;
   __syncthreads();
   bool bad = false;
-  // insert one record's key (or find it) and fold its values; false if it found no room
+  // insert one record's key (or find it) and fold its values; false if it found no room.
+  // The fold follows the probe loop, so that a wave runs it once whatever slot each lane found.
   auto fold_one = [&](uint64_t key, const uint64_t *vals) -> bool {
     uint32_t idx = (uint32_t)mulhi64(fmix64(key ^ kSeed0) << slot_shift, nslots);
+    uint32_t slot = ~0u;
     for (uint32_t t = 0; t < nslots; ++t) {
       unsigned long long sk = t_key[idx];
       if (sk == kEmpty) {
-        if (*s_groups >= P.cap) return false;
+        if (*s_groups >= P.cap) break;
         sk = atomicCAS(reinterpret_cast<unsigned long long *>(t_key + idx), (unsigned long long)kEmpty,
                        (unsigned long long)key);
         if (sk == kEmpty) {
@@ -94,12 +96,14 @@ __device__ void lds_aggregate(const uint8_t *in, uint64_t lo, uint64_t hi, const
         }
       }
       if (sk == key) {
-        fold_lds(t_acc + idx, nslots, ks, vals);
-        return true;
+        slot = idx;
+        break;
       }
       idx = idx + 1 == nslots ? 0 : idx + 1;
     }
-    return false;
+    if (slot == ~0u) return false;
+    fold_lds(t_acc + slot, nslots, ks, vals);
+    return true;
   };
   for (uint64_t i = lo + tid; i < hi; i += blockDim.x) {
     const uint8_t *rec = in + i * ks.rb;

@@ -18,6 +18,7 @@ constexpr uint64_t kClosed = ~0ULL - 1;
 constexpr int kMaxAggs = 8;
 constexpr int kMaxFanBits = 12;
 constexpr uint32_t kMaxFan = 1u << kMaxFanBits;
+constexpr int kLdsMaxFanBits = 13;  // partition-first LDS engine: its partitions need no per-partition tables
 // Per-partition group counters are updated with device-scope atomics on every
 // insert; each gets its own 128-byte line so that partitions never serialize
 // on a shared line at the memory-side atomic units.
@@ -166,9 +167,9 @@ hipError_t launch_part_offsets(hipStream_t s, const uint32_t *totals, uint32_t F
 hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
                                uint32_t mask, uint64_t chunk, unsigned long long *cursors, uint8_t *out);
 hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long long *offsets, uint32_t F,
-                          const KSpec &ks, uint32_t slot_shift, uint32_t nslots, uint32_t cap, uint32_t lds_bytes,
-                          uint32_t stage_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys, const OutCols &out_cols,
-                          uint64_t out_cap);
+                          const KSpec &ks, uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots, uint32_t cap,
+                          uint32_t lds_bytes, uint32_t stage_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys,
+                          const OutCols &out_cols, uint64_t out_cap);
 hipError_t launch_merge_rows(hipStream_t s, const uint64_t *keys, const OutCols &cols, uint64_t n, const KSpec &ks,
                              const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint64_t *arena, Ctrl *ctrl,
                              KSpill spill);

@@ -17,20 +17,33 @@
 
 namespace aggx {
 
+constexpr uint32_t kPartBlock = 1024;  // threads per block of the count and scatter kernels
+constexpr int kLdsUnroll = 4;          // records per thread read together by k_lds_agg
+
 __device__ __forceinline__ uint32_t digit_of(uint64_t key, uint32_t shift, uint32_t mask) {
   return mask ? (uint32_t)(fmix64(key ^ kSeed0) >> shift) & mask : 0u;
 }
 
 // Pass 1: records per partition.  Each block takes a contiguous chunk, counts
-// digits in LDS and adds its counts to the per-partition totals.
-__global__ void __launch_bounds__(256) k_part_count(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
-                                                    uint32_t shift, uint32_t mask, uint64_t chunk, uint32_t *totals) {
+// digits in LDS and adds its counts to the per-partition totals.  Each thread
+// reads four keys before it counts them, so that their loads are in flight
+// together (the chunks are long and the blocks few).
+__global__ void __launch_bounds__(kPartBlock) k_part_count(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
+                                                           uint32_t shift, uint32_t mask, uint64_t chunk,
+                                                           uint32_t *totals) {
   extern __shared__ uint32_t lh[];
   for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) lh[b] = 0;
   __syncthreads();
-  const uint64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
-    atomicAdd(&lh[digit_of(read_key(in + i * ks.rb, ks), shift, mask)], 1u);
+  const uint64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n, B = blockDim.x;
+  uint64_t i = lo + threadIdx.x;
+  for (; i + 3 * B < hi; i += 4 * B) {
+    uint64_t k[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) k[u] = read_key(in + (i + u * B) * ks.rb, ks);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) atomicAdd(&lh[digit_of(k[u], shift, mask)], 1u);
+  }
+  for (; i < hi; i += B) atomicAdd(&lh[digit_of(read_key(in + i * ks.rb, ks), shift, mask)], 1u);
   __syncthreads();
   for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x)
     if (lh[b]) __hip_atomic_fetch_add(totals + (uint64_t)b * kCntStride, lh[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -59,16 +72,42 @@ __global__ void __launch_bounds__(256) k_part_offsets(const uint32_t *totals, ui
 // Pass 2: scatter.  Each block re-reads its chunk, reserves one contiguous
 // range per partition with one atomic, and writes its records there; a
 // block's records of one partition are therefore contiguous in the output.
-__global__ void __launch_bounds__(256) k_part_scatter(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
-                                                      uint32_t shift, uint32_t mask, uint64_t chunk,
-                                                      unsigned long long *cursors, uint8_t *out) {
+// Four keys per thread are read before their records are placed.
+// Write one record to its partition.  The records land at scattered places, so
+// each is written with as few stores as its alignment allows (`vec` bytes each:
+// 16, 8 or 4; the destination's alignment was checked by the launch).
+__device__ __forceinline__ void scatter_one(const uint8_t *rec, uint32_t d, uint32_t rb, uint32_t vec, uint32_t *lc,
+                                            const unsigned long long *lbase, uint8_t *out) {
+  const uint32_t r = atomicAdd(&lc[d], 1u);
+  uint8_t *dst = out + (lbase[d] + r) * rb;
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(rec);
+  if (vec == 16) {
+    for (uint32_t w = 0; w < rb / 16; ++w)
+      reinterpret_cast<uint4 *>(dst)[w] = make_uint4(src[4 * w], src[4 * w + 1], src[4 * w + 2], src[4 * w + 3]);
+  } else if (vec == 8) {
+    for (uint32_t w = 0; w < rb / 8; ++w) reinterpret_cast<uint2 *>(dst)[w] = make_uint2(src[2 * w], src[2 * w + 1]);
+  } else {
+    for (uint32_t w = 0; w < rb / 4; ++w) reinterpret_cast<uint32_t *>(dst)[w] = src[w];
+  }
+}
+
+__global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
+                                                             uint32_t shift, uint32_t mask, uint64_t chunk,
+                                                             unsigned long long *cursors, uint8_t *out, uint32_t vec) {
   extern __shared__ uint32_t lc[];  // mask+1 counts, then mask+1 64-bit bases
   unsigned long long *lbase = reinterpret_cast<unsigned long long *>(lc + ((mask + 2) & ~1u));
   for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) lc[b] = 0;
   __syncthreads();
-  const uint64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
-    atomicAdd(&lc[digit_of(read_key(in + i * ks.rb, ks), shift, mask)], 1u);
+  const uint64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n, B = blockDim.x;
+  uint64_t i = lo + threadIdx.x;
+  for (; i + 3 * B < hi; i += 4 * B) {
+    uint64_t k[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) k[u] = read_key(in + (i + u * B) * ks.rb, ks);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) atomicAdd(&lc[digit_of(k[u], shift, mask)], 1u);
+  }
+  for (; i < hi; i += B) atomicAdd(&lc[digit_of(read_key(in + i * ks.rb, ks), shift, mask)], 1u);
   __syncthreads();
   for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) {
     if (lc[b])
@@ -77,14 +116,17 @@ __global__ void __launch_bounds__(256) k_part_scatter(const uint8_t *__restrict_
     lc[b] = 0;
   }
   __syncthreads();
-  const uint32_t words = ks.rb / 4;
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+  i = lo + threadIdx.x;
+  for (; i + 3 * B < hi; i += 4 * B) {
+    uint32_t d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) d[u] = digit_of(read_key(in + (i + u * B) * ks.rb, ks), shift, mask);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) scatter_one(in + (i + u * B) * ks.rb, d[u], ks.rb, vec, lc, lbase, out);
+  }
+  for (; i < hi; i += B) {
     const uint8_t *rec = in + i * ks.rb;
-    const uint32_t d = digit_of(read_key(rec, ks), shift, mask);
-    const uint32_t r = atomicAdd(&lc[d], 1u);
-    uint32_t *dst = reinterpret_cast<uint32_t *>(out + (lbase[d] + r) * ks.rb);
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(rec);
-    for (uint32_t w = 0; w < words; ++w) dst[w] = src[w];
+    scatter_one(rec, digit_of(read_key(rec, ks), shift, mask), ks.rb, vec, lc, lbase, out);
   }
 }
 
@@ -94,90 +136,109 @@ __global__ void __launch_bounds__(256) k_part_scatter(const uint8_t *__restrict_
 // inserted; once the table is full, new keys close the empty slot they reach
 // and their records are spilled raw, so a key is either in the table for all
 // of its records or spilled for all.  Finished groups are written as rows.
-__global__ void __launch_bounds__(512) k_lds_agg(const uint8_t *__restrict__ buf,
-                                                 const unsigned long long *__restrict__ offsets, KSpec ks,
-                                                 uint32_t slot_shift, uint32_t nslots, uint32_t cap, Ctrl *ctrl,
-                                                 KSpill spill, uint32_t stage_cap, uint64_t *out_keys,
-                                                 OutCols out_cols, uint64_t out_cap) {
-  extern __shared__ uint4 lds4[];
-  __shared__ uint32_t s_n, s_groups;
-  __shared__ unsigned long long s_base;
-  __shared__ uint32_t scratch[32];
-  uint64_t *t_key = reinterpret_cast<uint64_t *>(lds4);
+//
+// When a partition holds more groups than one table, the workgroup sweeps its
+// records 2^sweep_bits times: sweep s takes the keys whose next sweep_bits
+// hash bits (below the partition digit) equal s, in a fresh table, and writes
+// their rows before the next sweep.  Each sweep re-reads the partition; that
+// costs less than a second partition pass over the whole batch.  The table's
+// slot index uses the hash bits below both digits (slot_shift).
+// One sweep of k_lds_agg over the partition's records [lo, hi).
+__device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, uint64_t hi, const KSpec &ks,
+                                              uint32_t slot_shift, uint32_t sweep_bits, uint32_t sweep,
+                                              uint32_t nslots, uint32_t cap, Ctrl *ctrl, const KSpill &spill,
+                                              uint32_t stage_cap, uint64_t *out_keys, const OutCols &out_cols,
+                                              uint64_t out_cap, uint64_t *t_key, uint8_t *stage, uint32_t *s_n,
+                                              uint32_t *s_groups, unsigned long long *s_base, uint32_t *scratch) {
   uint64_t *t_acc = t_key + nslots;
-  uint8_t *stage = reinterpret_cast<uint8_t *>(t_acc + (uint64_t)ks.na * nslots);
   const uint32_t tid = threadIdx.x, rb = ks.rb;
+  const uint32_t part_bits = slot_shift - sweep_bits;
   for (uint32_t e = tid; e < nslots; e += blockDim.x) {
     t_key[e] = kEmpty;
     for (uint32_t a = 0; a < ks.na; ++a) t_acc[(uint64_t)a * nslots + e] = identity_of(ks.agg[a]);
   }
-  if (tid == 0) {
-    s_n = 0;
-    s_groups = 0;
-  }
+  if (tid == 0) *s_groups = 0;
   __syncthreads();
-  const uint64_t lo = offsets[blockIdx.x], hi = offsets[blockIdx.x + 1];
-  for (uint64_t t0 = lo; t0 < hi; t0 += blockDim.x) {
-    const uint64_t i = t0 + tid;
-    const bool valid = i < hi;
-    const uint8_t *rec = buf + (valid ? i : lo) * rb;
-    bool to_spill = false;
-    uint64_t key = 0;
-    if (valid) {
-      uint64_t vals[kMaxAggs];
-      key = read_key(rec, ks);
-      in_vals<0>(rec, ks, vals);
-      if (key >= kClosed) {
+  const uint64_t B = blockDim.x;
+  for (uint64_t t0 = lo; t0 < hi; t0 += kLdsUnroll * B) {
+    // the tile's records are read before any is probed, so that their loads are in flight together
+    uint64_t keys[kLdsUnroll], vals[kLdsUnroll][kMaxAggs];
+#pragma unroll
+    for (int u = 0; u < kLdsUnroll; ++u) {
+      const uint64_t i = t0 + u * B + tid;
+      const uint8_t *rec = buf + (i < hi ? i : lo) * rb;
+      keys[u] = read_key(rec, ks);
+      in_vals<0>(rec, ks, vals[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kLdsUnroll; ++u) {
+      const uint64_t i = t0 + u * B + tid;
+      const uint64_t key = keys[u];
+      const uint64_t h0 = fmix64(key ^ kSeed0);
+      // this sweep's records; the two reserved key values belong to the first sweep
+      const bool mine = i < hi && (key >= kClosed ? sweep == 0
+                                                  : !sweep_bits || (uint32_t)((h0 << part_bits) >> (64 - sweep_bits)) == sweep);
+      bool to_spill = false;
+      if (mine && key >= kClosed) {
         const int sg = key == kEmpty ? 0 : 1;
-        fold_global(reinterpret_cast<uint64_t *>(ctrl->side[sg]), ks, vals);
+        fold_global(reinterpret_cast<uint64_t *>(ctrl->side[sg]), ks, vals[u]);
         __hip_atomic_fetch_add(&ctrl->side_n[sg], 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        uint32_t idx = (uint32_t)mulhi64(fmix64(key ^ kSeed0) << slot_shift, nslots);
-        bool done = false;
-        for (uint32_t t = 0; t < nslots; ++t) {
-          unsigned long long sk = t_key[idx];
-          if (sk == kEmpty) {
-            const bool full = s_groups >= cap;
-            const unsigned long long desired = full ? kClosed : key;
-            sk = atomicCAS(reinterpret_cast<unsigned long long *>(t_key + idx), (unsigned long long)kEmpty, desired);
+      } else if (mine) {
+        // linear probing over groups of four slots, whose keys come in two 16-byte reads;
+        // the fold comes after the loop, once per wave, whatever slot each lane ended on
+        const uint32_t ng = nslots / 4;
+        uint32_t g = (uint32_t)mulhi64(h0 << slot_shift, ng);
+        uint32_t slot = ~0u;
+        bool stop = false;
+        for (uint32_t t = 0; t < ng && !stop; ++t) {
+          const ulonglong2 *gk = reinterpret_cast<const ulonglong2 *>(t_key + 4 * g);
+          const ulonglong2 k01 = gk[0], k23 = gk[1];
+          const unsigned long long kv[4] = {k01.x, k01.y, k23.x, k23.y};
+#pragma unroll
+          for (uint32_t j = 0; j < 4; ++j) {
+            if (stop) break;
+            const uint32_t idx = 4 * g + j;
+            unsigned long long sk = kv[j];
             if (sk == kEmpty) {
-              if (!full) atomicAdd(&s_groups, 1u);
-              sk = desired;
+              const bool full = *s_groups >= cap;
+              const unsigned long long desired = full ? kClosed : key;
+              sk = atomicCAS(reinterpret_cast<unsigned long long *>(t_key + idx), (unsigned long long)kEmpty, desired);
+              if (sk == kEmpty) {
+                if (!full) atomicAdd(s_groups, 1u);
+                sk = desired;
+              }
             }
+            if (sk == key) slot = idx;
+            stop = sk == key || sk == kClosed;
           }
-          if (sk == key) {
-            fold_lds(t_acc + idx, nslots, ks, vals);
-            done = true;
-            break;
-          }
-          if (sk == kClosed) break;
-          idx = idx + 1 == nslots ? 0 : idx + 1;
+          g = g + 1 == ng ? 0 : g + 1;
         }
-        to_spill = !done;
+        if (slot != ~0u) fold_lds(t_acc + slot, nslots, ks, vals[u]);
+        to_spill = slot == ~0u;
+      }
+      if (to_spill) {
+        const uint32_t pos = atomicAdd(s_n, 1u);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(stage + pos * rb);
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(buf + i * rb);
+        for (uint32_t w = 0; w < rb / 4; ++w) dst[w] = src[w];
+        hll_add(spill.hll, key);
+      }
+      __syncthreads();
+      const uint32_t staged = *s_n;
+      if (staged + B > stage_cap || (staged && t0 + (u + 1) * B >= hi)) {
+        if (tid == 0)
+          *s_base = __hip_atomic_fetch_add(&ctrl->raw_ctr, (unsigned long long)staged, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        block_copy(reinterpret_cast<uint32_t *>(spill.raw + *s_base * rb), reinterpret_cast<const uint32_t *>(stage),
+                   staged * rb);
+        __syncthreads();
+        if (tid == 0) *s_n = 0;
+        __syncthreads();
       }
     }
-    if (to_spill) {
-      const uint32_t pos = atomicAdd(&s_n, 1u);
-      uint32_t *dst = reinterpret_cast<uint32_t *>(stage + pos * rb);
-      const uint32_t *src = reinterpret_cast<const uint32_t *>(rec);
-      for (uint32_t w = 0; w < rb / 4; ++w) dst[w] = src[w];
-      hll_add(spill.hll, key);
-    }
-    __syncthreads();
-    const uint32_t staged = s_n;
-    if (staged + blockDim.x > stage_cap || (staged && t0 + blockDim.x >= hi)) {
-      if (tid == 0)
-        s_base = __hip_atomic_fetch_add(&ctrl->raw_ctr, (unsigned long long)staged, __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-      __syncthreads();
-      block_copy(reinterpret_cast<uint32_t *>(spill.raw + s_base * rb), reinterpret_cast<const uint32_t *>(stage),
-                 staged * rb);
-      __syncthreads();
-      if (tid == 0) s_n = 0;
-      __syncthreads();
-    }
   }
-  // write the partition's groups as result rows
+  // write the sweep's groups as result rows
   const uint32_t per = (nslots + blockDim.x - 1) / blockDim.x;
   uint32_t occ = 0, c = 0;
   for (uint32_t j = 0; j < per; ++j) {
@@ -189,20 +250,41 @@ __global__ void __launch_bounds__(512) k_lds_agg(const uint8_t *__restrict__ buf
   }
   uint32_t total;
   const uint32_t pre = block_exclusive_scan(c, &total, scratch);
-  if (total == 0) return;
-  if (tid == 0)
-    s_base = __hip_atomic_fetch_add(&ctrl->rows, (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  uint64_t r = s_base + pre;
-  for (uint32_t j = 0; j < per; ++j) {
-    if (!(occ >> j & 1u)) continue;
-    const uint32_t e = j * blockDim.x + tid;
-    if (r < out_cap) {
-      out_keys[r] = t_key[e];
-      for (uint32_t a = 0; a < ks.na; ++a) out_cols.c[a][r] = (int64_t)t_acc[(uint64_t)a * nslots + e];
+  if (total) {
+    if (tid == 0)
+      *s_base = __hip_atomic_fetch_add(&ctrl->rows, (unsigned long long)total, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    uint64_t r = *s_base + pre;
+    for (uint32_t j = 0; j < per; ++j) {
+      if (!(occ >> j & 1u)) continue;
+      const uint32_t e = j * blockDim.x + tid;
+      if (r < out_cap) {
+        out_keys[r] = t_key[e];
+        for (uint32_t a = 0; a < ks.na; ++a) out_cols.c[a][r] = (int64_t)t_acc[(uint64_t)a * nslots + e];
+      }
+      ++r;
     }
-    ++r;
   }
+  __syncthreads();  // every thread has read the table before it is cleared again
+}
+
+__global__ void __launch_bounds__(512) k_lds_agg(const uint8_t *__restrict__ buf,
+                                                 const unsigned long long *__restrict__ offsets, KSpec ks,
+                                                 uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots,
+                                                 uint32_t cap, Ctrl *ctrl, KSpill spill, uint32_t stage_cap,
+                                                 uint64_t *out_keys, OutCols out_cols, uint64_t out_cap) {
+  extern __shared__ uint4 lds4[];
+  __shared__ uint32_t s_n, s_groups;
+  __shared__ unsigned long long s_base;
+  __shared__ uint32_t scratch[32];
+  uint64_t *t_key = reinterpret_cast<uint64_t *>(lds4);
+  uint8_t *stage = reinterpret_cast<uint8_t *>(t_key + (uint64_t)(1 + ks.na) * nslots);
+  const uint64_t lo = offsets[blockIdx.x], hi = offsets[blockIdx.x + 1];
+  if (threadIdx.x == 0) s_n = 0;
+  for (uint32_t sweep = 0; sweep < (1u << sweep_bits); ++sweep)
+    lds_agg_sweep(buf, lo, hi, ks, slot_shift, sweep_bits, sweep, nslots, cap, ctrl, spill, stage_cap, out_keys,
+                  out_cols, out_cap, t_key, stage, &s_n, &s_groups, &s_base, scratch);
 }
 
 // Rows already written to a result (SoA) folded into HBM tables as grouping
@@ -242,8 +324,8 @@ hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const
                              uint32_t mask, uint64_t chunk, uint32_t *totals) {
   if (n == 0) return hipSuccess;
   const uint64_t blocks = (n + chunk - 1) / chunk;
-  hipLaunchKernelGGL(k_part_count, dim3((uint32_t)blocks), dim3(256), 4ull * (mask + 1), s, in, n, ks, shift, mask,
-                     chunk, totals);
+  hipLaunchKernelGGL(k_part_count, dim3((uint32_t)blocks), dim3(kPartBlock), 4ull * (mask + 1), s, in, n, ks, shift,
+                     mask, chunk, totals);
   return hipGetLastError();
 }
 
@@ -253,13 +335,37 @@ hipError_t launch_part_offsets(hipStream_t s, const uint32_t *totals, uint32_t F
   return hipGetLastError();
 }
 
+// The scatter's LDS grows with the fan-out (12 bytes per partition); above
+// 64 KB the kernel must be allowed more, once per device, under a lock.
+static bool scatter_lds_allowed(size_t lds) {
+  static std::mutex mu;
+  static std::map<int, size_t> allowed;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(mu);
+  size_t &a = allowed[dev];
+  if (a < 65536) a = 65536;
+  if (lds <= a) return true;
+  if (lds > 160 * 1024 - 1024 ||
+      hipFuncSetAttribute(reinterpret_cast<const void *>(k_part_scatter), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  a = lds;
+  return true;
+}
+
 hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
                                uint32_t mask, uint64_t chunk, unsigned long long *cursors, uint8_t *out) {
   if (n == 0) return hipSuccess;
   const uint64_t blocks = (n + chunk - 1) / chunk;
   const size_t lds = 4ull * ((mask + 2) & ~1u) + 8ull * (mask + 1);
-  hipLaunchKernelGGL(k_part_scatter, dim3((uint32_t)blocks), dim3(256), lds, s, in, n, ks, shift, mask, chunk, cursors,
-                     out);
+  if (!scatter_lds_allowed(lds)) return hipErrorInvalidValue;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(out);
+  const uint32_t vec = ks.rb % 16 == 0 && a % 16 == 0 ? 16 : ks.rb % 8 == 0 && a % 8 == 0 ? 8 : 4;
+  hipLaunchKernelGGL(k_part_scatter, dim3((uint32_t)blocks), dim3(kPartBlock), lds, s, in, n, ks, shift, mask, chunk,
+                     cursors, out, vec);
   return hipGetLastError();
 }
 
@@ -285,12 +391,13 @@ uint32_t lds_agg_max_bytes() {
 }
 
 hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long long *offsets, uint32_t F,
-                          const KSpec &ks, uint32_t slot_shift, uint32_t nslots, uint32_t cap, uint32_t lds_bytes,
-                          uint32_t stage_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys, const OutCols &out_cols,
-                          uint64_t out_cap) {
+                          const KSpec &ks, uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots, uint32_t cap,
+                          uint32_t lds_bytes, uint32_t stage_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys,
+                          const OutCols &out_cols, uint64_t out_cap) {
   if (F == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lds_agg, dim3(F), dim3(512), lds_bytes, s, buf, offsets, ks, slot_shift, nslots, cap, ctrl,
-                     spill, stage_bytes / ks.rb, out_keys, out_cols, out_cap);
+  if (sweep_bits > slot_shift || sweep_bits > 8 || nslots % 4 || nslots == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lds_agg, dim3(F), dim3(512), lds_bytes, s, buf, offsets, ks, slot_shift, sweep_bits, nslots,
+                     cap, ctrl, spill, stage_bytes / ks.rb, out_keys, out_cols, out_cap);
   return hipGetLastError();
 }
 

@@ -679,12 +679,16 @@ agg_status append_side_rows(agg_handle *h) {
 
 // ---- partition-first engine with LDS tables --------------------------------
 struct LdsPlan {
-  uint32_t b = 0, F = 1, nslots = 0, cap = 0, lds_bytes = 0, stage_bytes = 0;
+  uint32_t b = 0, F = 1, sbits = 0, nslots = 0, cap = 0, lds_bytes = 0, stage_bytes = 0;
   uint64_t buf_bytes = 0, need = 0;
 };
 
 constexpr uint32_t kLdsBlock = 512;
 constexpr double kLdsLoad = 0.75;
+constexpr uint32_t kLdsMaxSweepBits = 2;          // up to four sweeps of a partition
+// largest batch (bytes) for the LDS engine: its worst-case spill, reserved in
+// pinned host memory before the launch, is the whole batch
+constexpr uint64_t kLdsMaxInput = 4ull << 30;
 
 // Records per block of the partition count/scatter kernels: about 256 blocks
 // per launch.  Each block adds its LDS histogram to the global per-partition
@@ -695,24 +699,34 @@ uint64_t part_chunk(uint64_t n) { return std::max<uint64_t>(1024, (n + 255) / 25
 
 // Can the batch be aggregated partition by partition in LDS?  Each partition's
 // expected groups (plus four standard deviations) must fit one workgroup's LDS
-// table, with at most 2^12 partitions; the working budget must hold the
-// partitioned copy of the batch and the partition counters.
+// table, with at most 2^13 partitions, or else the groups of one sweep of it
+// (at most four sweeps); the working budget must hold the partitioned copy of
+// the batch and the partition counters.
 bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
   const uint32_t rb = h->ks.rb;
   lp->lds_bytes = lds_agg_max_bytes();
   lp->stage_bytes = 2 * kLdsBlock * rb;
   if (lp->lds_bytes < lp->stage_bytes + 256 * h->W8) return false;
-  lp->nslots = (lp->lds_bytes - lp->stage_bytes) / h->W8;
+  lp->nslots = (uint32_t)((lp->lds_bytes - lp->stage_bytes) / h->W8) & ~3u;  // whole groups of four slots
   lp->cap = (uint32_t)(lp->nslots * kLdsLoad);
-  // enough partitions to give every compute unit work, but at least ~256 records each
-  uint32_t b = 0;
-  while (b < 8 && ((uint64_t)kLdsBlock << (b + 1)) <= n) ++b;
-  for (;; ++b) {
-    if (b > (uint32_t)kMaxFanBits) return false;
-    const double g = G / (double)(1u << b);
-    if (g + 4.0 * std::sqrt(g) + 16.0 <= lp->cap) break;
+  // enough partitions to give every compute unit work, but at least ~256 records
+  // each; an explicit fan-out in the spec is taken as given
+  uint32_t b = h->spec.fanout_bits;
+  const uint32_t bmax = h->spec.fanout_bits ? h->spec.fanout_bits : (uint32_t)kLdsMaxFanBits;
+  while (!h->spec.fanout_bits && b < 8 && ((uint64_t)kLdsBlock << (b + 1)) <= n) ++b;
+  const auto fits = [&](uint32_t bits) {
+    const double g = G / (double)(1ull << bits);
+    return g + 4.0 * std::sqrt(g) + 16.0 <= lp->cap;
+  };
+  while (b <= bmax && !fits(b)) ++b;
+  uint32_t sbits = 0;
+  if (b > bmax) {
+    b = bmax;
+    while (sbits <= kLdsMaxSweepBits && !fits(b + sbits)) ++sbits;
+    if (sbits > kLdsMaxSweepBits) return false;
   }
   lp->b = b;
+  lp->sbits = sbits;
   lp->F = 1u << b;
   lp->buf_bytes = round_up(n * rb, 256);
   lp->need = lp->buf_bytes + 2ull * lp->F * 128 + 8ull * (lp->F + 1);
@@ -758,15 +772,16 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   if (!h->next.reserve(n * h->ks.rb, &dst)) return AGG_E_NOMEM;
   // rows per partition: at most its slot count (the group limit is checked with
   // a plain LDS read, so concurrent inserts may pass it by up to one block)
-  agg_status s = ensure_result_cap(h, h->r_rows + std::min<uint64_t>(n, (uint64_t)lp.F * lp.nslots) + 1);
+  agg_status s = ensure_result_cap(h, h->r_rows + std::min<uint64_t>(n, ((uint64_t)lp.F << lp.sbits) * lp.nslots) + 1);
   if (s) return s;
   HCK(h, launch_u64_set(h->stream, &h->d_ctrl->raw_ctr, 1, 0));
   HCK(h, launch_u64_set(h->stream, &h->d_ctrl->rows, 1, 0));
   OutCols oc{};
   for (uint32_t a = 0; a < h->spec.n_aggs; ++a) oc.c[a] = h->r_cols[a] + h->r_rows;
   HCK(h, hipEventRecord(h->ev0, h->stream));
-  HCK(h, launch_lds_agg(h->stream, buf, offsets, lp.F, h->ks, lp.b, lp.nslots, lp.cap, lp.lds_bytes, lp.stage_bytes,
-                        h->d_ctrl, spill_target(h, dst, nullptr), h->r_keys + h->r_rows, oc, h->r_cap - h->r_rows));
+  HCK(h, launch_lds_agg(h->stream, buf, offsets, lp.F, h->ks, lp.b + lp.sbits, lp.sbits, lp.nslots, lp.cap,
+                        lp.lds_bytes, lp.stage_bytes, h->d_ctrl, spill_target(h, dst, nullptr), h->r_keys + h->r_rows,
+                        oc, h->r_cap - h->r_rows));
   HCK(h, hipEventRecord(h->ev1, h->stream));
   s = read_ctrl(h);
   if (s) return s;
@@ -780,7 +795,8 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   if (h->h_ctrl->rows > h->r_cap - h->r_rows) return AGG_E_INTERNAL;
   h->r_rows += h->h_ctrl->rows;
   h->st.partitions = lp.F;
-  h->used_bits = std::max(h->used_bits, lp.b);
+  h->st.lds_sweeps = 1u << lp.sbits;
+  h->used_bits = std::max(h->used_bits, lp.b + lp.sbits);
   return AGG_OK;
 }
 
@@ -1262,7 +1278,7 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     LdsPlan lp;
     const double G = h->spec.est_groups ? (double)h->spec.est_groups : (double)n;
     if ((h->spec.engine == AGG_ENGINE_AUTO || h->spec.engine == AGG_ENGINE_LDS) &&
-        (h->spec.engine == AGG_ENGINE_LDS || !h->hot_key) && n * h->ks.rb <= (1ull << 30) &&
+        (h->spec.engine == AGG_ENGINE_LDS || !h->hot_key) && n * h->ks.rb <= kLdsMaxInput &&
         lds_plan(h, n, G, &lp)) {
       h->engine = 2;
       h->st.engine = 2;

@@ -1,0 +1,84 @@
+"""GPU parity of the LDS engine's sweeps: a partition with more groups than one
+LDS table is aggregated in 2-4 sweeps over its records, each sweep taking the
+keys of one value of the hash bits below the partition digit.
+
+Every case compares all rows with the CPU oracle: sweeps forced by a small
+explicit fan-out (R16 and composite R24 keys), the two reserved key values
+(folded by the first sweep only), overflow of a sweep's table (spill and
+recursion), more batches after a swept first batch, and the automatic choice
+of 2^13 partitions for a batch whose groups need more than 2^12.
+"""
+import numpy as np
+import pytest
+
+import datagen
+from datagen import workloads
+from tests.gpu_util import check_against_oracle, lib_spec_args, run_lib
+from tests.test_oracle import SPEC_R16
+from tests.wl import oracle_spec
+
+pytestmark = pytest.mark.gpu
+MIB = 1 << 20
+
+
+@pytest.mark.parametrize("n,d,bits,sweeps,parts", [(1_500_000, 150_000, 4, 4, 16), (1_000_000, 60_000, 4, 2, 16),
+                                                   (777_777, 40_000, 2, 4, 4), (3000, 2999, 0, 1, 4)])
+def test_sweeps_exact(n, d, bits, sweeps, parts):
+    wl = workloads.uniform_spill().scaled(n, d)
+    rec = wl.generate()
+    print(f"case: sweeps n={n} d={d} bits={bits}", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=d, engine="lds", fanout_bits=bits)
+    check_against_oracle(rec, oracle_spec(wl), k, c, f"sweeps {n} {d}")
+    assert st["engine"] == 2 and st["levels"] == 1 and st["records_spilled"] == 0
+    assert st["lds_sweeps"] == sweeps and st["partitions"] == parts
+
+
+def test_sweeps_composite_keys():
+    wl = workloads.zipf_composite().scaled(1_200_000, 100_000)
+    rec = wl.generate()
+    print("case: sweeps R24", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d, engine="lds", fanout_bits=4)
+    check_against_oracle(rec, oracle_spec(wl), k, c, "sweeps R24")
+    assert st["engine"] == 2 and st["lds_sweeps"] > 1
+
+
+def test_sweeps_reserved_keys_counted_once():
+    rec = datagen.r16(401, 900_000, 70_000, lo=-10**6, hi=10**6).copy()
+    rec["key"][::777] = np.uint64((1 << 64) - 1)
+    rec["key"][5::1009] = np.uint64((1 << 64) - 2)
+    print("case: sweeps + reserved keys", flush=True)
+    k, c, st = run_lib(rec, 16, [(0, "u64")], workloads.AGGS_R16_ALL, est_groups=70_000, engine="lds",
+                       fanout_bits=3)
+    check_against_oracle(rec, SPEC_R16, k, c, "sweeps reserved keys")
+    assert st["engine"] == 2 and st["lds_sweeps"] == 4
+
+
+def test_sweep_overflow_spills_and_recurses():
+    """An estimate far below the true count: each sweep's table fills, new keys spill
+    raw and are aggregated at the next level."""
+    wl = workloads.uniform_spill().scaled(2_000_000, 400_000)
+    rec = wl.generate()
+    print("case: sweeps overflow", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=100_000, engine="lds", fanout_bits=4)
+    check_against_oracle(rec, oracle_spec(wl), k, c, "sweeps overflow")
+    assert st["engine"] == 2 and st["lds_sweeps"] == 4 and st["levels"] >= 2 and st["records_spilled"] > 0
+
+
+def test_sweeps_then_more_batches():
+    wl = workloads.uniform_spill().scaled(1_600_000, 120_000)
+    rec = wl.generate()
+    print("case: sweeps + batches", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d, engine="lds", fanout_bits=4, batches=3)
+    check_against_oracle(rec, oracle_spec(wl), k, c, "sweeps batches")
+    assert st["engine"] == 2 and st["lds_sweeps"] == 4
+
+
+def test_automatic_fanout_beyond_table_engine_limit():
+    """12M groups need more than 2^12 one-table partitions: the automatic choice keeps the
+    LDS engine with 2^13 partitions, one sweep each (unlimited budget, no hot key)."""
+    wl = workloads.uniform_spill().scaled(24_000_000, 12_000_000)
+    rec = wl.generate()
+    print("case: automatic 24M/12M", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=0, est_groups=wl.d)
+    assert st["engine"] == 2 and st["lds_sweeps"] == 1 and st["partitions"] == 8192
+    check_against_oracle(rec, oracle_spec(wl), k, c, "automatic 2^13 partitions")
