@@ -19,6 +19,8 @@ constexpr int kMaxAggs = 8;
 constexpr int kMaxFanBits = 12;
 constexpr uint32_t kMaxFan = 1u << kMaxFanBits;
 constexpr int kLdsMaxFanBits = 13;  // partition-first LDS engine: its partitions need no per-partition tables
+constexpr uint32_t kLdsBlock = 1024;    // threads per workgroup of the LDS aggregation kernel
+constexpr uint32_t kLdsStageBlocks = 1; // its spill stage holds this many workgroups' worth of records
 // Per-partition group counters are updated with device-scope atomics on every
 // insert; each gets its own 128-byte line so that partitions never serialize
 // on a shared line at the memory-side atomic units.

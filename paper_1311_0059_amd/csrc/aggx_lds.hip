@@ -18,7 +18,7 @@
 namespace aggx {
 
 constexpr uint32_t kPartBlock = 1024;  // threads per block of the count and scatter kernels
-constexpr int kLdsUnroll = 4;          // records per thread read together by k_lds_agg
+constexpr int kLdsUnroll = 2;          // records per thread read together by k_lds_agg
 
 __device__ __forceinline__ uint32_t digit_of(uint64_t key, uint32_t shift, uint32_t mask) {
   return mask ? (uint32_t)(fmix64(key ^ kSeed0) >> shift) & mask : 0u;
@@ -269,7 +269,7 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
   __syncthreads();  // every thread has read the table before it is cleared again
 }
 
-__global__ void __launch_bounds__(512) k_lds_agg(const uint8_t *__restrict__ buf,
+__global__ void __launch_bounds__(kLdsBlock) k_lds_agg(const uint8_t *__restrict__ buf,
                                                  const unsigned long long *__restrict__ offsets, KSpec ks,
                                                  uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots,
                                                  uint32_t cap, Ctrl *ctrl, KSpill spill, uint32_t stage_cap,
@@ -396,8 +396,8 @@ hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long
                           const OutCols &out_cols, uint64_t out_cap) {
   if (F == 0) return hipSuccess;
   if (sweep_bits > slot_shift || sweep_bits > 8 || nslots % 4 || nslots == 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_lds_agg, dim3(F), dim3(512), lds_bytes, s, buf, offsets, ks, slot_shift, sweep_bits, nslots,
-                     cap, ctrl, spill, stage_bytes / ks.rb, out_keys, out_cols, out_cap);
+  hipLaunchKernelGGL(k_lds_agg, dim3(F), dim3(kLdsBlock), lds_bytes, s, buf, offsets, ks, slot_shift, sweep_bits,
+                     nslots, cap, ctrl, spill, stage_bytes / ks.rb, out_keys, out_cols, out_cap);
   return hipGetLastError();
 }
 

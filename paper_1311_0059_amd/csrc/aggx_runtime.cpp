@@ -683,7 +683,6 @@ struct LdsPlan {
   uint64_t buf_bytes = 0, need = 0;
 };
 
-constexpr uint32_t kLdsBlock = 512;
 constexpr double kLdsLoad = 0.75;
 constexpr uint32_t kLdsMaxSweepBits = 2;          // up to four sweeps of a partition
 // largest batch (bytes) for the LDS engine: its worst-case spill, reserved in
@@ -705,7 +704,7 @@ uint64_t part_chunk(uint64_t n) { return std::max<uint64_t>(1024, (n + 255) / 25
 bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
   const uint32_t rb = h->ks.rb;
   lp->lds_bytes = lds_agg_max_bytes();
-  lp->stage_bytes = 2 * kLdsBlock * rb;
+  lp->stage_bytes = kLdsStageBlocks * kLdsBlock * rb;
   if (lp->lds_bytes < lp->stage_bytes + 256 * h->W8) return false;
   lp->nslots = (uint32_t)((lp->lds_bytes - lp->stage_bytes) / h->W8) & ~3u;  // whole groups of four slots
   lp->cap = (uint32_t)(lp->nslots * kLdsLoad);

@@ -22,7 +22,7 @@ MIB = 1 << 20
 
 
 @pytest.mark.parametrize("n,d,bits,sweeps,parts", [(1_500_000, 150_000, 4, 4, 16), (1_000_000, 60_000, 4, 2, 16),
-                                                   (777_777, 40_000, 2, 4, 4), (3000, 2999, 0, 1, 4)])
+                                                   (777_777, 40_000, 2, 4, 4), (3000, 2999, 0, 1, 2)])
 def test_sweeps_exact(n, d, bits, sweeps, parts):
     wl = workloads.uniform_spill().scaled(n, d)
     rec = wl.generate()
