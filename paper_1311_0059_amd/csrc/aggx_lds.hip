@@ -77,9 +77,9 @@ __global__ void __launch_bounds__(256) k_part_offsets(const uint32_t *totals, ui
 // each is written with as few stores as its alignment allows (`vec` bytes each:
 // 16, 8 or 4; the destination's alignment was checked by the launch).
 __device__ __forceinline__ void scatter_one(const uint8_t *rec, uint32_t d, uint32_t rb, uint32_t vec, uint32_t *lc,
-                                            const unsigned long long *lbase, uint8_t *out) {
+                                            const uint32_t *lbase, uint8_t *out) {
   const uint32_t r = atomicAdd(&lc[d], 1u);
-  uint8_t *dst = out + (lbase[d] + r) * rb;
+  uint8_t *dst = out + ((uint64_t)lbase[d] + r) * rb;
   const uint32_t *src = reinterpret_cast<const uint32_t *>(rec);
   if (vec == 16) {
     for (uint32_t w = 0; w < rb / 16; ++w)
@@ -94,8 +94,8 @@ __device__ __forceinline__ void scatter_one(const uint8_t *rec, uint32_t d, uint
 __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
                                                              uint32_t shift, uint32_t mask, uint64_t chunk,
                                                              unsigned long long *cursors, uint8_t *out, uint32_t vec) {
-  extern __shared__ uint32_t lc[];  // mask+1 counts, then mask+1 64-bit bases
-  unsigned long long *lbase = reinterpret_cast<unsigned long long *>(lc + ((mask + 2) & ~1u));
+  extern __shared__ uint32_t lc[];  // mask+1 counts, then mask+1 bases (record indices below 2^32)
+  uint32_t *lbase = lc + mask + 1;
   for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) lc[b] = 0;
   __syncthreads();
   const uint64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n, B = blockDim.x;
@@ -111,8 +111,9 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
   __syncthreads();
   for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) {
     if (lc[b])
-      lbase[b] = __hip_atomic_fetch_add(cursors + (uint64_t)b * (kCntStride / 2), (unsigned long long)lc[b],
-                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      lbase[b] = (uint32_t)__hip_atomic_fetch_add(cursors + (uint64_t)b * (kCntStride / 2),
+                                                  (unsigned long long)lc[b], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
     lc[b] = 0;
   }
   __syncthreads();
@@ -335,7 +336,7 @@ hipError_t launch_part_offsets(hipStream_t s, const uint32_t *totals, uint32_t F
   return hipGetLastError();
 }
 
-// The scatter's LDS grows with the fan-out (12 bytes per partition); above
+// The scatter's LDS grows with the fan-out (8 bytes per partition); above
 // 64 KB the kernel must be allowed more, once per device, under a lock.
 static bool scatter_lds_allowed(size_t lds) {
   static std::mutex mu;
@@ -360,7 +361,8 @@ hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, con
                                uint32_t mask, uint64_t chunk, unsigned long long *cursors, uint8_t *out) {
   if (n == 0) return hipSuccess;
   const uint64_t blocks = (n + chunk - 1) / chunk;
-  const size_t lds = 4ull * ((mask + 2) & ~1u) + 8ull * (mask + 1);
+  if (n >= (1ull << 32)) return hipErrorInvalidValue;  // the LDS bases are 32-bit record indices
+  const size_t lds = 8ull * (mask + 1);
   if (!scatter_lds_allowed(lds)) return hipErrorInvalidValue;
   const uintptr_t a = reinterpret_cast<uintptr_t>(out);
   const uint32_t vec = ks.rb % 16 == 0 && a % 16 == 0 ? 16 : ks.rb % 8 == 0 && a % 8 == 0 ? 8 : 4;
