@@ -20,7 +20,6 @@ constexpr int kMaxFanBits = 12;
 constexpr uint32_t kMaxFan = 1u << kMaxFanBits;
 constexpr int kLdsMaxFanBits = 13;  // partition-first LDS engine: its partitions need no per-partition tables
 constexpr uint32_t kLdsBlock = 1024;    // threads per workgroup of the LDS aggregation kernel
-constexpr uint32_t kLdsStageBlocks = 1; // its spill stage holds this many workgroups' worth of records
 // Per-partition group counters are updated with device-scope atomics on every
 // insert; each gets its own 128-byte line so that partitions never serialize
 // on a shared line at the memory-side atomic units.
@@ -170,8 +169,8 @@ hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, con
                                uint32_t mask, uint64_t chunk, unsigned long long *cursors, uint8_t *out);
 hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long long *offsets, uint32_t F,
                           const KSpec &ks, uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots, uint32_t cap,
-                          uint32_t lds_bytes, uint32_t stage_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys,
-                          const OutCols &out_cols, uint64_t out_cap);
+                          uint32_t lds_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys, const OutCols &out_cols,
+                          uint64_t out_cap);
 hipError_t launch_merge_rows(hipStream_t s, const uint64_t *keys, const OutCols &cols, uint64_t n, const KSpec &ks,
                              const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint64_t *arena, Ctrl *ctrl,
                              KSpill spill);

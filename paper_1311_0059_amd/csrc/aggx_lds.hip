@@ -148,9 +148,9 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
 __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, uint64_t hi, const KSpec &ks,
                                               uint32_t slot_shift, uint32_t sweep_bits, uint32_t sweep,
                                               uint32_t nslots, uint32_t cap, Ctrl *ctrl, const KSpill &spill,
-                                              uint32_t stage_cap, uint64_t *out_keys, const OutCols &out_cols,
-                                              uint64_t out_cap, uint64_t *t_key, uint8_t *stage, uint32_t *s_n,
-                                              uint32_t *s_groups, unsigned long long *s_base, uint32_t *scratch) {
+                                              uint64_t *out_keys, const OutCols &out_cols, uint64_t out_cap,
+                                              uint64_t *t_key, uint32_t *s_groups, unsigned long long *s_base,
+                                              uint32_t *scratch) {
   uint64_t *t_acc = t_key + nslots;
   const uint32_t tid = threadIdx.x, rb = ks.rb;
   const uint32_t part_bits = slot_shift - sweep_bits;
@@ -217,28 +217,11 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
         if (slot != ~0u) fold_lds(t_acc + slot, nslots, ks, vals[u]);
         to_spill = slot == ~0u;
       }
-      if (to_spill) {
-        const uint32_t pos = atomicAdd(s_n, 1u);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(stage + pos * rb);
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(buf + i * rb);
-        for (uint32_t w = 0; w < rb / 4; ++w) dst[w] = src[w];
-        hll_add(spill.hll, key);
-      }
-      __syncthreads();
-      const uint32_t staged = *s_n;
-      if (staged + B > stage_cap || (staged && t0 + (u + 1) * B >= hi)) {
-        if (tid == 0)
-          *s_base = __hip_atomic_fetch_add(&ctrl->raw_ctr, (unsigned long long)staged, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        block_copy(reinterpret_cast<uint32_t *>(spill.raw + *s_base * rb), reinterpret_cast<const uint32_t *>(stage),
-                   staged * rb);
-        __syncthreads();
-        if (tid == 0) *s_n = 0;
-        __syncthreads();
-      }
+      // records of keys that found no room go to the spill run, one reservation per wave
+      spill_append(to_spill, buf + (i < hi ? i : lo) * rb, rb, spill.raw, &ctrl->raw_ctr, spill.hll, key);
     }
   }
+  __syncthreads();
   // write the sweep's groups as result rows
   const uint32_t per = (nslots + blockDim.x - 1) / blockDim.x;
   uint32_t occ = 0, c = 0;
@@ -273,19 +256,17 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
 __global__ void __launch_bounds__(kLdsBlock) k_lds_agg(const uint8_t *__restrict__ buf,
                                                  const unsigned long long *__restrict__ offsets, KSpec ks,
                                                  uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots,
-                                                 uint32_t cap, Ctrl *ctrl, KSpill spill, uint32_t stage_cap,
-                                                 uint64_t *out_keys, OutCols out_cols, uint64_t out_cap) {
+                                                 uint32_t cap, Ctrl *ctrl, KSpill spill, uint64_t *out_keys,
+                                                 OutCols out_cols, uint64_t out_cap) {
   extern __shared__ uint4 lds4[];
-  __shared__ uint32_t s_n, s_groups;
+  __shared__ uint32_t s_groups;
   __shared__ unsigned long long s_base;
   __shared__ uint32_t scratch[32];
   uint64_t *t_key = reinterpret_cast<uint64_t *>(lds4);
-  uint8_t *stage = reinterpret_cast<uint8_t *>(t_key + (uint64_t)(1 + ks.na) * nslots);
   const uint64_t lo = offsets[blockIdx.x], hi = offsets[blockIdx.x + 1];
-  if (threadIdx.x == 0) s_n = 0;
   for (uint32_t sweep = 0; sweep < (1u << sweep_bits); ++sweep)
-    lds_agg_sweep(buf, lo, hi, ks, slot_shift, sweep_bits, sweep, nslots, cap, ctrl, spill, stage_cap, out_keys,
-                  out_cols, out_cap, t_key, stage, &s_n, &s_groups, &s_base, scratch);
+    lds_agg_sweep(buf, lo, hi, ks, slot_shift, sweep_bits, sweep, nslots, cap, ctrl, spill, out_keys, out_cols,
+                  out_cap, t_key, &s_groups, &s_base, scratch);
 }
 
 // Rows already written to a result (SoA) folded into HBM tables as grouping
@@ -394,12 +375,13 @@ uint32_t lds_agg_max_bytes() {
 
 hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long long *offsets, uint32_t F,
                           const KSpec &ks, uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots, uint32_t cap,
-                          uint32_t lds_bytes, uint32_t stage_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys,
-                          const OutCols &out_cols, uint64_t out_cap) {
+                          uint32_t lds_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys, const OutCols &out_cols,
+                          uint64_t out_cap) {
   if (F == 0) return hipSuccess;
-  if (sweep_bits > slot_shift || sweep_bits > 8 || nslots % 4 || nslots == 0) return hipErrorInvalidValue;
+  if (sweep_bits > slot_shift || sweep_bits > 8 || nslots % 4 || nslots == 0 || (1ull + ks.na) * 8 * nslots > lds_bytes)
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_lds_agg, dim3(F), dim3(kLdsBlock), lds_bytes, s, buf, offsets, ks, slot_shift, sweep_bits,
-                     nslots, cap, ctrl, spill, stage_bytes / ks.rb, out_keys, out_cols, out_cap);
+                     nslots, cap, ctrl, spill, out_keys, out_cols, out_cap);
   return hipGetLastError();
 }
 

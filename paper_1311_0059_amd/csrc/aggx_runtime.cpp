@@ -679,7 +679,7 @@ agg_status append_side_rows(agg_handle *h) {
 
 // ---- partition-first engine with LDS tables --------------------------------
 struct LdsPlan {
-  uint32_t b = 0, F = 1, sbits = 0, nslots = 0, cap = 0, lds_bytes = 0, stage_bytes = 0;
+  uint32_t b = 0, F = 1, sbits = 0, nslots = 0, cap = 0, lds_bytes = 0;
   uint64_t buf_bytes = 0, need = 0;
 };
 
@@ -704,9 +704,8 @@ uint64_t part_chunk(uint64_t n) { return std::max<uint64_t>(1024, (n + 255) / 25
 bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
   const uint32_t rb = h->ks.rb;
   lp->lds_bytes = lds_agg_max_bytes();
-  lp->stage_bytes = kLdsStageBlocks * kLdsBlock * rb;
-  if (lp->lds_bytes < lp->stage_bytes + 256 * h->W8) return false;
-  lp->nslots = (uint32_t)((lp->lds_bytes - lp->stage_bytes) / h->W8) & ~3u;  // whole groups of four slots
+  if (lp->lds_bytes < 256 * h->W8) return false;
+  lp->nslots = (uint32_t)(lp->lds_bytes / h->W8) & ~3u;  // whole groups of four slots
   lp->cap = (uint32_t)(lp->nslots * kLdsLoad);
   // enough partitions to give every compute unit work, but at least ~256 records
   // each; an explicit fan-out in the spec is taken as given
@@ -779,8 +778,8 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   for (uint32_t a = 0; a < h->spec.n_aggs; ++a) oc.c[a] = h->r_cols[a] + h->r_rows;
   HCK(h, hipEventRecord(h->ev0, h->stream));
   HCK(h, launch_lds_agg(h->stream, buf, offsets, lp.F, h->ks, lp.b + lp.sbits, lp.sbits, lp.nslots, lp.cap,
-                        lp.lds_bytes, lp.stage_bytes, h->d_ctrl, spill_target(h, dst, nullptr), h->r_keys + h->r_rows,
-                        oc, h->r_cap - h->r_rows));
+                        lp.lds_bytes, h->d_ctrl, spill_target(h, dst, nullptr), h->r_keys + h->r_rows, oc,
+                        h->r_cap - h->r_rows));
   HCK(h, hipEventRecord(h->ev1, h->stream));
   s = read_ctrl(h);
   if (s) return s;
