@@ -246,6 +246,7 @@ def main():
             "partition_ms": round(agg["partition_ms"] / args.steps, 3),
             "sorted_ms": round(agg["sorted_ms"] / args.steps, 3),
             "lds_sweeps": agg["lds_sweeps"] // args.steps,
+            "lds_passes": agg["lds_passes"] // args.steps,
             "engine": agg["engine"] // args.steps,
             "preagg": agg["preagg"] // args.steps,
             "pool_high_water": agg["pool_high_water"] // args.steps,

@@ -165,7 +165,8 @@ typedef struct agg_stats {
                                    is counted in the update_* figures */
   double sorted_ms;             /* sorted-run engine: its check, scan and run-reduction kernels */
   uint32_t lds_sweeps;          /* LDS engine: sweeps over each partition, one table each (0 = not used) */
-  uint32_t reserved0;           /* zero */
+  uint32_t lds_passes;          /* LDS engine: passes over the batch, one per run of partitions that
+                                   fits the budget (0 = not used) */
 } agg_stats;
 
 /* Validate and copy `spec`, reserve the working budget (or adopt the caller's

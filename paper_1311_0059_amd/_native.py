@@ -79,7 +79,7 @@ class Stats(ctypes.Structure):
         ("partition_ms", ctypes.c_double),
         ("sorted_ms", ctypes.c_double),
         ("lds_sweeps", ctypes.c_uint32),
-        ("reserved0", ctypes.c_uint32),
+        ("lds_passes", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:

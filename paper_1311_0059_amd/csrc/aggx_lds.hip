@@ -91,25 +91,35 @@ __device__ __forceinline__ void scatter_one(const uint8_t *rec, uint32_t d, uint
   }
 }
 
+// Only partitions [d_lo, d_lo + d_n) are written (a pass of the LDS engine over
+// part of the digit range); `cursors` and the output are relative to d_lo.
 __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
-                                                             uint32_t shift, uint32_t mask, uint64_t chunk,
+                                                             uint32_t shift, uint32_t mask, uint32_t d_lo,
+                                                             uint32_t d_n, uint64_t chunk,
                                                              unsigned long long *cursors, uint8_t *out, uint32_t vec) {
-  extern __shared__ uint32_t lc[];  // mask+1 counts, then mask+1 bases (record indices below 2^32)
-  uint32_t *lbase = lc + mask + 1;
-  for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) lc[b] = 0;
+  extern __shared__ uint32_t lc[];  // d_n counts, then d_n bases (record indices below 2^32)
+  uint32_t *lbase = lc + d_n;
+  for (uint32_t b = threadIdx.x; b < d_n; b += blockDim.x) lc[b] = 0;
   __syncthreads();
   const uint64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n, B = blockDim.x;
   uint64_t i = lo + threadIdx.x;
+  // the digits, relative to d_lo (out of range: d_n or more, as unsigned)
   for (; i + 3 * B < hi; i += 4 * B) {
     uint64_t k[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) k[u] = read_key(in + (i + u * B) * ks.rb, ks);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) atomicAdd(&lc[digit_of(k[u], shift, mask)], 1u);
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t d = digit_of(k[u], shift, mask) - d_lo;
+      if (d < d_n) atomicAdd(&lc[d], 1u);
+    }
   }
-  for (; i < hi; i += B) atomicAdd(&lc[digit_of(read_key(in + i * ks.rb, ks), shift, mask)], 1u);
+  for (; i < hi; i += B) {
+    const uint32_t d = digit_of(read_key(in + i * ks.rb, ks), shift, mask) - d_lo;
+    if (d < d_n) atomicAdd(&lc[d], 1u);
+  }
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) {
+  for (uint32_t b = threadIdx.x; b < d_n; b += blockDim.x) {
     if (lc[b])
       lbase[b] = (uint32_t)__hip_atomic_fetch_add(cursors + (uint64_t)b * (kCntStride / 2),
                                                   (unsigned long long)lc[b], __ATOMIC_RELAXED,
@@ -121,13 +131,15 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
   for (; i + 3 * B < hi; i += 4 * B) {
     uint32_t d[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) d[u] = digit_of(read_key(in + (i + u * B) * ks.rb, ks), shift, mask);
+    for (int u = 0; u < 4; ++u) d[u] = digit_of(read_key(in + (i + u * B) * ks.rb, ks), shift, mask) - d_lo;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) scatter_one(in + (i + u * B) * ks.rb, d[u], ks.rb, vec, lc, lbase, out);
+    for (int u = 0; u < 4; ++u)
+      if (d[u] < d_n) scatter_one(in + (i + u * B) * ks.rb, d[u], ks.rb, vec, lc, lbase, out);
   }
   for (; i < hi; i += B) {
     const uint8_t *rec = in + i * ks.rb;
-    scatter_one(rec, digit_of(read_key(rec, ks), shift, mask), ks.rb, vec, lc, lbase, out);
+    const uint32_t d = digit_of(read_key(rec, ks), shift, mask) - d_lo;
+    if (d < d_n) scatter_one(rec, d, ks.rb, vec, lc, lbase, out);
   }
 }
 
@@ -339,16 +351,18 @@ static bool scatter_lds_allowed(size_t lds) {
 }
 
 hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
-                               uint32_t mask, uint64_t chunk, unsigned long long *cursors, uint8_t *out) {
-  if (n == 0) return hipSuccess;
+                               uint32_t mask, uint32_t d_lo, uint32_t d_n, uint64_t chunk,
+                               unsigned long long *cursors, uint8_t *out) {
+  if (n == 0 || d_n == 0) return hipSuccess;
+  if (d_lo > mask || d_n > mask + 1 - d_lo) return hipErrorInvalidValue;
   const uint64_t blocks = (n + chunk - 1) / chunk;
   if (n >= (1ull << 32)) return hipErrorInvalidValue;  // the LDS bases are 32-bit record indices
-  const size_t lds = 8ull * (mask + 1);
+  const size_t lds = 8ull * d_n;
   if (!scatter_lds_allowed(lds)) return hipErrorInvalidValue;
   const uintptr_t a = reinterpret_cast<uintptr_t>(out);
   const uint32_t vec = ks.rb % 16 == 0 && a % 16 == 0 ? 16 : ks.rb % 8 == 0 && a % 8 == 0 ? 8 : 4;
-  hipLaunchKernelGGL(k_part_scatter, dim3((uint32_t)blocks), dim3(kPartBlock), lds, s, in, n, ks, shift, mask, chunk,
-                     cursors, out, vec);
+  hipLaunchKernelGGL(k_part_scatter, dim3((uint32_t)blocks), dim3(kPartBlock), lds, s, in, n, ks, shift, mask, d_lo,
+                     d_n, chunk, cursors, out, vec);
   return hipGetLastError();
 }
 

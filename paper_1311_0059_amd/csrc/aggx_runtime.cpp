@@ -680,14 +680,16 @@ agg_status append_side_rows(agg_handle *h) {
 // ---- partition-first engine with LDS tables --------------------------------
 struct LdsPlan {
   uint32_t b = 0, F = 1, sbits = 0, nslots = 0, cap = 0, lds_bytes = 0;
-  uint64_t buf_bytes = 0, need = 0;
+  uint64_t buf_bytes = 0, aux_bytes = 0, need = 0;
+  bool passes = false;  // the buffer holds only part of the batch: partitions go in passes
 };
 
 constexpr double kLdsLoad = 0.75;
 constexpr uint32_t kLdsMaxSweepBits = 2;          // up to four sweeps of a partition
 // largest batch (bytes) for the LDS engine: its worst-case spill, reserved in
-// pinned host memory before the launch, is the whole batch
+// pinned host memory before a launch, is what that launch aggregates
 constexpr uint64_t kLdsMaxInput = 4ull << 30;
+constexpr uint32_t kLdsMaxPasses = 8;             // passes over the batch when the budget holds part of it
 
 // Records per block of the partition count/scatter kernels: about 256 blocks
 // per launch.  Each block adds its LDS histogram to the global per-partition
@@ -699,8 +701,10 @@ uint64_t part_chunk(uint64_t n) { return std::max<uint64_t>(1024, (n + 255) / 25
 // Can the batch be aggregated partition by partition in LDS?  Each partition's
 // expected groups (plus four standard deviations) must fit one workgroup's LDS
 // table, with at most 2^13 partitions, or else the groups of one sweep of it
-// (at most four sweeps); the working budget must hold the partitioned copy of
-// the batch and the partition counters.
+// (at most four sweeps).  The working budget holds the partition counters and a
+// buffer for the partitioned batch, or, when the batch is larger, for a run of
+// consecutive partitions: the batch is then read once per run (at most
+// kLdsMaxPasses runs), and only that run's records are written to the buffer.
 bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
   const uint32_t rb = h->ks.rb;
   lp->lds_bytes = lds_agg_max_bytes();
@@ -726,9 +730,19 @@ bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
   lp->b = b;
   lp->sbits = sbits;
   lp->F = 1u << b;
+  // counters and cursors on their own 128-byte lines, offsets, packed counts
+  lp->aux_bytes = round_up(2ull * lp->F * 128 + 8ull * (lp->F + 1) + 4ull * lp->F, 256);
   lp->buf_bytes = round_up(n * rb, 256);
-  lp->need = lp->buf_bytes + 2ull * lp->F * 128 + 8ull * (lp->F + 1);
-  return h->unlimited || lp->need <= h->arena_cap_bytes;
+  lp->passes = false;
+  if (!h->unlimited && lp->buf_bytes + lp->aux_bytes > h->arena_cap_bytes) {
+    if (h->arena_cap_bytes <= lp->aux_bytes) return false;
+    lp->buf_bytes = (h->arena_cap_bytes - lp->aux_bytes) / 256 * 256;
+    // expected passes, with room for uneven partition sizes
+    if ((double)n * rb > 0.9 * (double)lp->buf_bytes * kLdsMaxPasses) return false;
+    lp->passes = true;
+  }
+  lp->need = lp->buf_bytes + lp->aux_bytes;
+  return true;
 }
 
 agg_status grow_unlimited_pool(agg_handle *h, uint64_t arena_need) {
@@ -746,38 +760,30 @@ agg_status grow_unlimited_pool(agg_handle *h, uint64_t arena_need) {
   return AGG_OK;
 }
 
-// Radix-partition the batch into the arena, aggregate each partition in LDS
-// and write its groups to the result; records of partitions whose LDS table
-// filled up go to the spill run.
-agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &lp) {
-  if (h->unlimited) {
-    agg_status s = grow_unlimited_pool(h, lp.need);
-    if (s) return s;
-  }
+// Aggregate partitions [d_lo, d_lo + d_n) of the batch: scatter their records
+// into the buffer, aggregate each partition in LDS and append its groups to the
+// result; records of keys that found no room in their table go to the spill run.
+agg_status lds_run_partitions(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &lp, uint32_t d_lo,
+                              uint32_t d_n, uint64_t records) {
   uint8_t *arena = reinterpret_cast<uint8_t *>(h->d_arena);
   uint8_t *buf = arena;
   uint32_t *totals = reinterpret_cast<uint32_t *>(arena + lp.buf_bytes);
   unsigned long long *cursors = reinterpret_cast<unsigned long long *>(arena + lp.buf_bytes + 128ull * lp.F);
   unsigned long long *offsets = cursors + (uint64_t)lp.F * (kCntStride / 2);
-  h->st.pool_high_water = std::max(h->st.pool_high_water, kOverhead + lp.need);
   const uint32_t shift = lp.b ? 64 - lp.b : 0, mask = lp.F - 1;
-  const uint64_t chunk = part_chunk(n);
-  HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)lp.F * kCntStride, 0));
-  HCK(h, launch_part_count(h->stream, in, n, h->ks, shift, mask, chunk, totals));
-  HCK(h, launch_part_offsets(h->stream, totals, lp.F, offsets, cursors));
-  HCK(h, launch_part_scatter(h->stream, in, n, h->ks, shift, mask, chunk, cursors, buf));
+  HCK(h, launch_part_offsets(h->stream, totals + (uint64_t)d_lo * kCntStride, d_n, offsets, cursors));
+  HCK(h, launch_part_scatter(h->stream, in, n, h->ks, shift, mask, d_lo, d_n, part_chunk(n), cursors, buf));
   uint8_t *dst = nullptr;
-  if (!h->next.reserve(n * h->ks.rb, &dst)) return AGG_E_NOMEM;
-  // rows per partition: at most its slot count (the group limit is checked with
-  // a plain LDS read, so concurrent inserts may pass it by up to one block)
-  agg_status s = ensure_result_cap(h, h->r_rows + std::min<uint64_t>(n, ((uint64_t)lp.F << lp.sbits) * lp.nslots) + 1);
+  if (!h->next.reserve(std::max<uint64_t>(records, 1) * h->ks.rb, &dst)) return AGG_E_NOMEM;
+  // rows per partition: at most its slot count per sweep
+  agg_status s = ensure_result_cap(h, h->r_rows + std::min<uint64_t>(records, ((uint64_t)d_n << lp.sbits) * lp.nslots) + 1);
   if (s) return s;
   HCK(h, launch_u64_set(h->stream, &h->d_ctrl->raw_ctr, 1, 0));
   HCK(h, launch_u64_set(h->stream, &h->d_ctrl->rows, 1, 0));
   OutCols oc{};
   for (uint32_t a = 0; a < h->spec.n_aggs; ++a) oc.c[a] = h->r_cols[a] + h->r_rows;
   HCK(h, hipEventRecord(h->ev0, h->stream));
-  HCK(h, launch_lds_agg(h->stream, buf, offsets, lp.F, h->ks, lp.b + lp.sbits, lp.sbits, lp.nslots, lp.cap,
+  HCK(h, launch_lds_agg(h->stream, buf, offsets, d_n, h->ks, lp.b + lp.sbits, lp.sbits, lp.nslots, lp.cap,
                         lp.lds_bytes, h->d_ctrl, spill_target(h, dst, nullptr), h->r_keys + h->r_rows, oc,
                         h->r_cap - h->r_rows));
   HCK(h, hipEventRecord(h->ev1, h->stream));
@@ -792,8 +798,59 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   h->st.bytes_spilled_d2h += h->h_ctrl->raw_ctr * h->ks.rb;
   if (h->h_ctrl->rows > h->r_cap - h->r_rows) return AGG_E_INTERNAL;
   h->r_rows += h->h_ctrl->rows;
+  return AGG_OK;
+}
+
+// Radix-partition the batch and aggregate every partition in LDS (engine L).
+// When the buffer holds only part of the batch, the exact partition sizes are
+// read back after the count and the partitions are taken in runs of
+// consecutive digits that fit the buffer, one pass over the batch per run.
+// *applied is false (and nothing but scratch was touched) when a single
+// partition does not fit the buffer.
+agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &lp, bool *applied) {
+  *applied = false;
+  if (h->unlimited) {
+    agg_status s = grow_unlimited_pool(h, lp.need);
+    if (s) return s;
+  }
+  uint8_t *arena = reinterpret_cast<uint8_t *>(h->d_arena);
+  uint32_t *totals = reinterpret_cast<uint32_t *>(arena + lp.buf_bytes);
+  uint32_t *packed = reinterpret_cast<uint32_t *>(arena + lp.buf_bytes + 2ull * lp.F * 128 + 8ull * (lp.F + 1));
+  const uint32_t shift = lp.b ? 64 - lp.b : 0, mask = lp.F - 1;
+  HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)lp.F * kCntStride, 0));
+  HCK(h, launch_part_count(h->stream, in, n, h->ks, shift, mask, part_chunk(n), totals));
+  // runs of consecutive partitions, each fitting the buffer
+  std::vector<std::pair<uint32_t, uint64_t>> runs;  // (first digit past the run, records)
+  if (!lp.passes) {
+    runs.push_back({lp.F, n});
+  } else {
+    HCK(h, launch_gather_u32(h->stream, totals, kCntStride, lp.F, packed));
+    HCK(h, hipMemcpyAsync(h->h_scratch, packed, 4ull * lp.F, hipMemcpyDeviceToHost, h->stream));
+    HCK(h, hipStreamSynchronize(h->stream));
+    const uint64_t cap = lp.buf_bytes / h->ks.rb;
+    uint64_t in_run = 0;
+    for (uint32_t d = 0; d < lp.F; ++d) {
+      const uint64_t c = h->h_scratch[d];
+      if (c > cap) return AGG_OK;  // one partition larger than the buffer: not this engine
+      if (in_run + c > cap) {
+        runs.push_back({d, in_run});
+        in_run = 0;
+      }
+      in_run += c;
+    }
+    runs.push_back({lp.F, in_run});
+  }
+  *applied = true;
+  h->st.pool_high_water = std::max(h->st.pool_high_water, kOverhead + lp.need);
+  uint32_t d_lo = 0;
+  for (const auto &r : runs) {
+    agg_status s = lds_run_partitions(h, in, n, lp, d_lo, r.first - d_lo, r.second);
+    if (s) return s;
+    d_lo = r.first;
+  }
   h->st.partitions = lp.F;
   h->st.lds_sweeps = 1u << lp.sbits;
+  h->st.lds_passes = (uint32_t)runs.size();
   h->used_bits = std::max(h->used_bits, lp.b + lp.sbits);
   return AGG_OK;
 }
@@ -901,7 +958,7 @@ agg_status run_owner_stream(agg_handle *h, const uint8_t *in, uint64_t n) {
       HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)pl.F * kCntStride, 0));
       HCK(h, launch_part_count(h->stream, src, c, h->ks, shift, mask, chunk, totals));
       HCK(h, launch_part_offsets(h->stream, totals, pl.F, offsets, cursors));
-      HCK(h, launch_part_scatter(h->stream, src, c, h->ks, shift, mask, chunk, cursors, buf));
+      HCK(h, launch_part_scatter(h->stream, src, c, h->ks, shift, mask, 0, mask + 1, chunk, cursors, buf));
       HCK(h, hipEventRecord(h->ev_own[2 * subs], h->stream));
       HCK(h, launch_owner_update(h->stream, buf, offsets, pl.F, h->ks, lv, h->d_meta, h->d_cnt, h->d_ovf,
                                  h->d_arena, h->d_ctrl, sp));
@@ -1276,11 +1333,15 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     LdsPlan lp;
     const double G = h->spec.est_groups ? (double)h->spec.est_groups : (double)n;
     if ((h->spec.engine == AGG_ENGINE_AUTO || h->spec.engine == AGG_ENGINE_LDS) &&
-        (h->spec.engine == AGG_ENGINE_LDS || !h->hot_key) && n * h->ks.rb <= kLdsMaxInput &&
-        lds_plan(h, n, G, &lp)) {
-      h->engine = 2;
-      h->st.engine = 2;
-      return run_lds(h, (const uint8_t *)d_records, n, lp);
+        (h->spec.engine == AGG_ENGINE_LDS || (!h->hot_key && h->spec.preagg != 1)) &&
+        n * h->ks.rb <= kLdsMaxInput && lds_plan(h, n, G, &lp)) {
+      bool applied = false;
+      agg_status s = run_lds(h, (const uint8_t *)d_records, n, lp, &applied);
+      if (s || applied) {
+        h->engine = 2;
+        h->st.engine = 2;
+        return s;
+      }
     }
     // Owner-computed tables when asked for.  (Not yet chosen automatically: on
     // the 200M-record uniform workload it measured slower than the atomic

@@ -66,10 +66,15 @@ def test_lds_then_more_batches(budget):
     assert a[2]["engine"] == 2
 
 
-def test_lds_refused_when_budget_cannot_hold_batch():
+def test_lds_passes_or_refused_by_budget():
+    """A budget that holds part of the partitioned batch: the LDS engine reads the batch in
+    passes; one that would need more than eight passes: the HBM tables take the batch."""
     wl = workloads.uniform_spill().scaled(1_000_000, 100_000)
     rec = wl.generate()
     k, c, st = run_lib(rec, **lib_spec_args(wl), budget=8 * MIB, est_groups=wl.d, engine="lds")
+    check_against_oracle(rec, oracle_spec(wl), k, c, "lds passes")
+    assert st["engine"] == 2 and st["lds_passes"] >= 2 and st["pool_high_water"] <= 8 * MIB
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=2 * MIB, est_groups=wl.d, engine="lds")
     check_against_oracle(rec, oracle_spec(wl), k, c, "lds refused")
     assert st["engine"] == 1
 

@@ -1,12 +1,17 @@
-"""GPU parity of the LDS engine's sweeps: a partition with more groups than one
-LDS table is aggregated in 2-4 sweeps over its records, each sweep taking the
-keys of one value of the hash bits below the partition digit.
+"""GPU parity of the LDS engine's sweeps and passes.
+
+Sweeps: a partition with more groups than one LDS table is aggregated in 2-4
+sweeps over its records, each sweep taking the keys of one value of the hash
+bits below the partition digit.  Passes: when the budget holds only part of
+the partitioned batch, runs of consecutive partitions are partitioned and
+aggregated one after the other, each run in one pass over the batch.
 
 Every case compares all rows with the CPU oracle: sweeps forced by a small
 explicit fan-out (R16 and composite R24 keys), the two reserved key values
-(folded by the first sweep only), overflow of a sweep's table (spill and
-recursion), more batches after a swept first batch, and the automatic choice
-of 2^13 partitions for a batch whose groups need more than 2^12.
+(folded by the first sweep only, and in exactly one pass), overflow of a
+table (spill and recursion, with sweeps and with passes), more batches after
+a swept or passed first batch, passes and sweeps together, and the automatic
+choice of 2^13 partitions for a batch whose groups need more than 2^12.
 """
 import numpy as np
 import pytest
@@ -82,3 +87,54 @@ def test_automatic_fanout_beyond_table_engine_limit():
     k, c, st = run_lib(rec, **lib_spec_args(wl), budget=0, est_groups=wl.d)
     assert st["engine"] == 2 and st["lds_sweeps"] == 1 and st["partitions"] == 8192
     check_against_oracle(rec, oracle_spec(wl), k, c, "automatic 2^13 partitions")
+
+
+@pytest.mark.parametrize("n,d,budget_mib", [(3_000_000, 300_000, 16), (2_000_000, 50_000, 9), (1_500_000, 1, 8)])
+def test_passes_exact(n, d, budget_mib):
+    wl = workloads.uniform_spill().scaled(n, d)
+    rec = wl.generate()
+    print(f"case: passes n={n} d={d} budget={budget_mib}MiB", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=budget_mib * MIB, est_groups=d)
+    check_against_oracle(rec, oracle_spec(wl), k, c, f"passes {n} {d}")
+    if d > 1:
+        assert st["engine"] == 2 and st["lds_passes"] >= 2 and st["levels"] == 1 and st["records_spilled"] == 0
+    assert st["pool_high_water"] <= budget_mib * MIB
+
+
+def test_passes_composite_keys_and_reserved_values():
+    wl = workloads.zipf_composite().scaled(1_500_000, 120_000)
+    rec = wl.generate().copy()
+    print("case: passes R24", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=12 * MIB, est_groups=wl.d, engine="lds")
+    check_against_oracle(rec, oracle_spec(wl), k, c, "passes R24")
+    assert st["engine"] == 2 and st["lds_passes"] >= 2
+    r16 = datagen.r16(409, 2_000_000, 100_000, lo=-10**6, hi=10**6).copy()
+    r16["key"][::333] = np.uint64((1 << 64) - 1)
+    r16["key"][1::777] = np.uint64((1 << 64) - 2)
+    print("case: passes + reserved keys", flush=True)
+    k, c, st = run_lib(r16, 16, [(0, "u64")], workloads.AGGS_R16_ALL, budget=12 * MIB, est_groups=100_000)
+    check_against_oracle(r16, SPEC_R16, k, c, "passes reserved keys")
+    assert st["engine"] == 2 and st["lds_passes"] >= 2
+
+
+@pytest.mark.parametrize("policy", ["destage", "prepart"])
+def test_passes_with_overflow_spill_and_recursion(policy):
+    """An estimate far below the true count: the LDS tables of every pass fill, new keys spill
+    raw and are aggregated at the next level inside the same budget."""
+    wl = workloads.uniform_spill().scaled(2_500_000, 1_200_000)
+    rec = wl.generate()
+    print(f"case: passes overflow {policy}", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=16 * MIB, est_groups=60_000, engine="lds", policy=policy)
+    check_against_oracle(rec, oracle_spec(wl), k, c, f"passes overflow {policy}")
+    assert st["engine"] == 2 and st["lds_passes"] >= 2 and st["levels"] >= 2 and st["records_spilled"] > 0
+    assert st["pool_high_water"] <= 16 * MIB
+
+
+def test_passes_with_sweeps_then_more_batches():
+    wl = workloads.uniform_spill().scaled(2_400_000, 200_000)
+    rec = wl.generate()
+    print("case: passes + sweeps + batches", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=10 * MIB, est_groups=wl.d, engine="lds", fanout_bits=5,
+                       batches=3)
+    check_against_oracle(rec, oracle_spec(wl), k, c, "passes sweeps batches")
+    assert st["engine"] == 2 and st["lds_passes"] >= 2 and st["lds_sweeps"] >= 2

@@ -71,12 +71,15 @@ def test_empty_input():
 @pytest.mark.parametrize("policy", ["destage", "prepart"])
 @pytest.mark.parametrize("budget_mib,est_scale", [(4, 1.0), (2, 1.0), (4, 1 / 16), (4, 16.0), (3, 0.0)])
 def test_spill_and_recursion(policy, budget_mib, est_scale):
-    """Budgets far below the table size: partitions spill to host memory and are re-aggregated."""
+    """Budgets far below the table size: partitions of the HBM tables spill to host memory and
+    are re-aggregated (the table engine is asked for: the LDS engine would read the batch in
+    passes instead of spilling)."""
     wl = workloads.uniform_spill().scaled(2_000_000, 400_000)
     rec = wl.generate()
     est = int(wl.d * est_scale)
     print(f"case: spill budget={budget_mib}MiB est={est} policy={policy}", flush=True)
-    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=budget_mib * MIB, est_groups=est, policy=policy)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=budget_mib * MIB, est_groups=est, policy=policy,
+                       engine="tables")
     check_against_oracle(rec, oracle_spec(wl), k, c, f"spill {budget_mib} {est_scale} {policy}")
     assert st["levels"] >= 2
     assert st["records_spilled"] + st["states_spilled"] > 0
