@@ -6,7 +6,9 @@ resident in HBM: agg_create (on a preallocated workspace of the budget's size)
 + agg_consume + agg_finish (every recursion level, result rows in HBM) +
 agg_destroy.  Default workload: 200M R16 records {u64 key, i64 v}, 20M
 distinct uniform keys, v uniform in [-1e6, 1e6], COUNT+SUM+MIN+MAX, 1 GiB
-device budget (forces partition spill and recursive re-aggregation).
+device budget (too small for the partitioned batch or for tables at the
+default load: the library reads the batch in passes of partitions, or with
+`--engine tables` packs its HBM tables to keep every group resident).
 
 Prints one JSON line.  `roofline` describes the dominant kernel (the level-0
 aggregation/routing kernel), timed with HIP events recorded by the library on
@@ -47,6 +49,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform-spill", choices=sorted(WORKLOADS))
     ap.add_argument("--policy", default="destage", choices=["destage", "prepart"])
+    ap.add_argument("--engine", default="auto", choices=["auto", "tables", "lds", "owner", "sorted"],
+                    help="engine for the first batch (auto = the library's choice)")
     ap.add_argument("--cpu-sample", type=int, default=48_000_000,
                     help="records of the input the CPU oracle is timed on (0 = skip)")
     ap.add_argument("--requests", type=int, default=400, help="served: requests in the trace")
@@ -124,7 +128,7 @@ def main():
     workspace = torch.empty(wl.budget, dtype=torch.uint8, device="cuda") if wl.budget else None
     torch.cuda.synchronize()
     spec = P.make_spec(wl.record_bytes, wl.key_fields, wl.aggs, budget=wl.budget, est_groups=wl.d,
-                       workspace=workspace, policy=args.policy)
+                       workspace=workspace, policy=args.policy, engine=args.engine)
     W8 = 8 * (1 + len(wl.aggs))
 
     def step():
@@ -167,6 +171,13 @@ def main():
         l0_bytes = agg["update_records_l0"] * wl.record_bytes + agg["resident_groups_l0"] * W8
         l0_ms = agg["update_ms_l0"]
         launches = max(1, agg["update_launches_l0"])
+    elif agg["scatter_ms"] > agg["lds_ms"]:
+        # the partition-first LDS engine ran and its scatter took longer than its aggregation:
+        # each scatter launch (one per pass) reads the whole batch; together they write it once
+        kname = "k_part_scatter"
+        launches = max(1, agg["scatter_launches"])
+        l0_bytes = (launches + args.steps) * wl.n * wl.record_bytes
+        l0_ms = agg["scatter_ms"]
     else:  # the partition-first LDS engine ran: its aggregation kernel reads the partitioned batch
         kname = "k_lds_agg"
         l0_bytes = wl.n * args.steps * wl.record_bytes + agg["resident_groups_l0"] * W8
@@ -225,6 +236,7 @@ def main():
             "aggregates": [a[0] for a in wl.aggs],
             "budget_bytes": wl.budget,
             "policy": args.policy,
+            "engine": args.engine,
             "parallelism": "1 GPU",
         },
         "gbps_algorithmic": round(alg_bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
@@ -247,6 +259,7 @@ def main():
             "sorted_ms": round(agg["sorted_ms"] / args.steps, 3),
             "lds_sweeps": agg["lds_sweeps"] // args.steps,
             "lds_passes": agg["lds_passes"] // args.steps,
+            "scatter_ms": round(agg["scatter_ms"] / args.steps, 3),
             "engine": agg["engine"] // args.steps,
             "preagg": agg["preagg"] // args.steps,
             "pool_high_water": agg["pool_high_water"] // args.steps,

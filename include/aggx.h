@@ -167,6 +167,8 @@ typedef struct agg_stats {
   uint32_t lds_sweeps;          /* LDS engine: sweeps over each partition, one table each (0 = not used) */
   uint32_t lds_passes;          /* LDS engine: passes over the batch, one per run of partitions that
                                    fits the budget (0 = not used) */
+  uint64_t scatter_launches;    /* LDS engine: launches of its scatter kernel (one per pass) */
+  double scatter_ms;            /* their summed duration */
 } agg_stats;
 
 /* Validate and copy `spec`, reserve the working budget (or adopt the caller's

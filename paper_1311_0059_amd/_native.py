@@ -80,6 +80,8 @@ class Stats(ctypes.Structure):
         ("sorted_ms", ctypes.c_double),
         ("lds_sweeps", ctypes.c_uint32),
         ("lds_passes", ctypes.c_uint32),
+        ("scatter_launches", ctypes.c_uint64),
+        ("scatter_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

@@ -162,12 +162,12 @@ hipError_t launch_digit_scatter(hipStream_t s, int kind, const uint8_t *in, uint
                                 uint32_t shift, uint32_t mask, unsigned long long *cursor, uint8_t *out);
 // Partition-first LDS engine.
 hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
-                             uint32_t mask, uint64_t chunk, uint32_t *totals);
+                             uint32_t mask, uint64_t chunk, uint32_t *totals, uint32_t *block_counts);
 hipError_t launch_part_offsets(hipStream_t s, const uint32_t *totals, uint32_t F, unsigned long long *offsets,
                                unsigned long long *cursors);
 hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
                                uint32_t mask, uint32_t d_lo, uint32_t d_n, uint64_t chunk,
-                               unsigned long long *cursors, uint8_t *out);
+                               const uint32_t *block_counts, unsigned long long *cursors, uint8_t *out);
 hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long long *offsets, uint32_t F,
                           const KSpec &ks, uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots, uint32_t cap,
                           uint32_t lds_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys, const OutCols &out_cols,

@@ -27,10 +27,12 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t key, uint32_t shift, uint3
 // Pass 1: records per partition.  Each block takes a contiguous chunk, counts
 // digits in LDS and adds its counts to the per-partition totals.  Each thread
 // reads four keys before it counts them, so that their loads are in flight
-// together (the chunks are long and the blocks few).
+// together (the chunks are long and the blocks few).  With `block_counts`, the
+// block also stores its counts (one row of mask+1 per block), so that a scatter
+// over the same chunks need not count again.
 __global__ void __launch_bounds__(kPartBlock) k_part_count(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
                                                            uint32_t shift, uint32_t mask, uint64_t chunk,
-                                                           uint32_t *totals) {
+                                                           uint32_t *totals, uint32_t *block_counts) {
   extern __shared__ uint32_t lh[];
   for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) lh[b] = 0;
   __syncthreads();
@@ -45,8 +47,10 @@ __global__ void __launch_bounds__(kPartBlock) k_part_count(const uint8_t *__rest
   }
   for (; i < hi; i += B) atomicAdd(&lh[digit_of(read_key(in + i * ks.rb, ks), shift, mask)], 1u);
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x)
+  for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) {
     if (lh[b]) __hip_atomic_fetch_add(totals + (uint64_t)b * kCntStride, lh[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (block_counts) block_counts[(uint64_t)blockIdx.x * (mask + 1) + b] = lh[b];
+  }
 }
 
 // Exclusive scan of the totals: partition p occupies [offsets[p], offsets[p+1]).
@@ -93,16 +97,25 @@ __device__ __forceinline__ void scatter_one(const uint8_t *rec, uint32_t d, uint
 
 // Only partitions [d_lo, d_lo + d_n) are written (a pass of the LDS engine over
 // part of the digit range); `cursors` and the output are relative to d_lo.
+// With `block_counts` (stored by k_part_count over the same chunks) the block
+// takes its counts from there instead of reading its keys twice.
 __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
                                                              uint32_t shift, uint32_t mask, uint32_t d_lo,
                                                              uint32_t d_n, uint64_t chunk,
+                                                             const uint32_t *__restrict__ block_counts,
                                                              unsigned long long *cursors, uint8_t *out, uint32_t vec) {
   extern __shared__ uint32_t lc[];  // d_n counts, then d_n bases (record indices below 2^32)
   uint32_t *lbase = lc + d_n;
-  for (uint32_t b = threadIdx.x; b < d_n; b += blockDim.x) lc[b] = 0;
-  __syncthreads();
   const uint64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n, B = blockDim.x;
   uint64_t i = lo + threadIdx.x;
+  if (block_counts) {
+    for (uint32_t b = threadIdx.x; b < d_n; b += blockDim.x)
+      lc[b] = block_counts[(uint64_t)blockIdx.x * (mask + 1) + d_lo + b];
+    i = hi;  // nothing to count
+  } else {
+    for (uint32_t b = threadIdx.x; b < d_n; b += blockDim.x) lc[b] = 0;
+  }
+  __syncthreads();
   // the digits, relative to d_lo (out of range: d_n or more, as unsigned)
   for (; i + 3 * B < hi; i += 4 * B) {
     uint64_t k[4];
@@ -315,11 +328,11 @@ __global__ void __launch_bounds__(256) k_merge_rows(const uint64_t *__restrict__
 }
 
 hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
-                             uint32_t mask, uint64_t chunk, uint32_t *totals) {
+                             uint32_t mask, uint64_t chunk, uint32_t *totals, uint32_t *block_counts) {
   if (n == 0) return hipSuccess;
   const uint64_t blocks = (n + chunk - 1) / chunk;
   hipLaunchKernelGGL(k_part_count, dim3((uint32_t)blocks), dim3(kPartBlock), 4ull * (mask + 1), s, in, n, ks, shift,
-                     mask, chunk, totals);
+                     mask, chunk, totals, block_counts);
   return hipGetLastError();
 }
 
@@ -352,7 +365,7 @@ static bool scatter_lds_allowed(size_t lds) {
 
 hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
                                uint32_t mask, uint32_t d_lo, uint32_t d_n, uint64_t chunk,
-                               unsigned long long *cursors, uint8_t *out) {
+                               const uint32_t *block_counts, unsigned long long *cursors, uint8_t *out) {
   if (n == 0 || d_n == 0) return hipSuccess;
   if (d_lo > mask || d_n > mask + 1 - d_lo) return hipErrorInvalidValue;
   const uint64_t blocks = (n + chunk - 1) / chunk;
@@ -362,7 +375,7 @@ hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, con
   const uintptr_t a = reinterpret_cast<uintptr_t>(out);
   const uint32_t vec = ks.rb % 16 == 0 && a % 16 == 0 ? 16 : ks.rb % 8 == 0 && a % 8 == 0 ? 8 : 4;
   hipLaunchKernelGGL(k_part_scatter, dim3((uint32_t)blocks), dim3(kPartBlock), lds, s, in, n, ks, shift, mask, d_lo,
-                     d_n, chunk, cursors, out, vec);
+                     d_n, chunk, block_counts, cursors, out, vec);
   return hipGetLastError();
 }
 

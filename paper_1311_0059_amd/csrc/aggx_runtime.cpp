@@ -214,6 +214,7 @@ struct agg_handle {
   uint64_t arena_cap_bytes = 0;
 
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // kernel timing on the handle's stream
+  hipEvent_t ev2 = nullptr, ev3 = nullptr;  // a second pair, for the LDS engine's scatter
   Ctrl *h_ctrl = nullptr;       // pinned mirror of the control block
   uint32_t *h_scratch = nullptr;  // pinned mirror for cnt / ovf / hll readbacks
 
@@ -730,8 +731,10 @@ bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
   lp->b = b;
   lp->sbits = sbits;
   lp->F = 1u << b;
-  // counters and cursors on their own 128-byte lines, offsets, packed counts
-  lp->aux_bytes = round_up(2ull * lp->F * 128 + 8ull * (lp->F + 1) + 4ull * lp->F, 256);
+  // counters and cursors on their own 128-byte lines, offsets, packed counts, and
+  // the count kernel's per-block counts (one row of F per block)
+  const uint64_t blocks = (n + part_chunk(n) - 1) / part_chunk(n);
+  lp->aux_bytes = round_up(2ull * lp->F * 128 + 8ull * (lp->F + 1) + 4ull * lp->F, 256) + round_up(4ull * blocks * lp->F, 256);
   lp->buf_bytes = round_up(n * rb, 256);
   lp->passes = false;
   if (!h->unlimited && lp->buf_bytes + lp->aux_bytes > h->arena_cap_bytes) {
@@ -760,6 +763,12 @@ agg_status grow_unlimited_pool(agg_handle *h, uint64_t arena_need) {
   return AGG_OK;
 }
 
+// The count kernel's per-block counts: after the counters, offsets and packed counts.
+uint32_t *lds_block_counts(uint8_t *arena, const LdsPlan &lp) {
+  return reinterpret_cast<uint32_t *>(arena + lp.buf_bytes +
+                                      round_up(2ull * lp.F * 128 + 8ull * (lp.F + 1) + 4ull * lp.F, 256));
+}
+
 // Aggregate partitions [d_lo, d_lo + d_n) of the batch: scatter their records
 // into the buffer, aggregate each partition in LDS and append its groups to the
 // result; records of keys that found no room in their table go to the spill run.
@@ -772,7 +781,10 @@ agg_status lds_run_partitions(agg_handle *h, const uint8_t *in, uint64_t n, cons
   unsigned long long *offsets = cursors + (uint64_t)lp.F * (kCntStride / 2);
   const uint32_t shift = lp.b ? 64 - lp.b : 0, mask = lp.F - 1;
   HCK(h, launch_part_offsets(h->stream, totals + (uint64_t)d_lo * kCntStride, d_n, offsets, cursors));
-  HCK(h, launch_part_scatter(h->stream, in, n, h->ks, shift, mask, d_lo, d_n, part_chunk(n), cursors, buf));
+  HCK(h, hipEventRecord(h->ev2, h->stream));
+  HCK(h, launch_part_scatter(h->stream, in, n, h->ks, shift, mask, d_lo, d_n, part_chunk(n), lds_block_counts(arena, lp),
+                             cursors, buf));
+  HCK(h, hipEventRecord(h->ev3, h->stream));
   uint8_t *dst = nullptr;
   if (!h->next.reserve(std::max<uint64_t>(records, 1) * h->ks.rb, &dst)) return AGG_E_NOMEM;
   // rows per partition: at most its slot count per sweep
@@ -793,6 +805,9 @@ agg_status lds_run_partitions(agg_handle *h, const uint8_t *in, uint64_t n, cons
   HCK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
   h->st.lds_launches += 1;
   h->st.lds_ms += ms;
+  HCK(h, hipEventElapsedTime(&ms, h->ev2, h->ev3));
+  h->st.scatter_launches += 1;
+  h->st.scatter_ms += ms;
   h->next.commit(dst, h->h_ctrl->raw_ctr, h->ks.rb, false);
   h->st.records_spilled += h->h_ctrl->raw_ctr;
   h->st.bytes_spilled_d2h += h->h_ctrl->raw_ctr * h->ks.rb;
@@ -818,7 +833,7 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   uint32_t *packed = reinterpret_cast<uint32_t *>(arena + lp.buf_bytes + 2ull * lp.F * 128 + 8ull * (lp.F + 1));
   const uint32_t shift = lp.b ? 64 - lp.b : 0, mask = lp.F - 1;
   HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)lp.F * kCntStride, 0));
-  HCK(h, launch_part_count(h->stream, in, n, h->ks, shift, mask, part_chunk(n), totals));
+  HCK(h, launch_part_count(h->stream, in, n, h->ks, shift, mask, part_chunk(n), totals, lds_block_counts(arena, lp)));
   // runs of consecutive partitions, each fitting the buffer
   std::vector<std::pair<uint32_t, uint64_t>> runs;  // (first digit past the run, records)
   if (!lp.passes) {
@@ -956,9 +971,9 @@ agg_status run_owner_stream(agg_handle *h, const uint8_t *in, uint64_t n) {
       const uint8_t *src = in + (off + so) * rb;
       const uint64_t chunk = part_chunk(c);
       HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)pl.F * kCntStride, 0));
-      HCK(h, launch_part_count(h->stream, src, c, h->ks, shift, mask, chunk, totals));
+      HCK(h, launch_part_count(h->stream, src, c, h->ks, shift, mask, chunk, totals, nullptr));
       HCK(h, launch_part_offsets(h->stream, totals, pl.F, offsets, cursors));
-      HCK(h, launch_part_scatter(h->stream, src, c, h->ks, shift, mask, 0, mask + 1, chunk, cursors, buf));
+      HCK(h, launch_part_scatter(h->stream, src, c, h->ks, shift, mask, 0, mask + 1, chunk, nullptr, cursors, buf));
       HCK(h, hipEventRecord(h->ev_own[2 * subs], h->stream));
       HCK(h, launch_owner_update(h->stream, buf, offsets, pl.F, h->ks, lv, h->d_meta, h->d_cnt, h->d_ovf,
                                  h->d_arena, h->d_ctrl, sp));
@@ -1252,7 +1267,8 @@ agg_status agg_create(const agg_spec *spec, agg_handle **out) {
     }
     h->own_stream = true;
   }
-  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+      hipEventCreate(&h->ev2) != hipSuccess || hipEventCreate(&h->ev3) != hipSuccess) {
     agg_destroy(h);
     return AGG_E_DEVICE;
   }
@@ -1428,6 +1444,8 @@ void agg_destroy(agg_handle *h) {
   if (h->r_block) dev_put(h->r_block, h->r_block_bytes);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
+  if (h->ev2) (void)hipEventDestroy(h->ev2);
+  if (h->ev3) (void)hipEventDestroy(h->ev3);
   for (auto &e : h->ev_own)
     if (e) (void)hipEventDestroy(e);
   if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
