@@ -294,7 +294,7 @@ def bench_g_sweep(args):
     def run(policy, factor):
         est = max(1, int(round(wl.d * factor)))
         spec = P.make_spec(wl.record_bytes, wl.key_fields, wl.aggs, budget=wl.budget, est_groups=est, workspace=ws,
-                           policy=policy)
+                           policy=policy, engine=args.engine)
         torch.cuda.synchronize()
         t = time.perf_counter()
         with P.GroupBy(spec) as g:
@@ -323,7 +323,7 @@ def bench_g_sweep(args):
            "warmup": 1, "ms_per_step": base, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "int64", "data": "synthetic",
            "config": {"workload": f"{wl.name} with est_groups = G x factor", "records": wl.n, "distinct_keys": wl.d,
-                      "budget_bytes": wl.budget},
+                      "budget_bytes": wl.budget, "engine": args.engine},
            "rows_ok": bool(ok), "sweep": points, "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
@@ -350,7 +350,7 @@ def bench_first_rows(args):
     ok = True
     for policy in ("destage", "prepart"):
         spec = P.make_spec(wl.record_bytes, wl.key_fields, wl.aggs, budget=budget, est_groups=wl.d, workspace=ws,
-                           policy=policy)
+                           policy=policy, engine=args.engine)
         runs = []
         for i in range(args.warmup + args.steps):
             torch.cuda.synchronize()
@@ -375,7 +375,7 @@ def bench_first_rows(args):
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": base, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
            "config": {"workload": f"{wl.name} with a 512 MiB budget: time to first rows", "records": wl.n,
-                      "distinct_keys": wl.d, "budget_bytes": budget},
+                      "distinct_keys": wl.d, "budget_bytes": budget, "engine": args.engine},
            "rows_ok": bool(ok), "first_rows": res, "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 

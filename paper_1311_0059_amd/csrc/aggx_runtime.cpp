@@ -706,6 +706,8 @@ uint64_t part_chunk(uint64_t n) { return std::max<uint64_t>(1024, (n + 255) / 25
 // buffer for the partitioned batch, or, when the batch is larger, for a run of
 // consecutive partitions: the batch is then read once per run (at most
 // kLdsMaxPasses runs), and only that run's records are written to the buffer.
+// With an automatic fan-out the group count planned for is raised (see below),
+// so that a low estimate does not make the tables overflow.
 bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
   const uint32_t rb = h->ks.rb;
   lp->lds_bytes = lds_agg_max_bytes();
@@ -717,16 +719,33 @@ bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
   uint32_t b = h->spec.fanout_bits;
   const uint32_t bmax = h->spec.fanout_bits ? h->spec.fanout_bits : (uint32_t)kLdsMaxFanBits;
   while (!h->spec.fanout_bits && b < 8 && ((uint64_t)kLdsBlock << (b + 1)) <= n) ++b;
-  const auto fits = [&](uint32_t bits) {
-    const double g = G / (double)(1ull << bits);
-    return g + 4.0 * std::sqrt(g) + 16.0 <= lp->cap;
-  };
+  const auto fits_groups = [&](double g) { return g + 4.0 * std::sqrt(g) + 16.0 <= lp->cap; };
+  if (!h->spec.fanout_bits) {
+    // No more groups than records.  And an estimate below the truth would leave
+    // too few partitions, whose tables overflow and spill; partitions cost little,
+    // so plan for at least what 2^13 partitions hold in one sweep (or the records).
+    double one_sweep = 0.0;  // largest group count per partition that fits one table
+    for (double lo = 0.0, hi = lp->cap; hi - lo > 0.5;) {
+      const double mid = 0.5 * (lo + hi);
+      (fits_groups(mid) ? lo : hi) = mid;
+      one_sweep = lo;
+    }
+    G = std::min(G, (double)n);
+    G = std::max(G, std::min((double)n, one_sweep * (double)(1u << kLdsMaxFanBits)));
+  }
+  const auto fits = [&](uint32_t bits) { return fits_groups(G / (double)(1ull << bits)); };
   while (b <= bmax && !fits(b)) ++b;
   uint32_t sbits = 0;
   if (b > bmax) {
     b = bmax;
     while (sbits <= kLdsMaxSweepBits && !fits(b + sbits)) ++sbits;
-    if (sbits > kLdsMaxSweepBits) return false;
+    if (sbits > kLdsMaxSweepBits) {
+      // more groups than four sweeps of 2^13 tables hold: with an automatic fan-out
+      // take the largest plan anyway (the estimate is an upper bound, and keys that
+      // find no room spill and recurse as with any full table)
+      if (h->spec.fanout_bits) return false;
+      sbits = kLdsMaxSweepBits;
+    }
   }
   lp->b = b;
   lp->sbits = sbits;
@@ -1297,19 +1316,10 @@ agg_status agg_create(const agg_spec *spec, agg_handle **out) {
     agg_destroy(h);
     return AGG_E_DEVICE;
   }
-  if (spec->engine == AGG_ENGINE_TABLES && spec->est_groups) {
-    // tables requested: plan and clear them now, outside the first consume
+  if (spec->engine == AGG_ENGINE_TABLES) {
+    // tables requested: the first consume plans them as for the automatic choice
     h->engine = 1;
     h->st.engine = 1;
-    s = make_plan(h, 0, (double)spec->est_groups, 0);
-    h->used_bits = h->plan.fan_bits;
-    if (!s) s = start_level(h);
-    if (s) {
-      agg_destroy(h);
-      return s;
-    }
-    h->st.partitions = h->plan.F;
-    h->st.partitions_spilled = h->plan.planned_spilled;
   }
   *out = h;
   return AGG_OK;
@@ -1321,9 +1331,10 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
   if (h->state != H_OPEN || h->l0_done) return AGG_E_STATE;
   if (n == 0) return AGG_OK;
   if (!d_records || ((uintptr_t)d_records & (h->ks.rb % 8 ? 3 : 7))) return AGG_E_INVALID;
-  if (h->engine == 0) {
+  if (h->st.records_in == 0) {
     // Early aggregation pays off when keys repeat within a workgroup's share of
-    // the input: look for repeated keys in an evenly spaced sample of the batch.
+    // the input: look for repeated keys in an evenly spaced sample of the first
+    // batch (also when the tables were planned at creation).
     const uint32_t ns = (uint32_t)std::min<uint64_t>(n, 2048);  // the sampler's set has 4096 slots
     HCK(h, launch_sample_dups(h->stream, (const uint8_t *)d_records, n, h->ks, ns, &h->d_ctrl->sample_dups));
     agg_status s = read_ctrl(h);
@@ -1334,7 +1345,7 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     h->hot_key = ns >= 256 && h->h_ctrl->sample_max * 50 > ns;
     h->sample_sorted = ns >= 2 && h->h_ctrl->sample_unsorted == 0;
   }
-  h->st.preagg = (uint32_t)h->preagg;
+  h->st.preagg = h->preagg > 0 ? 1u : 0u;
   h->st.records_in += n;
   if (h->engine == 0 &&
       (h->spec.engine == AGG_ENGINE_SORTED || (h->spec.engine == AGG_ENGINE_AUTO && h->sample_sorted))) {

@@ -45,15 +45,26 @@ def test_lds_engine_edge_layouts(layout):
         assert st["engine"] == 2
 
 
-@pytest.mark.parametrize("scale", [50, 400])
-def test_lds_overflow_spills_and_recurses(scale):
-    """An estimate far below the true group count gives too few partitions: LDS tables fill,
-    new keys spill raw and are re-aggregated at the next level."""
+@pytest.mark.parametrize("bits", [2, 6])
+def test_lds_overflow_spills_and_recurses(bits):
+    """Too few partitions for the groups (an explicit fan-out, so that the low estimate is
+    taken as given): LDS tables fill, new keys spill raw and are re-aggregated at the
+    next level."""
     wl = workloads.uniform_spill().scaled(1_500_000, 1_200_000)
     rec = wl.generate()
-    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d // scale, engine="lds")
-    check_against_oracle(rec, oracle_spec(wl), k, c, f"lds overflow /{scale}")
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d // 400, engine="lds", fanout_bits=bits)
+    check_against_oracle(rec, oracle_spec(wl), k, c, f"lds overflow {bits}")
     assert st["engine"] == 2 and st["levels"] >= 2 and st["records_spilled"] > 0
+
+
+def test_lds_low_estimate_plans_enough_partitions():
+    """Without an explicit fan-out, an estimate 400x too low still gets enough partitions:
+    nothing spills."""
+    wl = workloads.uniform_spill().scaled(1_500_000, 1_200_000)
+    rec = wl.generate()
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d // 400)
+    check_against_oracle(rec, oracle_spec(wl), k, c, "lds low estimate")
+    assert st["engine"] == 2 and st["levels"] == 1 and st["records_spilled"] == 0
 
 
 @pytest.mark.parametrize("budget", [0, 64 * MIB])

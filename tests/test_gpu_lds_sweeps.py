@@ -119,12 +119,14 @@ def test_passes_composite_keys_and_reserved_values():
 
 @pytest.mark.parametrize("policy", ["destage", "prepart"])
 def test_passes_with_overflow_spill_and_recursion(policy):
-    """An estimate far below the true count: the LDS tables of every pass fill, new keys spill
-    raw and are aggregated at the next level inside the same budget."""
+    """Too few partitions for the groups (a low estimate with an explicit fan-out): the LDS
+    tables of every pass fill, new keys spill raw and are aggregated at the next level inside
+    the same budget."""
     wl = workloads.uniform_spill().scaled(2_500_000, 1_200_000)
     rec = wl.generate()
     print(f"case: passes overflow {policy}", flush=True)
-    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=16 * MIB, est_groups=60_000, engine="lds", policy=policy)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=16 * MIB, est_groups=60_000, engine="lds", policy=policy,
+                       fanout_bits=6)
     check_against_oracle(rec, oracle_spec(wl), k, c, f"passes overflow {policy}")
     assert st["engine"] == 2 and st["lds_passes"] >= 2 and st["levels"] >= 2 and st["records_spilled"] > 0
     assert st["pool_high_water"] <= 16 * MIB

@@ -167,6 +167,21 @@ def test_full_size_uniform_spill():
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("factor", [1 / 4096, 16])
+def test_full_size_uniform_spill_wrong_estimate(factor):
+    """The same workload with the distinct-key estimate 4096x too low and 16x too high (more
+    groups than the records): the LDS engine plans enough partitions, and for the high
+    estimate its largest plan (2^13 partitions, four sweeps) with no overflow."""
+    wl = workloads.uniform_spill()
+    rec = wl.generate()
+    print(f"case: full uniform-200M-20M-1GiB, estimate x{factor}", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=wl.budget, est_groups=max(1, int(wl.d * factor)))
+    check_sampled(rec, wl, k, c)
+    assert st["pool_high_water"] <= wl.budget and st["engine"] == 2 and st["records_spilled"] == 0
+    assert st["lds_sweeps"] == (4 if factor > 1 else 1)
+
+
+@pytest.mark.slow
 def test_full_size_zipf_composite():
     """500M R24 records, 50M Zipf(1.0) composite keys, 4 GiB budget: sampled rows + invariants."""
     wl = workloads.zipf_composite()
