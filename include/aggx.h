@@ -76,11 +76,16 @@ typedef enum agg_policy {
 
 /* Aggregation engines (all compute the same rows). */
 typedef enum agg_engine {
-  AGG_ENGINE_AUTO = 0,    /* LDS engine when it applies; else owner-computed HBM tables for large batches
-                             without a dominant key; else HBM tables with atomics */
+  AGG_ENGINE_AUTO = 0,    /* for the first batch: the sorted-run path when a sample of it is sorted; else
+                             the LDS engine when it applies and no key dominates a sample; else HBM
+                             tables with atomics.  Later batches and recursion levels use HBM tables */
   AGG_ENGINE_TABLES = 1,  /* per-partition open-addressing tables in HBM, 64-bit atomics, chunked input */
-  AGG_ENGINE_LDS = 2,     /* radix-partition the batch, then one workgroup aggregates each partition in an
-                             LDS table; needs the budget to hold the partitioned batch (else falls back) */
+  AGG_ENGINE_LDS = 2,     /* radix-partition the batch (up to 2^13 partitions), then one workgroup
+                             aggregates each partition in an LDS table (in up to 4 sweeps when a partition
+                             has more groups than a table).  When the budget holds only part of the
+                             partitioned batch, runs of partitions that fit it are done one pass over the
+                             batch each.  Applies to a first batch of at most 4 GiB needing at most 8
+                             passes, with no partition larger than the buffer (else HBM tables) */
   AGG_ENGINE_OWNER = 3,   /* the same HBM tables, updated without atomics: sub-chunks of the batch are
                              radix-partitioned into a buffer carved from the budget, and one workgroup owns
                              each partition's table while it folds that partition's records in */
