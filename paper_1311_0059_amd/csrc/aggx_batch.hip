@@ -215,7 +215,8 @@ __global__ void __launch_bounds__(1024) k_batch(BParams P) {
           lh[d] = 0;
         }
         __syncthreads();
-        const uint32_t words = ks.rb / 4;
+        // the partition buffers are 256-byte aligned, so the record size alone decides the stores
+        const uint32_t vec = ks.rb % 16 == 0 ? 16 : ks.rb % 8 == 0 ? 8 : 4;
         const uint64_t B = blockDim.x;
         uint64_t i = it.lo + tid;
         // four records per thread per step, so that their loads are in flight together
@@ -226,18 +227,15 @@ __global__ void __launch_bounds__(1024) k_batch(BParams P) {
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const uint32_t r = atomicAdd(&lh[dg[u]], 1u);
-            uint32_t *dst = reinterpret_cast<uint32_t *>(I.buf + (lbase[dg[u]] + r) * ks.rb);
-            const uint32_t *src = reinterpret_cast<const uint32_t *>(I.in + (i + u * B) * ks.rb);
-            for (uint32_t w = 0; w < words; ++w) dst[w] = src[w];
+            store_record(I.buf + (lbase[dg[u]] + r) * ks.rb,
+                         reinterpret_cast<const uint32_t *>(I.in + (i + u * B) * ks.rb), ks.rb, vec);
           }
         }
         for (; i < it.hi; i += B) {
           const uint8_t *rec = I.in + i * ks.rb;
           const uint32_t d = bdigit(read_key(rec, ks), I.b);
           const uint32_t r = atomicAdd(&lh[d], 1u);
-          uint32_t *dst = reinterpret_cast<uint32_t *>(I.buf + (lbase[d] + r) * ks.rb);
-          const uint32_t *src = reinterpret_cast<const uint32_t *>(rec);
-          for (uint32_t w = 0; w < words; ++w) dst[w] = src[w];
+          store_record(I.buf + (lbase[d] + r) * ks.rb, reinterpret_cast<const uint32_t *>(rec), ks.rb, vec);
         }
         __syncthreads();
         if (tid == 0) publish(P.scat_done + it.inst);

@@ -156,6 +156,21 @@ __device__ __forceinline__ void in_vals(const uint8_t *rec, const KSpec &ks, uin
 
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 
+// Store one record of `rb` bytes (a multiple of 4) read from `src` at `dst`.
+// Scattered records land at places no other lane writes next to, so each is
+// written with as few stores as its alignment allows: `vec` bytes each (16, 8
+// or 4; the caller checked that dst and rb allow it).
+__device__ __forceinline__ void store_record(uint8_t *dst, const uint32_t *src, uint32_t rb, uint32_t vec) {
+  if (vec == 16) {
+    for (uint32_t w = 0; w < rb / 16; ++w)
+      reinterpret_cast<uint4 *>(dst)[w] = make_uint4(src[4 * w], src[4 * w + 1], src[4 * w + 2], src[4 * w + 3]);
+  } else if (vec == 8) {
+    for (uint32_t w = 0; w < rb / 8; ++w) reinterpret_cast<uint2 *>(dst)[w] = make_uint2(src[2 * w], src[2 * w + 1]);
+  } else {
+    for (uint32_t w = 0; w < rb / 4; ++w) reinterpret_cast<uint32_t *>(dst)[w] = src[w];
+  }
+}
+
 // Copy `bytes` (a multiple of 4) between two regions with all threads of the block.
 __device__ __forceinline__ void block_copy(uint32_t *dst, const uint32_t *src, uint32_t bytes) {
   for (uint32_t w = threadIdx.x; w < bytes / 4; w += blockDim.x) dst[w] = src[w];

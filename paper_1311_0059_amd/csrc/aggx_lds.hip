@@ -77,22 +77,11 @@ __global__ void __launch_bounds__(256) k_part_offsets(const uint32_t *totals, ui
 // range per partition with one atomic, and writes its records there; a
 // block's records of one partition are therefore contiguous in the output.
 // Four keys per thread are read before their records are placed.
-// Write one record to its partition.  The records land at scattered places, so
-// each is written with as few stores as its alignment allows (`vec` bytes each:
-// 16, 8 or 4; the destination's alignment was checked by the launch).
+// Write one record to its partition (see store_record).
 __device__ __forceinline__ void scatter_one(const uint8_t *rec, uint32_t d, uint32_t rb, uint32_t vec, uint32_t *lc,
                                             const uint32_t *lbase, uint8_t *out) {
   const uint32_t r = atomicAdd(&lc[d], 1u);
-  uint8_t *dst = out + ((uint64_t)lbase[d] + r) * rb;
-  const uint32_t *src = reinterpret_cast<const uint32_t *>(rec);
-  if (vec == 16) {
-    for (uint32_t w = 0; w < rb / 16; ++w)
-      reinterpret_cast<uint4 *>(dst)[w] = make_uint4(src[4 * w], src[4 * w + 1], src[4 * w + 2], src[4 * w + 3]);
-  } else if (vec == 8) {
-    for (uint32_t w = 0; w < rb / 8; ++w) reinterpret_cast<uint2 *>(dst)[w] = make_uint2(src[2 * w], src[2 * w + 1]);
-  } else {
-    for (uint32_t w = 0; w < rb / 4; ++w) reinterpret_cast<uint32_t *>(dst)[w] = src[w];
-  }
+  store_record(out + ((uint64_t)lbase[d] + r) * rb, reinterpret_cast<const uint32_t *>(rec), rb, vec);
 }
 
 // Only partitions [d_lo, d_lo + d_n) are written (a pass of the LDS engine over
