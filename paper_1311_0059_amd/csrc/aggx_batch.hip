@@ -172,8 +172,11 @@ __global__ void __launch_bounds__(1024) k_batch(BParams P) {
         __syncthreads();
         count_digits(I.in, it.lo, it.hi, ks, I.b, lh);
         __syncthreads();
-        for (uint32_t d = tid; d < F; d += blockDim.x)
+        uint32_t *cc = P.chunk_counts + I.cbase + (it.lo / I.chunk) * F;  // kept for the scatter item
+        for (uint32_t d = tid; d < F; d += blockDim.x) {
+          cc[d] = lh[d];
           if (lh[d]) __hip_atomic_fetch_add(P.totals + I.pbase + d, lh[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         __syncthreads();
         if (tid == 0) publish(P.cnt_done + it.inst);
         break;
@@ -204,9 +207,9 @@ __global__ void __launch_bounds__(1024) k_batch(BParams P) {
         __syncthreads();
         if (!s_ok) break;
         unsigned long long *lbase = reinterpret_cast<unsigned long long *>(lh + 4096);
-        for (uint32_t d = tid; d < F; d += blockDim.x) lh[d] = 0;
-        __syncthreads();
-        count_digits(I.in, it.lo, it.hi, ks, I.b, lh);
+        // the counts of this chunk, stored by its count item (published before the offsets)
+        const uint32_t *cc = P.chunk_counts + I.cbase + (it.lo / I.chunk) * F;
+        for (uint32_t d = tid; d < F; d += blockDim.x) lh[d] = cc[d];
         __syncthreads();
         for (uint32_t d = tid; d < F; d += blockDim.x) {
           if (lh[d])

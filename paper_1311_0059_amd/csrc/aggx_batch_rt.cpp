@@ -105,7 +105,7 @@ uint32_t part_bits(const agg_batch *b, uint64_t n, double G, uint64_t part_recor
 struct Layout {
   std::vector<BItem> items;
   std::vector<BInst> binst;
-  uint64_t n_parts = 0, pbuf_bytes = 0, out_total = 0;
+  uint64_t n_parts = 0, pbuf_bytes = 0, out_total = 0, n_ccounts = 0;
   uint32_t solo = 0, parted = 0;
   uint64_t partitions = 0;
 };
@@ -116,7 +116,7 @@ Layout build_layout(const agg_batch *b, const Cand &c) {
   const uint32_t n = (uint32_t)b->inst.size();
   L.binst.resize(n);
   std::vector<BItem> count, solo, offs, scat, agg;
-  uint64_t pbase = 0, pbuf = 0, out = 0;
+  uint64_t pbase = 0, pbuf = 0, out = 0, ccount = 0;
   for (uint32_t i = 0; i < n; ++i) {
     const agg_instance &in = b->inst[i];
     BInst &I = L.binst[i];
@@ -149,6 +149,9 @@ Layout build_layout(const agg_batch *b, const Cand &c) {
       pbuf += rup(in.n * b->ks.rb, 256);
       const uint64_t chunks = (in.n + c.chunk_records - 1) / c.chunk_records;
       I.nchunks = (uint32_t)chunks;
+      I.chunk = c.chunk_records;
+      I.cbase = ccount;
+      ccount += chunks * F;
       for (uint64_t k = 0; k < chunks; ++k) {
         const uint64_t lo = k * c.chunk_records, hi = std::min(in.n, lo + c.chunk_records);
         count.push_back({IT_COUNT, i, lo, hi});
@@ -171,6 +174,7 @@ Layout build_layout(const agg_batch *b, const Cand &c) {
   L.n_parts = pbase;
   L.pbuf_bytes = pbuf;
   L.out_total = out;
+  L.n_ccounts = ccount;
   return L;
 }
 
@@ -245,19 +249,20 @@ agg_status agg_batch_create(const agg_spec *spec, const agg_instance *inst, uint
     b->st.records += inst[i].n;
   }
   // buffers sized for the largest candidate layout
-  uint64_t n_parts = 0, pbuf = 0, outt = 0, n_items = 0;
+  uint64_t n_parts = 0, pbuf = 0, outt = 0, n_items = 0, n_cc = 0;
   std::vector<Layout> lays;
   for (const Cand &c : kCands) {
     lays.push_back(build_layout(b, c));
     const Layout &L = lays.back();
     n_parts = std::max(n_parts, L.n_parts);
+    n_cc = std::max(n_cc, L.n_ccounts);
     pbuf = std::max(pbuf, L.pbuf_bytes);
     outt = std::max(outt, L.out_total);
     n_items = std::max<uint64_t>(n_items, L.items.size());
   }
   const uint64_t ninst = std::max<uint32_t>(n_inst, 1);
   // work block: head, err | 3 done counters, ovf (u32) | rows (u64) | totals (u32) | cursors, offsets (u64) |
-  // items | instance table
+  // items | instance table | per-item partition counts (u32)
   uint64_t off = 0;
   auto carve = [&](uint64_t bytes) {
     const uint64_t at = off;
@@ -267,7 +272,7 @@ agg_status agg_batch_create(const agg_spec *spec, const agg_instance *inst, uint
   const uint64_t o_head = carve(256), o_done = carve(16 * ninst), o_rows = carve(8 * ninst),
                  o_tot = carve(4 * std::max<uint64_t>(n_parts, 1)), o_cur = carve(8 * std::max<uint64_t>(n_parts, 1)),
                  o_offs = carve(8 * (n_parts + ninst)), o_items = carve(sizeof(BItem) * std::max<uint64_t>(n_items, 1)),
-                 o_inst = carve(sizeof(BInst) * ninst);
+                 o_inst = carve(sizeof(BInst) * ninst), o_cc = carve(4 * std::max<uint64_t>(n_cc, 1));
   if (hipMalloc(&b->work, off) != hipSuccess) return bail(AGG_E_NOMEM);
   if (pbuf && hipMalloc(&b->pbuf, pbuf) != hipSuccess) return bail(AGG_E_NOMEM);
   b->out_total = outt;
@@ -292,6 +297,7 @@ agg_status agg_batch_create(const agg_spec *spec, const agg_instance *inst, uint
   P.offsets = (unsigned long long *)(w + o_offs);
   P.items = (const BItem *)(w + o_items);
   P.inst = (const BInst *)(w + o_inst);
+  P.chunk_counts = (uint32_t *)(w + o_cc);
   P.out_keys = (uint64_t *)b->outb;
   for (uint32_t a = 0; a < spec->n_aggs; ++a) P.out_cols.c[a] = (int64_t *)((uint8_t *)b->outb + colb * (1 + a));
 

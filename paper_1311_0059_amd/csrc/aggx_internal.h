@@ -110,6 +110,8 @@ struct BInst {
   uint64_t pbase;      // first entry of the instance in the per-partition arrays
   uint64_t out_base;   // first row of the instance in the output columns
   uint64_t out_cap;    // rows reserved for it
+  uint64_t chunk;      // records per count / scatter item (partitioned instances)
+  uint64_t cbase;      // first entry of its per-item partition counts (nchunks rows of 2^b)
 };
 
 struct BParams {
@@ -125,6 +127,7 @@ struct BParams {
   uint32_t *cnt_done, *offs_done, *scat_done, *ovf;
   unsigned long long *rows;
   uint32_t *totals;
+  uint32_t *chunk_counts;    // each count item's partition counts, read again by its scatter item
   unsigned long long *cursors, *offsets;
   uint64_t *out_keys;
   OutCols out_cols;
