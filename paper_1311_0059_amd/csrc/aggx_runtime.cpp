@@ -577,9 +577,11 @@ agg_status run_stream(agg_handle *h, const uint8_t *in, uint64_t n, int kind) {
     if (!h->next.reserve(c * in_bytes, &dst)) return AGG_E_NOMEM;
     HCK(h, launch_u64_set(h->stream, kind == 0 ? &h->d_ctrl->raw_ctr : &h->d_ctrl->state_ctr, 1, 0));
     KSpill sp = spill_target(h, kind == 0 ? dst : nullptr, kind == 0 ? nullptr : dst);
+    const bool preagg = h->preagg > 0 && h->plan.arena_slots < (1ull << 32);
+    if (preagg) h->st.preagg = 1;
     HCK(h, hipEventRecord(h->ev0, h->stream));
     HCK(h, launch_update(h->stream, kind, in + off * in_bytes, c, h->ks, lv, h->d_meta, h->d_cnt, h->d_ovf,
-                         h->d_arena, h->d_ctrl, sp, h->preagg > 0 && h->plan.arena_slots < (1ull << 32)));
+                         h->d_arena, h->d_ctrl, sp, preagg));
     HCK(h, hipEventRecord(h->ev1, h->stream));
     agg_status s = read_ctrl(h);
     if (s) return s;
@@ -1345,7 +1347,6 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     h->hot_key = ns >= 256 && h->h_ctrl->sample_max * 50 > ns;
     h->sample_sorted = ns >= 2 && h->h_ctrl->sample_unsorted == 0;
   }
-  h->st.preagg = h->preagg > 0 ? 1u : 0u;
   h->st.records_in += n;
   if (h->engine == 0 &&
       (h->spec.engine == AGG_ENGINE_SORTED || (h->spec.engine == AGG_ENGINE_AUTO && h->sample_sorted))) {
