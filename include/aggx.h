@@ -174,6 +174,9 @@ typedef struct agg_stats {
                                    fits the budget (0 = not used) */
   uint64_t scatter_launches;    /* LDS engine: launches of its scatter kernel (one per pass) */
   double scatter_ms;            /* their summed duration */
+  uint32_t lds_hot_keys;        /* LDS engine: frequent keys aggregated apart from the partitions (their
+                                   records are folded while the batch is counted; one row each) */
+  uint32_t reserved1;           /* zero */
 } agg_stats;
 
 /* Validate and copy `spec`, reserve the working budget (or adopt the caller's

@@ -82,6 +82,8 @@ class Stats(ctypes.Structure):
         ("lds_passes", ctypes.c_uint32),
         ("scatter_launches", ctypes.c_uint64),
         ("scatter_ms", ctypes.c_double),
+        ("lds_hot_keys", ctypes.c_uint32),
+        ("reserved1", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:

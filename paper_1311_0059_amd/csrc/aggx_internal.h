@@ -67,6 +67,9 @@ struct PartMeta {
 };
 
 // Control block in device memory (inside the working budget).
+constexpr uint32_t kMaxHot = 64;  // keys the sampler can report as frequent
+constexpr uint32_t kHotMin = 3;    // occurrences in the 2048-record sample that make a key frequent
+
 struct Ctrl {
   unsigned long long raw_ctr;     // records appended to the current raw spill region
   unsigned long long state_ctr;   // states appended to the current state spill region
@@ -78,6 +81,17 @@ struct Ctrl {
   unsigned long long sample_unsorted;  // skew sampling: 1 if the sampled keys are not in non-decreasing order
   unsigned long long unsorted;     // sorted-run path: 1 if the batch is not in non-decreasing key order
   unsigned long long side[2][kMaxAggs];  // their side groups' aggregates
+  unsigned long long sample_hot_n;        // keys seen at least kHotMin times in the sample (at most kMaxHot)
+  unsigned long long sample_hot[kMaxHot];  // those keys (never a reserved value)
+};
+
+// Frequent keys taken out of the LDS engine's partitioning: they are folded
+// into per-workgroup LDS accumulators while the batch is counted, and each
+// becomes one result row.  n == 0: none.
+struct KHot {
+  const unsigned long long *keys;  // n keys (device)
+  uint32_t n;
+  uint64_t *acc;                   // n x na accumulators, AoS (device, identity-initialised)
 };
 
 // Output columns of the flush kernel (passed by value).
@@ -149,7 +163,7 @@ hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint6
 // Among `ns` evenly spaced records (ns <= 2048): repeated keys, the largest key
 // multiplicity, and whether the sampled keys are out of order (out[0..2]).
 hipError_t launch_sample_dups(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t ns,
-                              unsigned long long *out);
+                              Ctrl *ctrl);
 hipError_t launch_flush(hipStream_t s, const uint64_t *arena, uint64_t nslots, const KSpec &ks, uint64_t *out_keys,
                         const OutCols &out_cols, uint64_t out_cap, Ctrl *ctrl);
 hipError_t launch_u64_set(hipStream_t s, unsigned long long *p, uint32_t n, unsigned long long v);
@@ -165,12 +179,17 @@ hipError_t launch_digit_scatter(hipStream_t s, int kind, const uint8_t *in, uint
                                 uint32_t shift, uint32_t mask, unsigned long long *cursor, uint8_t *out);
 // Partition-first LDS engine.
 hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
-                             uint32_t mask, uint64_t chunk, uint32_t *totals, uint32_t *block_counts);
+                             uint32_t mask, uint64_t chunk, uint32_t *totals, uint32_t *block_counts,
+                             const KHot &hot);
 hipError_t launch_part_offsets(hipStream_t s, const uint32_t *totals, uint32_t F, unsigned long long *offsets,
                                unsigned long long *cursors);
 hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
                                uint32_t mask, uint32_t d_lo, uint32_t d_n, uint64_t chunk,
-                               const uint32_t *block_counts, unsigned long long *cursors, uint8_t *out);
+                               const uint32_t *block_counts, const KHot &hot, unsigned long long *cursors,
+                               uint8_t *out);
+hipError_t launch_hot_init(hipStream_t s, const KHot &hot, const KSpec &ks);
+hipError_t launch_hot_rows(hipStream_t s, const KHot &hot, const KSpec &ks, uint64_t *out_keys,
+                           const OutCols &out_cols);
 hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long long *offsets, uint32_t F,
                           const KSpec &ks, uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots, uint32_t cap,
                           uint32_t lds_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys, const OutCols &out_cols,

@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, 
 // hot-key cache on when keys repeat, and keeps skewed inputs (one key holding
 // a large share) away from the partition-per-workgroup engine.
 __global__ void __launch_bounds__(256) k_sample_dups(const uint8_t *__restrict__ in, uint64_t n, KSpec ks, uint32_t ns,
-                                                     unsigned long long *out) {
+                                                     Ctrl *ctrl) {
   __shared__ unsigned long long set[4096];
   __shared__ uint32_t cnt[4096];
   __shared__ uint32_t dups, maxc;
@@ -212,11 +212,25 @@ __global__ void __launch_bounds__(256) k_sample_dups(const uint8_t *__restrict__
     const uint64_t b = read_key(in + ((uint64_t)(j + 1) * n / ns) * ks.rb, ks);
     if (b < a) atomicAdd(&descents, 1u);
   }
+  // the frequent keys (at least kHotMin samples), most frequent first: one scan
+  // per band of counts, while there is room
+  __shared__ uint32_t nhot;
+  if (threadIdx.x == 0) nhot = 0;
   __syncthreads();
+  const uint32_t bands[5] = {~0u, 64, 16, 6, kHotMin};
+  for (int band = 1; band < 5; ++band) {
+    for (uint32_t e = threadIdx.x; e < 4096; e += blockDim.x) {
+      if (set[e] >= kClosed || cnt[e] < bands[band] || cnt[e] >= bands[band - 1]) continue;
+      const uint32_t pos = atomicAdd(&nhot, 1u);
+      if (pos < kMaxHot) ctrl->sample_hot[pos] = set[e];
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    out[0] = dups;
-    out[1] = maxc;
-    out[2] = descents ? 1 : 0;
+    ctrl->sample_dups = dups;
+    ctrl->sample_max = maxc;
+    ctrl->sample_unsorted = descents ? 1 : 0;
+    ctrl->sample_hot_n = nhot < kMaxHot ? nhot : kMaxHot;
   }
 }
 
@@ -476,8 +490,8 @@ hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint6
 }
 
 hipError_t launch_sample_dups(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t ns,
-                              unsigned long long *out) {
-  hipLaunchKernelGGL(k_sample_dups, dim3(1), dim3(256), 0, s, in, n, ks, ns, out);
+                              Ctrl *ctrl) {
+  hipLaunchKernelGGL(k_sample_dups, dim3(1), dim3(256), 0, s, in, n, ks, ns, ctrl);
   return hipGetLastError();
 }
 

@@ -24,32 +24,97 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t key, uint32_t shift, uint3
   return mask ? (uint32_t)(fmix64(key ^ kSeed0) >> shift) & mask : 0u;
 }
 
+// The frequent keys in LDS: an open-addressing set of 128 slots mapping a key to
+// its index in KHot.  Built by the whole block; hot keys are never reserved values.
+constexpr uint32_t kHotSlots = 128;
+
+__device__ __forceinline__ void hot_build(const KHot &hot, unsigned long long *hk, uint32_t *hid) {
+  for (uint32_t e = threadIdx.x; e < kHotSlots; e += blockDim.x) hk[e] = kEmpty;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < hot.n; i += blockDim.x) {
+    const unsigned long long key = hot.keys[i];
+    uint32_t e = (uint32_t)(fmix64(key ^ kSeed0) >> 57);
+    for (uint32_t t = 0; t < kHotSlots; ++t) {
+      if (atomicCAS(&hk[e], (unsigned long long)kEmpty, key) == kEmpty) {
+        hid[e] = i;
+        break;
+      }
+      e = (e + 1) & (kHotSlots - 1);
+    }
+  }
+  __syncthreads();
+}
+
+// Index of `key` among the frequent keys, or -1.  The reserved key values are
+// never frequent keys (and kEmpty marks the set's free slots).
+__device__ __forceinline__ int hot_find(const unsigned long long *hk, const uint32_t *hid, uint64_t key) {
+  if (key >= kClosed) return -1;
+  uint32_t e = (uint32_t)(fmix64(key ^ kSeed0) >> 57);
+  for (uint32_t t = 0; t < kHotSlots; ++t) {
+    const unsigned long long k = hk[e];
+    if (k == key) return (int)hid[e];
+    if (k == kEmpty) return -1;
+    e = (e + 1) & (kHotSlots - 1);
+  }
+  return -1;
+}
+
 // Pass 1: records per partition.  Each block takes a contiguous chunk, counts
 // digits in LDS and adds its counts to the per-partition totals.  Each thread
 // reads four keys before it counts them, so that their loads are in flight
 // together (the chunks are long and the blocks few).  With `block_counts`, the
 // block also stores its counts (one row of mask+1 per block), so that a scatter
-// over the same chunks need not count again.
+// over the same chunks need not count again.  Records of the frequent keys in
+// `hot` are not counted: they are folded into the block's LDS accumulators,
+// which are added to the global ones at the end.
 __global__ void __launch_bounds__(kPartBlock) k_part_count(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
                                                            uint32_t shift, uint32_t mask, uint64_t chunk,
-                                                           uint32_t *totals, uint32_t *block_counts) {
+                                                           uint32_t *totals, uint32_t *block_counts, KHot hot) {
   extern __shared__ uint32_t lh[];
+  __shared__ unsigned long long hk[kHotSlots];
+  __shared__ uint32_t hid[kHotSlots], hseen[kMaxHot];
+  __shared__ unsigned long long hacc[kMaxAggs * kMaxHot];
   for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) lh[b] = 0;
+  if (hot.n) {
+    for (uint32_t i = threadIdx.x; i < hot.n; i += blockDim.x) {
+      hseen[i] = 0;
+      for (uint32_t a = 0; a < ks.na; ++a) hacc[a * kMaxHot + i] = identity_of(ks.agg[a]);
+    }
+    hot_build(hot, hk, hid);
+  }
   __syncthreads();
   const uint64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n, B = blockDim.x;
+  // count one record, or fold it into its frequent key's accumulators
+  auto take = [&](const uint8_t *rec, uint64_t key) {
+    const int x = hot.n ? hot_find(hk, hid, key) : -1;
+    if (x < 0) {
+      atomicAdd(&lh[digit_of(key, shift, mask)], 1u);
+    } else {
+      uint64_t vals[kMaxAggs];
+      in_vals<0>(rec, ks, vals);
+      fold_lds(reinterpret_cast<uint64_t *>(hacc) + x, kMaxHot, ks, vals);
+      hseen[x] = 1;
+    }
+  };
   uint64_t i = lo + threadIdx.x;
   for (; i + 3 * B < hi; i += 4 * B) {
     uint64_t k[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) k[u] = read_key(in + (i + u * B) * ks.rb, ks);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) atomicAdd(&lh[digit_of(k[u], shift, mask)], 1u);
+    for (int u = 0; u < 4; ++u) take(in + (i + u * B) * ks.rb, k[u]);
   }
-  for (; i < hi; i += B) atomicAdd(&lh[digit_of(read_key(in + i * ks.rb, ks), shift, mask)], 1u);
+  for (; i < hi; i += B) take(in + i * ks.rb, read_key(in + i * ks.rb, ks));
   __syncthreads();
   for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) {
     if (lh[b]) __hip_atomic_fetch_add(totals + (uint64_t)b * kCntStride, lh[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (block_counts) block_counts[(uint64_t)blockIdx.x * (mask + 1) + b] = lh[b];
+  }
+  for (uint32_t x = threadIdx.x; x < hot.n; x += blockDim.x) {
+    if (!hseen[x]) continue;
+    uint64_t vals[kMaxAggs];
+    for (uint32_t a = 0; a < ks.na; ++a) vals[a] = hacc[a * kMaxHot + x];
+    fold_global(hot.acc + (uint64_t)x * ks.na, ks, vals);
   }
 }
 
@@ -91,10 +156,19 @@ __device__ __forceinline__ void scatter_one(const uint8_t *rec, uint32_t d, uint
 __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
                                                              uint32_t shift, uint32_t mask, uint32_t d_lo,
                                                              uint32_t d_n, uint64_t chunk,
-                                                             const uint32_t *__restrict__ block_counts,
+                                                             const uint32_t *__restrict__ block_counts, KHot hot,
                                                              unsigned long long *cursors, uint8_t *out, uint32_t vec) {
-  extern __shared__ uint32_t lc[];  // d_n counts, then d_n bases (record indices below 2^32)
+  // d_n counts, d_n bases (record indices below 2^32), then the frequent-key set
+  extern __shared__ uint32_t lc[];
   uint32_t *lbase = lc + d_n;
+  unsigned long long *hk = reinterpret_cast<unsigned long long *>(lc + 2 * d_n);
+  uint32_t *hid = reinterpret_cast<uint32_t *>(hk + kHotSlots);
+  if (hot.n) hot_build(hot, hk, hid);
+  // the digit relative to d_lo; frequent keys (and digits out of range) give d_n or more
+  const auto rel_digit = [&](uint64_t key) -> uint32_t {
+    if (hot.n && hot_find(hk, hid, key) >= 0) return d_n;
+    return digit_of(key, shift, mask) - d_lo;
+  };
   const uint64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n, B = blockDim.x;
   uint64_t i = lo + threadIdx.x;
   if (block_counts) {
@@ -112,12 +186,12 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
     for (int u = 0; u < 4; ++u) k[u] = read_key(in + (i + u * B) * ks.rb, ks);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const uint32_t d = digit_of(k[u], shift, mask) - d_lo;
+      const uint32_t d = rel_digit(k[u]);
       if (d < d_n) atomicAdd(&lc[d], 1u);
     }
   }
   for (; i < hi; i += B) {
-    const uint32_t d = digit_of(read_key(in + i * ks.rb, ks), shift, mask) - d_lo;
+    const uint32_t d = rel_digit(read_key(in + i * ks.rb, ks));
     if (d < d_n) atomicAdd(&lc[d], 1u);
   }
   __syncthreads();
@@ -133,14 +207,14 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
   for (; i + 3 * B < hi; i += 4 * B) {
     uint32_t d[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) d[u] = digit_of(read_key(in + (i + u * B) * ks.rb, ks), shift, mask) - d_lo;
+    for (int u = 0; u < 4; ++u) d[u] = rel_digit(read_key(in + (i + u * B) * ks.rb, ks));
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (d[u] < d_n) scatter_one(in + (i + u * B) * ks.rb, d[u], ks.rb, vec, lc, lbase, out);
   }
   for (; i < hi; i += B) {
     const uint8_t *rec = in + i * ks.rb;
-    const uint32_t d = digit_of(read_key(rec, ks), shift, mask) - d_lo;
+    const uint32_t d = rel_digit(read_key(rec, ks));
     if (d < d_n) scatter_one(rec, d, ks.rb, vec, lc, lbase, out);
   }
 }
@@ -317,11 +391,13 @@ __global__ void __launch_bounds__(256) k_merge_rows(const uint64_t *__restrict__
 }
 
 hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
-                             uint32_t mask, uint64_t chunk, uint32_t *totals, uint32_t *block_counts) {
+                             uint32_t mask, uint64_t chunk, uint32_t *totals, uint32_t *block_counts,
+                             const KHot &hot) {
   if (n == 0) return hipSuccess;
+  if (hot.n > kMaxHot) return hipErrorInvalidValue;
   const uint64_t blocks = (n + chunk - 1) / chunk;
   hipLaunchKernelGGL(k_part_count, dim3((uint32_t)blocks), dim3(kPartBlock), 4ull * (mask + 1), s, in, n, ks, shift,
-                     mask, chunk, totals, block_counts);
+                     mask, chunk, totals, block_counts, hot);
   return hipGetLastError();
 }
 
@@ -354,17 +430,46 @@ static bool scatter_lds_allowed(size_t lds) {
 
 hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
                                uint32_t mask, uint32_t d_lo, uint32_t d_n, uint64_t chunk,
-                               const uint32_t *block_counts, unsigned long long *cursors, uint8_t *out) {
+                               const uint32_t *block_counts, const KHot &hot, unsigned long long *cursors,
+                               uint8_t *out) {
   if (n == 0 || d_n == 0) return hipSuccess;
+  if (hot.n > kMaxHot) return hipErrorInvalidValue;
   if (d_lo > mask || d_n > mask + 1 - d_lo) return hipErrorInvalidValue;
   const uint64_t blocks = (n + chunk - 1) / chunk;
   if (n >= (1ull << 32)) return hipErrorInvalidValue;  // the LDS bases are 32-bit record indices
-  const size_t lds = 8ull * d_n;
+  const size_t lds = 8ull * d_n + 12ull * kHotSlots;
   if (!scatter_lds_allowed(lds)) return hipErrorInvalidValue;
   const uintptr_t a = reinterpret_cast<uintptr_t>(out);
   const uint32_t vec = ks.rb % 16 == 0 && a % 16 == 0 ? 16 : ks.rb % 8 == 0 && a % 8 == 0 ? 8 : 4;
   hipLaunchKernelGGL(k_part_scatter, dim3((uint32_t)blocks), dim3(kPartBlock), lds, s, in, n, ks, shift, mask, d_lo,
-                     d_n, chunk, block_counts, cursors, out, vec);
+                     d_n, chunk, block_counts, hot, cursors, out, vec);
+  return hipGetLastError();
+}
+
+// Identity values for the frequent keys' accumulators, and their result rows.
+__global__ void k_hot_init(KHot hot, KSpec ks) {
+  for (uint32_t i = threadIdx.x; i < hot.n * ks.na; i += blockDim.x) hot.acc[i] = identity_of(ks.agg[i % ks.na]);
+}
+
+__global__ void k_hot_rows(KHot hot, KSpec ks, uint64_t *out_keys, OutCols out_cols) {
+  for (uint32_t i = threadIdx.x; i < hot.n; i += blockDim.x) {
+    out_keys[i] = hot.keys[i];
+    for (uint32_t a = 0; a < ks.na; ++a) out_cols.c[a][i] = (int64_t)hot.acc[(uint64_t)i * ks.na + a];
+  }
+}
+
+hipError_t launch_hot_init(hipStream_t s, const KHot &hot, const KSpec &ks) {
+  if (hot.n == 0) return hipSuccess;
+  if (hot.n > kMaxHot) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_hot_init, dim3(1), dim3(256), 0, s, hot, ks);
+  return hipGetLastError();
+}
+
+hipError_t launch_hot_rows(hipStream_t s, const KHot &hot, const KSpec &ks, uint64_t *out_keys,
+                           const OutCols &out_cols) {
+  if (hot.n == 0) return hipSuccess;
+  if (hot.n > kMaxHot) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_hot_rows, dim3(1), dim3(64), 0, s, hot, ks, out_keys, out_cols);
   return hipGetLastError();
 }
 

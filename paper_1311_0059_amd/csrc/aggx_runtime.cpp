@@ -239,6 +239,7 @@ struct agg_handle {
   uint64_t owner_m = 0;
   hipEvent_t ev_own[2 * kOwnerMaxSub] = {};
   int hot_key = 0;  // the sample showed one key with a large share of the records
+  uint32_t hot_n = 0;  // then: the frequent keys the LDS engine takes out of its partitions
   int sample_sorted = 0;  // the sampled keys were in non-decreasing order
   int state = H_OPEN;
   bool l0_done = false;  // level 0 flushed (agg_first_rows or agg_finish); no more batches
@@ -712,6 +713,7 @@ uint64_t part_chunk(uint64_t n) { return std::max<uint64_t>(1024, (n + 255) / 25
 // so that a low estimate does not make the tables overflow.
 bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
   const uint32_t rb = h->ks.rb;
+  if (n >= (1ull << 32)) return false;  // the scatter's partition bases are 32-bit record indices
   lp->lds_bytes = lds_agg_max_bytes();
   if (lp->lds_bytes < 256 * h->W8) return false;
   lp->nslots = (uint32_t)(lp->lds_bytes / h->W8) & ~3u;  // whole groups of four slots
@@ -755,7 +757,8 @@ bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
   // counters and cursors on their own 128-byte lines, offsets, packed counts, and
   // the count kernel's per-block counts (one row of F per block)
   const uint64_t blocks = (n + part_chunk(n) - 1) / part_chunk(n);
-  lp->aux_bytes = round_up(2ull * lp->F * 128 + 8ull * (lp->F + 1) + 4ull * lp->F, 256) + round_up(4ull * blocks * lp->F, 256);
+  lp->aux_bytes = round_up(2ull * lp->F * 128 + 8ull * (lp->F + 1) + 4ull * lp->F, 256) +
+                  round_up(4ull * blocks * lp->F, 256) + round_up(8ull * kMaxHot * h->ks.na, 256);
   lp->buf_bytes = round_up(n * rb, 256);
   lp->passes = false;
   if (!h->unlimited && lp->buf_bytes + lp->aux_bytes > h->arena_cap_bytes) {
@@ -790,6 +793,18 @@ uint32_t *lds_block_counts(uint8_t *arena, const LdsPlan &lp) {
                                       round_up(2ull * lp.F * 128 + 8ull * (lp.F + 1) + 4ull * lp.F, 256));
 }
 
+// The frequent keys taken out of the partitions (keys in the control block,
+// accumulators at the end of the engine's counters).
+KHot lds_hot(agg_handle *h, uint8_t *arena, const LdsPlan &lp, uint64_t n) {
+  KHot hot{};
+  hot.n = h->hot_n;
+  hot.keys = h->d_ctrl->sample_hot;
+  const uint64_t blocks = (n + part_chunk(n) - 1) / part_chunk(n);
+  hot.acc = reinterpret_cast<uint64_t *>(reinterpret_cast<uint8_t *>(lds_block_counts(arena, lp)) +
+                                         round_up(4ull * blocks * lp.F, 256));
+  return hot;
+}
+
 // Aggregate partitions [d_lo, d_lo + d_n) of the batch: scatter their records
 // into the buffer, aggregate each partition in LDS and append its groups to the
 // result; records of keys that found no room in their table go to the spill run.
@@ -804,7 +819,7 @@ agg_status lds_run_partitions(agg_handle *h, const uint8_t *in, uint64_t n, cons
   HCK(h, launch_part_offsets(h->stream, totals + (uint64_t)d_lo * kCntStride, d_n, offsets, cursors));
   HCK(h, hipEventRecord(h->ev2, h->stream));
   HCK(h, launch_part_scatter(h->stream, in, n, h->ks, shift, mask, d_lo, d_n, part_chunk(n), lds_block_counts(arena, lp),
-                             cursors, buf));
+                             lds_hot(h, arena, lp, n), cursors, buf));
   HCK(h, hipEventRecord(h->ev3, h->stream));
   uint8_t *dst = nullptr;
   if (!h->next.reserve(std::max<uint64_t>(records, 1) * h->ks.rb, &dst)) return AGG_E_NOMEM;
@@ -853,8 +868,11 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   uint32_t *totals = reinterpret_cast<uint32_t *>(arena + lp.buf_bytes);
   uint32_t *packed = reinterpret_cast<uint32_t *>(arena + lp.buf_bytes + 2ull * lp.F * 128 + 8ull * (lp.F + 1));
   const uint32_t shift = lp.b ? 64 - lp.b : 0, mask = lp.F - 1;
+  const KHot hot = lds_hot(h, arena, lp, n);
   HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)lp.F * kCntStride, 0));
-  HCK(h, launch_part_count(h->stream, in, n, h->ks, shift, mask, part_chunk(n), totals, lds_block_counts(arena, lp)));
+  HCK(h, launch_hot_init(h->stream, hot, h->ks));
+  HCK(h, launch_part_count(h->stream, in, n, h->ks, shift, mask, part_chunk(n), totals, lds_block_counts(arena, lp),
+                           hot));
   // runs of consecutive partitions, each fitting the buffer
   std::vector<std::pair<uint32_t, uint64_t>> runs;  // (first digit past the run, records)
   if (!lp.passes) {
@@ -884,6 +902,17 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
     if (s) return s;
     d_lo = r.first;
   }
+  if (hot.n) {
+    // one row per frequent key (each occurs in the batch: the sample read it there)
+    agg_status s = ensure_result_cap(h, h->r_rows + hot.n);
+    if (s) return s;
+    OutCols oc{};
+    for (uint32_t a = 0; a < h->spec.n_aggs; ++a) oc.c[a] = h->r_cols[a] + h->r_rows;
+    HCK(h, launch_hot_rows(h->stream, hot, h->ks, h->r_keys + h->r_rows, oc));
+    HCK(h, hipStreamSynchronize(h->stream));
+    h->r_rows += hot.n;
+  }
+  h->st.lds_hot_keys = hot.n;
   h->st.partitions = lp.F;
   h->st.lds_sweeps = 1u << lp.sbits;
   h->st.lds_passes = (uint32_t)runs.size();
@@ -992,9 +1021,10 @@ agg_status run_owner_stream(agg_handle *h, const uint8_t *in, uint64_t n) {
       const uint8_t *src = in + (off + so) * rb;
       const uint64_t chunk = part_chunk(c);
       HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)pl.F * kCntStride, 0));
-      HCK(h, launch_part_count(h->stream, src, c, h->ks, shift, mask, chunk, totals, nullptr));
+      HCK(h, launch_part_count(h->stream, src, c, h->ks, shift, mask, chunk, totals, nullptr, KHot{}));
       HCK(h, launch_part_offsets(h->stream, totals, pl.F, offsets, cursors));
-      HCK(h, launch_part_scatter(h->stream, src, c, h->ks, shift, mask, 0, mask + 1, chunk, nullptr, cursors, buf));
+      HCK(h, launch_part_scatter(h->stream, src, c, h->ks, shift, mask, 0, mask + 1, chunk, nullptr, KHot{}, cursors,
+                                 buf));
       HCK(h, hipEventRecord(h->ev_own[2 * subs], h->stream));
       HCK(h, launch_owner_update(h->stream, buf, offsets, pl.F, h->ks, lv, h->d_meta, h->d_cnt, h->d_ovf,
                                  h->d_arena, h->d_ctrl, sp));
@@ -1338,13 +1368,14 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     // the input: look for repeated keys in an evenly spaced sample of the first
     // batch (also when the tables were planned at creation).
     const uint32_t ns = (uint32_t)std::min<uint64_t>(n, 2048);  // the sampler's set has 4096 slots
-    HCK(h, launch_sample_dups(h->stream, (const uint8_t *)d_records, n, h->ks, ns, &h->d_ctrl->sample_dups));
+    HCK(h, launch_sample_dups(h->stream, (const uint8_t *)d_records, n, h->ks, ns, h->d_ctrl));
     agg_status s = read_ctrl(h);
     if (s) return s;
     // repeated keys in more than 5% of the sample: pre-aggregate; one key in more
     // than 2% of it: a hot key that would unbalance a partition-per-workgroup pass
     if (h->preagg < 0) h->preagg = ns >= 256 && h->h_ctrl->sample_dups * 20 > ns ? 1 : 0;
     h->hot_key = ns >= 256 && h->h_ctrl->sample_max * 50 > ns;
+    h->hot_n = h->hot_key ? (uint32_t)h->h_ctrl->sample_hot_n : 0;
     h->sample_sorted = ns >= 2 && h->h_ctrl->sample_unsorted == 0;
   }
   h->st.records_in += n;
@@ -1361,8 +1392,8 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     LdsPlan lp;
     const double G = h->spec.est_groups ? (double)h->spec.est_groups : (double)n;
     if ((h->spec.engine == AGG_ENGINE_AUTO || h->spec.engine == AGG_ENGINE_LDS) &&
-        (h->spec.engine == AGG_ENGINE_LDS || (!h->hot_key && h->spec.preagg != 1)) &&
-        n * h->ks.rb <= kLdsMaxInput && lds_plan(h, n, G, &lp)) {
+        (h->spec.engine == AGG_ENGINE_LDS || ((!h->hot_key || h->hot_n > 0) && h->spec.preagg != 1)) &&
+        (n * h->ks.rb <= kLdsMaxInput || !h->unlimited) && lds_plan(h, n, G, &lp)) {
       bool applied = false;
       agg_status s = run_lds(h, (const uint8_t *)d_records, n, lp, &applied);
       if (s || applied) {
