@@ -18,7 +18,8 @@ constexpr uint64_t kClosed = ~0ULL - 1;
 constexpr int kMaxAggs = 8;
 constexpr int kMaxFanBits = 12;
 constexpr uint32_t kMaxFan = 1u << kMaxFanBits;
-constexpr int kLdsMaxFanBits = 13;  // partition-first LDS engine: its partitions need no per-partition tables
+constexpr int kLdsMaxFanBits = 14;  // partition-first LDS engine: its partitions need no per-partition tables
+constexpr int kLdsPlanFanBits = 13; // it plans for at least the groups this many one-sweep partitions hold
 constexpr uint32_t kLdsBlock = 1024;    // threads per workgroup of the LDS aggregation kernel
 // Per-partition group counters are updated with device-scope atomics on every
 // insert; each gets its own 128-byte line so that partitions never serialize

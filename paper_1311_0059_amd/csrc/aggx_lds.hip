@@ -390,12 +390,36 @@ __global__ void __launch_bounds__(256) k_merge_rows(const uint64_t *__restrict__
   }
 }
 
+// The count and scatter kernels' LDS grows with the fan-out (4 and 8 bytes per
+// partition); above 64 KB a kernel must be allowed more, once per device and
+// kernel, under a lock.
+static bool kernel_lds_allowed(const void *fn, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void *>, size_t> allowed;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(mu);
+  size_t &a = allowed[{dev, fn}];
+  if (a < 65536) a = 65536;
+  if (lds <= a) return true;
+  if (lds > 160 * 1024 - 1024 ||
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  a = lds;
+  return true;
+}
+
 hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
                              uint32_t mask, uint64_t chunk, uint32_t *totals, uint32_t *block_counts,
                              const KHot &hot) {
   if (n == 0) return hipSuccess;
   if (hot.n > kMaxHot) return hipErrorInvalidValue;
   const uint64_t blocks = (n + chunk - 1) / chunk;
+  // (its frequent-key arrays take another ~6 KB of static LDS)
+  if (!kernel_lds_allowed(reinterpret_cast<const void *>(k_part_count), 4ull * (mask + 1) + 6144))
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_part_count, dim3((uint32_t)blocks), dim3(kPartBlock), 4ull * (mask + 1), s, in, n, ks, shift,
                      mask, chunk, totals, block_counts, hot);
   return hipGetLastError();
@@ -405,27 +429,6 @@ hipError_t launch_part_offsets(hipStream_t s, const uint32_t *totals, uint32_t F
                                unsigned long long *cursors) {
   hipLaunchKernelGGL(k_part_offsets, dim3(1), dim3(256), 0, s, totals, F, offsets, cursors);
   return hipGetLastError();
-}
-
-// The scatter's LDS grows with the fan-out (8 bytes per partition); above
-// 64 KB the kernel must be allowed more, once per device, under a lock.
-static bool scatter_lds_allowed(size_t lds) {
-  static std::mutex mu;
-  static std::map<int, size_t> allowed;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return false;
-  std::lock_guard<std::mutex> lk(mu);
-  size_t &a = allowed[dev];
-  if (a < 65536) a = 65536;
-  if (lds <= a) return true;
-  if (lds > 160 * 1024 - 1024 ||
-      hipFuncSetAttribute(reinterpret_cast<const void *>(k_part_scatter), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  a = lds;
-  return true;
 }
 
 hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
@@ -438,7 +441,7 @@ hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, con
   const uint64_t blocks = (n + chunk - 1) / chunk;
   if (n >= (1ull << 32)) return hipErrorInvalidValue;  // the LDS bases are 32-bit record indices
   const size_t lds = 8ull * d_n + 12ull * kHotSlots;
-  if (!scatter_lds_allowed(lds)) return hipErrorInvalidValue;
+  if (!kernel_lds_allowed(reinterpret_cast<const void *>(k_part_scatter), lds)) return hipErrorInvalidValue;
   const uintptr_t a = reinterpret_cast<uintptr_t>(out);
   const uint32_t vec = ks.rb % 16 == 0 && a % 16 == 0 ? 16 : ks.rb % 8 == 0 && a % 8 == 0 ? 8 : 4;
   hipLaunchKernelGGL(k_part_scatter, dim3((uint32_t)blocks), dim3(kPartBlock), lds, s, in, n, ks, shift, mask, d_lo,

@@ -704,7 +704,7 @@ uint64_t part_chunk(uint64_t n) { return std::max<uint64_t>(1024, (n + 255) / 25
 
 // Can the batch be aggregated partition by partition in LDS?  Each partition's
 // expected groups (plus four standard deviations) must fit one workgroup's LDS
-// table, with at most 2^13 partitions, or else the groups of one sweep of it
+// table, with at most 2^14 partitions, or else the groups of one sweep of it
 // (at most four sweeps).  The working budget holds the partition counters and a
 // buffer for the partitioned batch, or, when the batch is larger, for a run of
 // consecutive partitions: the batch is then read once per run (at most
@@ -735,7 +735,7 @@ bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
       one_sweep = lo;
     }
     G = std::min(G, (double)n);
-    G = std::max(G, std::min((double)n, one_sweep * (double)(1u << kLdsMaxFanBits)));
+    G = std::max(G, std::min((double)n, one_sweep * (double)(1u << kLdsPlanFanBits)));
   }
   const auto fits = [&](uint32_t bits) { return fits_groups(G / (double)(1ull << bits)); };
   while (b <= bmax && !fits(b)) ++b;
@@ -744,7 +744,7 @@ bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
     b = bmax;
     while (sbits <= kLdsMaxSweepBits && !fits(b + sbits)) ++sbits;
     if (sbits > kLdsMaxSweepBits) {
-      // more groups than four sweeps of 2^13 tables hold: with an automatic fan-out
+      // more groups than four sweeps of 2^14 tables hold: with an automatic fan-out
       // take the largest plan anyway (the estimate is an upper bound, and keys that
       // find no room spill and recurse as with any full table)
       if (h->spec.fanout_bits) return false;
