@@ -80,26 +80,40 @@ __device__ void lds_aggregate(const uint8_t *in, uint64_t lo, uint64_t hi, const
   __syncthreads();
   bool bad = false;
   // insert one record's key (or find it) and fold its values; false if it found no room.
-  // The fold follows the probe loop, so that a wave runs it once whatever slot each lane found.
+  // Linear probing over groups of four slots (nslots is a multiple of four), whose keys
+  // come in two 16-byte reads.  The fold follows the probe loop, so that a wave runs it
+  // once whatever slot each lane found.
   auto fold_one = [&](uint64_t key, const uint64_t *vals) -> bool {
-    uint32_t idx = (uint32_t)mulhi64(fmix64(key ^ kSeed0) << slot_shift, nslots);
+    const uint32_t ng = nslots / 4;
+    uint32_t g = (uint32_t)mulhi64(fmix64(key ^ kSeed0) << slot_shift, ng);
     uint32_t slot = ~0u;
-    for (uint32_t t = 0; t < nslots; ++t) {
-      unsigned long long sk = t_key[idx];
-      if (sk == kEmpty) {
-        if (*s_groups >= P.cap) break;
-        sk = atomicCAS(reinterpret_cast<unsigned long long *>(t_key + idx), (unsigned long long)kEmpty,
-                       (unsigned long long)key);
+    bool stop = false;
+    for (uint32_t t = 0; t < ng && !stop; ++t) {
+      const ulonglong2 *gk = reinterpret_cast<const ulonglong2 *>(t_key + 4 * g);
+      const ulonglong2 k01 = gk[0], k23 = gk[1];
+      const unsigned long long kv[4] = {k01.x, k01.y, k23.x, k23.y};
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) {
+        if (stop) break;
+        unsigned long long sk = kv[j];
         if (sk == kEmpty) {
-          atomicAdd(s_groups, 1u);
-          sk = key;
+          if (*s_groups >= P.cap) {
+            stop = true;
+            break;
+          }
+          sk = atomicCAS(reinterpret_cast<unsigned long long *>(t_key + 4 * g + j), (unsigned long long)kEmpty,
+                         (unsigned long long)key);
+          if (sk == kEmpty) {
+            atomicAdd(s_groups, 1u);
+            sk = key;
+          }
+        }
+        if (sk == key) {
+          slot = 4 * g + j;
+          stop = true;
         }
       }
-      if (sk == key) {
-        slot = idx;
-        break;
-      }
-      idx = idx + 1 == nslots ? 0 : idx + 1;
+      g = g + 1 == ng ? 0 : g + 1;
     }
     if (slot == ~0u) return false;
     fold_lds(t_acc + slot, nslots, ks, vals);

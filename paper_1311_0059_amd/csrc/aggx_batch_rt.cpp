@@ -239,7 +239,7 @@ agg_status agg_batch_create(const agg_spec *spec, const agg_instance *inst, uint
     b->lds_bytes = 64 * 1024;
     (void)batch_lds_setup(b->lds_bytes);
   }
-  b->nslots = b->lds_bytes / b->W8;
+  b->nslots = (b->lds_bytes / b->W8) & ~3u;  // whole groups of four slots
   b->cap = (uint32_t)(b->nslots * kLoad);
   b->blocks = (uint32_t)batch_resident_blocks(kBlock, b->lds_bytes);
   b->st.blocks = b->blocks;

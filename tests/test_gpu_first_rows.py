@@ -62,6 +62,17 @@ def test_first_rows_with_spill(engine, policy):
     assert st["engine"] == (3 if engine == "owner" else 1)
 
 
+def test_first_rows_with_frequent_keys():
+    """Zipf keys on the LDS engine: the frequent keys' rows are final at level 0 too."""
+    wl = workloads.Workload("zipf-first", "R16", 1_200_000, 100_000, datagen.ZIPF, 1.2, -10**6, 10**6,
+                            workloads.AGGS_R16_ALL, 0, workloads.SEED_BASE + 41)
+    rec = wl.generate()
+    print("case: first rows with frequent keys", flush=True)
+    fk, fc, k, c, st = _run(rec, wl, 0, "auto")
+    _check(rec, wl, fk, fc, k, c, "first rows frequent keys")
+    assert st["engine"] == 2 and st["lds_hot_keys"] > 0 and fk.size == k.size
+
+
 @pytest.mark.parametrize("engine", ["lds", "sorted"])
 def test_first_rows_without_spill(engine):
     wl = workloads.uniform_spill().scaled(600_000, 50_000)
