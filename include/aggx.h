@@ -176,7 +176,8 @@ typedef struct agg_stats {
   double scatter_ms;            /* their summed duration */
   uint32_t lds_hot_keys;        /* LDS engine: frequent keys aggregated apart from the partitions (their
                                    records are folded while the batch is counted; one row each) */
-  uint32_t reserved1;           /* zero */
+  uint32_t lds_narrow;          /* LDS engine: 1 when its tables kept COUNT and MIN/MAX of 32-bit fields in
+                                   4-byte columns (chosen when that saves sweeps or partitions) */
 } agg_stats;
 
 /* Validate and copy `spec`, reserve the working budget (or adopt the caller's

@@ -83,7 +83,7 @@ class Stats(ctypes.Structure):
         ("scatter_launches", ctypes.c_uint64),
         ("scatter_ms", ctypes.c_double),
         ("lds_hot_keys", ctypes.c_uint32),
-        ("reserved1", ctypes.c_uint32),
+        ("lds_narrow", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:

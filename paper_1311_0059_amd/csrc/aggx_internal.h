@@ -47,6 +47,20 @@ struct KSpec {
   uint32_t agg[kMaxAggs];
 };
 
+// The partition engine's LDS tables can keep an aggregate in 4 bytes where its
+// value always fits: COUNT (one sweep of a partition sees fewer than 2^32
+// records) and MIN/MAX of a 32-bit field; every other aggregate takes 8.  Rows
+// widen them to int64.  Narrow columns let a table hold more groups in the same
+// LDS; a table with `narrow` false keeps every column in 8 bytes.
+__host__ __device__ inline bool lds_narrow(uint32_t d) {
+  return desc_op(d) == OP_COUNT || (desc_op(d) >= OP_MIN && (desc_type(d) == T_U32 || desc_type(d) == T_I32));
+}
+__host__ __device__ inline uint32_t lds_slot_bytes(const KSpec &ks, bool narrow) {
+  uint32_t w = 8;  // the key
+  for (uint32_t a = 0; a < ks.na; ++a) w += narrow && lds_narrow(ks.agg[a]) ? 4 : 8;
+  return w;
+}
+
 // One hybrid-hash pass ("level"): which digit of the hash selects the
 // partition, and the seed of the slot hash.
 struct KLevel {
@@ -193,8 +207,8 @@ hipError_t launch_hot_rows(hipStream_t s, const KHot &hot, const KSpec &ks, uint
                            const OutCols &out_cols);
 hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long long *offsets, uint32_t F,
                           const KSpec &ks, uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots, uint32_t cap,
-                          uint32_t lds_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys, const OutCols &out_cols,
-                          uint64_t out_cap);
+                          bool narrow, uint32_t lds_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys,
+                          const OutCols &out_cols, uint64_t out_cap);
 hipError_t launch_merge_rows(hipStream_t s, const uint64_t *keys, const OutCols &cols, uint64_t n, const KSpec &ks,
                              const KLevel &lv, const PartMeta *meta, uint32_t *cnt, uint64_t *arena, Ctrl *ctrl,
                              KSpill spill);

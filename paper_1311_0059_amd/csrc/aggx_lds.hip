@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
 }
 
 // Pass 3: one workgroup per partition aggregates it in an LDS table of
-// `nslots` slots (keys, then one column per aggregate), with the same
+// `nslots` slots (keys, then one column per aggregate, 4 or 8 bytes a slot), with the same
 // insert-or-close protocol as the HBM tables: at most `cap` groups are
 // inserted; once the table is full, new keys close the empty slot they reach
 // and their records are spilled raw, so a key is either in the table for all
@@ -232,19 +232,71 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
 // their rows before the next sweep.  Each sweep re-reads the partition; that
 // costs less than a second partition pass over the whole batch.  The table's
 // slot index uses the hash bits below both digits (slot_shift).
+// The table's aggregate columns follow its nslots keys, column a taking 4 bytes
+// a slot where kNarrow and lds_narrow allow, else 8; f(a, descriptor, narrow,
+// column) runs for each.  (Tables without narrow columns are compiled apart:
+// the per-column width test costs the common case some speed.)
+template <bool kNarrow, typename Fn>
+__device__ __forceinline__ void for_lds_cols(const KSpec &ks, uint8_t *cols, uint32_t nslots, Fn f) {
+  uint32_t off = 0;  // LDS byte offsets fit 32 bits
+#pragma unroll
+  for (int a = 0; a < kMaxAggs; ++a) {
+    if (a >= (int)ks.na) break;
+    const uint32_t d = ks.agg[a];
+    const bool nw = kNarrow && lds_narrow(d);
+    f(a, d, nw, cols + off);
+    off += (nw ? 4u : 8u) * nslots;
+  }
+}
+
+// Identity of a 4-byte column (COUNT, or MIN/MAX of a 32-bit field).
+__device__ __forceinline__ uint32_t narrow_identity(uint32_t d) {
+  const bool sg = type_signed(desc_type(d));
+  switch (desc_op(d)) {
+    case OP_MIN: return sg ? 0x7fffffffu : 0xffffffffu;
+    case OP_MAX: return sg ? 0x80000000u : 0u;
+    default: return 0u;
+  }
+}
+
+// Fold one record's values into slot `e` of the table's columns.
+template <bool kNarrow>
+__device__ __forceinline__ void fold_lds_cols(uint8_t *cols, uint32_t nslots, uint32_t e, const KSpec &ks,
+                                              const uint64_t *vals) {
+  for_lds_cols<kNarrow>(ks, cols, nslots, [&](int a, uint32_t d, bool nw, uint8_t *c) {
+    const bool sg = type_signed(desc_type(d));
+    const uint64_t v = vals[a];
+    if (nw) {
+      uint32_t *w = reinterpret_cast<uint32_t *>(c) + e;
+      if (desc_op(d) <= OP_SUM) atomicAdd(w, (uint32_t)v);
+      else if (desc_op(d) == OP_MIN) sg ? (void)atomicMin(reinterpret_cast<int *>(w), (int)(uint32_t)v) : (void)atomicMin(w, (uint32_t)v);
+      else sg ? (void)atomicMax(reinterpret_cast<int *>(w), (int)(uint32_t)v) : (void)atomicMax(w, (uint32_t)v);
+    } else {
+      unsigned long long *w = reinterpret_cast<unsigned long long *>(c) + e;
+      if (desc_op(d) <= OP_SUM) atomicAdd(w, (unsigned long long)v);
+      else if (desc_op(d) == OP_MIN) sg ? (void)atomicMin(reinterpret_cast<long long *>(w), (long long)v) : (void)atomicMin(w, (unsigned long long)v);
+      else sg ? (void)atomicMax(reinterpret_cast<long long *>(w), (long long)v) : (void)atomicMax(w, (unsigned long long)v);
+    }
+  });
+}
+
 // One sweep of k_lds_agg over the partition's records [lo, hi).
+template <bool kNarrow>
 __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, uint64_t hi, const KSpec &ks,
                                               uint32_t slot_shift, uint32_t sweep_bits, uint32_t sweep,
                                               uint32_t nslots, uint32_t cap, Ctrl *ctrl, const KSpill &spill,
                                               uint64_t *out_keys, const OutCols &out_cols, uint64_t out_cap,
                                               uint64_t *t_key, uint32_t *s_groups, unsigned long long *s_base,
                                               uint32_t *scratch) {
-  uint64_t *t_acc = t_key + nslots;
+  uint8_t *t_cols = reinterpret_cast<uint8_t *>(t_key + nslots);
   const uint32_t tid = threadIdx.x, rb = ks.rb;
   const uint32_t part_bits = slot_shift - sweep_bits;
   for (uint32_t e = tid; e < nslots; e += blockDim.x) {
     t_key[e] = kEmpty;
-    for (uint32_t a = 0; a < ks.na; ++a) t_acc[(uint64_t)a * nslots + e] = identity_of(ks.agg[a]);
+    for_lds_cols<kNarrow>(ks, t_cols, nslots, [&](int, uint32_t d, bool nw, uint8_t *c) {
+      if (nw) reinterpret_cast<uint32_t *>(c)[e] = narrow_identity(d);
+      else reinterpret_cast<uint64_t *>(c)[e] = identity_of(d);
+    });
   }
   if (tid == 0) *s_groups = 0;
   __syncthreads();
@@ -302,7 +354,7 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
           }
           g = g + 1 == ng ? 0 : g + 1;
         }
-        if (slot != ~0u) fold_lds(t_acc + slot, nslots, ks, vals[u]);
+        if (slot != ~0u) fold_lds_cols<kNarrow>(t_cols, nslots, slot, ks, vals[u]);
         to_spill = slot == ~0u;
       }
       // records of keys that found no room go to the spill run, one reservation per wave
@@ -333,7 +385,15 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
       const uint32_t e = j * blockDim.x + tid;
       if (r < out_cap) {
         out_keys[r] = t_key[e];
-        for (uint32_t a = 0; a < ks.na; ++a) out_cols.c[a][r] = (int64_t)t_acc[(uint64_t)a * nslots + e];
+        for_lds_cols<kNarrow>(ks, t_cols, nslots, [&](int a, uint32_t d, bool nw, uint8_t *c) {
+          if (!nw) {
+            out_cols.c[a][r] = (int64_t)reinterpret_cast<const uint64_t *>(c)[e];
+          } else {
+            const uint32_t x = reinterpret_cast<const uint32_t *>(c)[e];
+            // COUNT and unsigned fields widen with zeros, signed fields with their sign
+            out_cols.c[a][r] = desc_op(d) >= OP_MIN && type_signed(desc_type(d)) ? (int64_t)(int32_t)x : (int64_t)x;
+          }
+        });
       }
       ++r;
     }
@@ -341,6 +401,7 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
   __syncthreads();  // every thread has read the table before it is cleared again
 }
 
+template <bool kNarrow>
 __global__ void __launch_bounds__(kLdsBlock) k_lds_agg(const uint8_t *__restrict__ buf,
                                                  const unsigned long long *__restrict__ offsets, KSpec ks,
                                                  uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots,
@@ -353,7 +414,7 @@ __global__ void __launch_bounds__(kLdsBlock) k_lds_agg(const uint8_t *__restrict
   uint64_t *t_key = reinterpret_cast<uint64_t *>(lds4);
   const uint64_t lo = offsets[blockIdx.x], hi = offsets[blockIdx.x + 1];
   for (uint32_t sweep = 0; sweep < (1u << sweep_bits); ++sweep)
-    lds_agg_sweep(buf, lo, hi, ks, slot_shift, sweep_bits, sweep, nslots, cap, ctrl, spill, out_keys, out_cols,
+    lds_agg_sweep<kNarrow>(buf, lo, hi, ks, slot_shift, sweep_bits, sweep, nslots, cap, ctrl, spill, out_keys, out_cols,
                   out_cap, t_key, &s_groups, &s_base, scratch);
 }
 
@@ -489,8 +550,10 @@ uint32_t lds_agg_max_bytes() {
   // gfx950 has 160 KB of LDS per compute unit; ask for most of it, else 64 KB
   const uint32_t want = 160 * 1024 - 1024;
   uint32_t got = 64 * 1024;
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_agg), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)want) == hipSuccess)
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_agg<false>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) == hipSuccess &&
+      hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_agg<true>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) == hipSuccess)
     got = want;
   (void)hipGetLastError();
   cache.emplace(dev, got);
@@ -499,13 +562,18 @@ uint32_t lds_agg_max_bytes() {
 
 hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long long *offsets, uint32_t F,
                           const KSpec &ks, uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots, uint32_t cap,
-                          uint32_t lds_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys, const OutCols &out_cols,
-                          uint64_t out_cap) {
+                          bool narrow, uint32_t lds_bytes, Ctrl *ctrl, KSpill spill, uint64_t *out_keys,
+                          const OutCols &out_cols, uint64_t out_cap) {
   if (F == 0) return hipSuccess;
-  if (sweep_bits > slot_shift || sweep_bits > 8 || nslots % 4 || nslots == 0 || (1ull + ks.na) * 8 * nslots > lds_bytes)
+  if (sweep_bits > slot_shift || sweep_bits > 8 || nslots % 4 || nslots == 0 ||
+      (uint64_t)lds_slot_bytes(ks, narrow) * nslots > lds_bytes)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_lds_agg, dim3(F), dim3(kLdsBlock), lds_bytes, s, buf, offsets, ks, slot_shift, sweep_bits,
-                     nslots, cap, ctrl, spill, out_keys, out_cols, out_cap);
+  if (narrow)
+    hipLaunchKernelGGL(k_lds_agg<true>, dim3(F), dim3(kLdsBlock), lds_bytes, s, buf, offsets, ks, slot_shift,
+                       sweep_bits, nslots, cap, ctrl, spill, out_keys, out_cols, out_cap);
+  else
+    hipLaunchKernelGGL(k_lds_agg<false>, dim3(F), dim3(kLdsBlock), lds_bytes, s, buf, offsets, ks, slot_shift,
+                       sweep_bits, nslots, cap, ctrl, spill, out_keys, out_cols, out_cap);
   return hipGetLastError();
 }
 

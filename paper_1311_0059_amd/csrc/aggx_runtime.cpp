@@ -684,6 +684,7 @@ agg_status append_side_rows(agg_handle *h) {
 // ---- partition-first engine with LDS tables --------------------------------
 struct LdsPlan {
   uint32_t b = 0, F = 1, sbits = 0, nslots = 0, cap = 0, lds_bytes = 0;
+  bool narrow = false;  // 4-byte table columns where the values fit
   uint64_t buf_bytes = 0, aux_bytes = 0, need = 0;
   bool passes = false;  // the buffer holds only part of the batch: partitions go in passes
 };
@@ -711,12 +712,13 @@ uint64_t part_chunk(uint64_t n) { return std::max<uint64_t>(1024, (n + 255) / 25
 // kLdsMaxPasses runs), and only that run's records are written to the buffer.
 // With an automatic fan-out the group count planned for is raised (see below),
 // so that a low estimate does not make the tables overflow.
-bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
-  const uint32_t rb = h->ks.rb;
-  if (n >= (1ull << 32)) return false;  // the scatter's partition bases are 32-bit record indices
-  lp->lds_bytes = lds_agg_max_bytes();
-  if (lp->lds_bytes < 256 * h->W8) return false;
-  lp->nslots = (uint32_t)(lp->lds_bytes / h->W8) & ~3u;  // whole groups of four slots
+// The shape of the partitions and tables for one slot layout (4-byte columns
+// where the values fit, or all 8-byte): fan-out bits, sweep bits and slots.
+bool lds_shape(const agg_handle *h, uint64_t n, double G, bool narrow, LdsPlan *lp) {
+  const uint32_t sw = lds_slot_bytes(h->ks, narrow);  // LDS bytes per slot
+  if (lp->lds_bytes < 256 * sw) return false;
+  lp->narrow = narrow;
+  lp->nslots = (uint32_t)(lp->lds_bytes / sw) & ~3u;  // whole groups of four slots
   lp->cap = (uint32_t)(lp->nslots * kLdsLoad);
   // enough partitions to give every compute unit work, but at least ~256 records
   // each; an explicit fan-out in the spec is taken as given
@@ -751,9 +753,38 @@ bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
       sbits = kLdsMaxSweepBits;
     }
   }
+  // The table itself: the fewest whole multiples of the workgroup's threads (which
+  // clear it and read it out, a slot each per step) whose capacity holds one
+  // sweep's planned groups; the largest table when none does.
+  const double per_table = G / (double)(1ull << (b + sbits));
+  for (uint32_t ns = kLdsBlock; ns < lp->nslots; ns += kLdsBlock) {
+    if (per_table + 4.0 * std::sqrt(per_table) + 16.0 <= (uint32_t)(ns * kLdsLoad)) {
+      lp->nslots = ns;
+      lp->cap = (uint32_t)(ns * kLdsLoad);
+      break;
+    }
+  }
   lp->b = b;
   lp->sbits = sbits;
   lp->F = 1u << b;
+  return true;
+}
+
+bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
+  const uint32_t rb = h->ks.rb;
+  if (n >= (1ull << 32)) return false;  // the scatter's partition bases are 32-bit record indices
+  lp->lds_bytes = lds_agg_max_bytes();
+  // 8-byte columns unless narrow ones save sweeps or partitions (the narrow
+  // kernel is a little slower per record)
+  LdsPlan wide = *lp, nar = *lp;
+  const bool ok_w = lds_shape(h, n, G, false, &wide);
+  const bool ok_n = lds_slot_bytes(h->ks, true) < lds_slot_bytes(h->ks, false) && lds_shape(h, n, G, true, &nar);
+  if (ok_n && (!ok_w || nar.sbits < wide.sbits || (nar.sbits == wide.sbits && nar.b < wide.b)))
+    *lp = nar;
+  else if (ok_w)
+    *lp = wide;
+  else
+    return false;
   // counters and cursors on their own 128-byte lines, offsets, packed counts, and
   // the count kernel's per-block counts (one row of F per block)
   const uint64_t blocks = (n + part_chunk(n) - 1) / part_chunk(n);
@@ -831,7 +862,7 @@ agg_status lds_run_partitions(agg_handle *h, const uint8_t *in, uint64_t n, cons
   OutCols oc{};
   for (uint32_t a = 0; a < h->spec.n_aggs; ++a) oc.c[a] = h->r_cols[a] + h->r_rows;
   HCK(h, hipEventRecord(h->ev0, h->stream));
-  HCK(h, launch_lds_agg(h->stream, buf, offsets, d_n, h->ks, lp.b + lp.sbits, lp.sbits, lp.nslots, lp.cap,
+  HCK(h, launch_lds_agg(h->stream, buf, offsets, d_n, h->ks, lp.b + lp.sbits, lp.sbits, lp.nslots, lp.cap, lp.narrow,
                         lp.lds_bytes, h->d_ctrl, spill_target(h, dst, nullptr), h->r_keys + h->r_rows, oc,
                         h->r_cap - h->r_rows));
   HCK(h, hipEventRecord(h->ev1, h->stream));
@@ -915,6 +946,7 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   h->st.lds_hot_keys = hot.n;
   h->st.partitions = lp.F;
   h->st.lds_sweeps = 1u << lp.sbits;
+  h->st.lds_narrow = lp.narrow ? 1u : 0u;
   h->st.lds_passes = (uint32_t)runs.size();
   h->used_bits = std::max(h->used_bits, lp.b + lp.sbits);
   return AGG_OK;

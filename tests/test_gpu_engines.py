@@ -45,6 +45,20 @@ def test_lds_engine_edge_layouts(layout):
         assert st["engine"] == 2
 
 
+@pytest.mark.parametrize("layout", ["R24", "MIX"])
+def test_lds_narrow_columns(layout):
+    """COUNT and MIN/MAX of 32-bit fields in 4-byte table columns, with the fields'
+    extreme values: a plan where the narrow columns save a sweep."""
+    rng = np.random.default_rng(7)
+    # two partitions; each one's expected groups fit a table of narrow slots but not of 8-byte ones
+    gen, spec, est = {"R24": (_rand_r24, SPEC_R24, 6400), "MIX": (_rand_mix, SPEC_MIX, 4800)}[layout]
+    rec = gen(rng, 40_000, _pool(rng, est - 100))
+    print(f"case: lds narrow {layout}", flush=True)
+    k, c, st = run_lib(rec, **_lib_args(spec), est_groups=est, engine="lds", fanout_bits=1)
+    check_against_oracle(rec, spec, k, c, f"lds narrow {layout}")
+    assert st["engine"] == 2 and st["lds_narrow"] == 1 and st["lds_sweeps"] == 1
+
+
 @pytest.mark.parametrize("bits", [2, 6])
 def test_lds_overflow_spills_and_recurses(bits):
     """Too few partitions for the groups (an explicit fan-out, so that the low estimate is

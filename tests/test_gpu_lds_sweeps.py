@@ -64,7 +64,7 @@ def test_sweep_overflow_spills_and_recurses():
     wl = workloads.uniform_spill().scaled(2_000_000, 400_000)
     rec = wl.generate()
     print("case: sweeps overflow", flush=True)
-    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=100_000, engine="lds", fanout_bits=4)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=120_000, engine="lds", fanout_bits=4)
     check_against_oracle(rec, oracle_spec(wl), k, c, "sweeps overflow")
     assert st["engine"] == 2 and st["lds_sweeps"] == 4 and st["levels"] >= 2 and st["records_spilled"] > 0
 
