@@ -31,7 +31,15 @@ __device__ __forceinline__ uint64_t read_field(const uint8_t *rec, uint32_t off,
 }
 
 __device__ __forceinline__ uint64_t read_key(const uint8_t *rec, const KSpec &ks) {
-  if (ks.nk == 2) return ((uint64_t)ld32(rec + ks.koff0) << 32) | (uint64_t)ld32(rec + ks.koff1);
+  if (ks.nk == 2) {
+    // adjacent fields at an 8-byte offset of an 8-byte multiple record (whose
+    // records are 8-byte aligned): one load, halves swapped (little-endian)
+    if (ks.koff1 == ks.koff0 + 4 && ((ks.koff0 | ks.rb) & 7) == 0) {
+      const uint64_t v = ld64(rec + ks.koff0);
+      return (v << 32) | (v >> 32);
+    }
+    return ((uint64_t)ld32(rec + ks.koff0) << 32) | (uint64_t)ld32(rec + ks.koff1);
+  }
   return read_field(rec, ks.koff0, ks.ktype0);
 }
 

@@ -24,16 +24,19 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t key, uint32_t shift, uint3
   return mask ? (uint32_t)(fmix64(key ^ kSeed0) >> shift) & mask : 0u;
 }
 
-// The frequent keys in LDS: an open-addressing set of 128 slots mapping a key to
+// The frequent keys in LDS: an open-addressing set of 1024 slots mapping a key to
 // its index in KHot.  Built by the whole block; hot keys are never reserved values.
-constexpr uint32_t kHotSlots = 128;
+// At most 64 keys in 1024 slots: a lookup, made for every record, almost always
+// ends at its first slot, so the lanes of a wave rarely wait on each other.
+constexpr uint32_t kHotSlots = 1024;
+constexpr uint32_t kHotHashShift = 54;  // 64 - log2(kHotSlots)
 
 __device__ __forceinline__ void hot_build(const KHot &hot, unsigned long long *hk, uint32_t *hid) {
   for (uint32_t e = threadIdx.x; e < kHotSlots; e += blockDim.x) hk[e] = kEmpty;
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < hot.n; i += blockDim.x) {
     const unsigned long long key = hot.keys[i];
-    uint32_t e = (uint32_t)(fmix64(key ^ kSeed0) >> 57);
+    uint32_t e = (uint32_t)(fmix64(key ^ kSeed0) >> kHotHashShift);
     for (uint32_t t = 0; t < kHotSlots; ++t) {
       if (atomicCAS(&hk[e], (unsigned long long)kEmpty, key) == kEmpty) {
         hid[e] = i;
@@ -49,7 +52,7 @@ __device__ __forceinline__ void hot_build(const KHot &hot, unsigned long long *h
 // never frequent keys (and kEmpty marks the set's free slots).
 __device__ __forceinline__ int hot_find(const unsigned long long *hk, const uint32_t *hid, uint64_t key) {
   if (key >= kClosed) return -1;
-  uint32_t e = (uint32_t)(fmix64(key ^ kSeed0) >> 57);
+  uint32_t e = (uint32_t)(fmix64(key ^ kSeed0) >> kHotHashShift);
   for (uint32_t t = 0; t < kHotSlots; ++t) {
     const unsigned long long k = hk[e];
     if (k == key) return (int)hid[e];
@@ -142,11 +145,20 @@ __global__ void __launch_bounds__(256) k_part_offsets(const uint32_t *totals, ui
 // range per partition with one atomic, and writes its records there; a
 // block's records of one partition are therefore contiguous in the output.
 // Four keys per thread are read before their records are placed.
-// Write one record to its partition (see store_record).
+// Write one record to its partition, read and written `vec` bytes at a time
+// (16, 8 or 4: the launch checked that the record size and both ends allow it).
 __device__ __forceinline__ void scatter_one(const uint8_t *rec, uint32_t d, uint32_t rb, uint32_t vec, uint32_t *lc,
                                             const uint32_t *lbase, uint8_t *out) {
   const uint32_t r = atomicAdd(&lc[d], 1u);
-  store_record(out + ((uint64_t)lbase[d] + r) * rb, reinterpret_cast<const uint32_t *>(rec), rb, vec);
+  uint8_t *dst = out + ((uint64_t)lbase[d] + r) * rb;
+  if (vec == 16) {
+    for (uint32_t w = 0; w < rb / 16; ++w) reinterpret_cast<uint4 *>(dst)[w] = reinterpret_cast<const uint4 *>(rec)[w];
+  } else if (vec == 8) {
+    for (uint32_t w = 0; w < rb / 8; ++w) reinterpret_cast<uint2 *>(dst)[w] = reinterpret_cast<const uint2 *>(rec)[w];
+  } else {
+    for (uint32_t w = 0; w < rb / 4; ++w)
+      reinterpret_cast<uint32_t *>(dst)[w] = reinterpret_cast<const uint32_t *>(rec)[w];
+  }
 }
 
 // Only partitions [d_lo, d_lo + d_n) are written (a pass of the LDS engine over
@@ -478,8 +490,9 @@ hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const
   if (n == 0) return hipSuccess;
   if (hot.n > kMaxHot) return hipErrorInvalidValue;
   const uint64_t blocks = (n + chunk - 1) / chunk;
-  // (its frequent-key arrays take another ~6 KB of static LDS)
-  if (!kernel_lds_allowed(reinterpret_cast<const void *>(k_part_count), 4ull * (mask + 1) + 6144))
+  // (its frequent-key arrays take another ~17 KB of static LDS)
+  constexpr size_t kStatic = 12ull * kHotSlots + 4ull * kMaxHot + 8ull * kMaxAggs * kMaxHot;
+  if (!kernel_lds_allowed(reinterpret_cast<const void *>(k_part_count), 4ull * (mask + 1) + kStatic))
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_part_count, dim3((uint32_t)blocks), dim3(kPartBlock), 4ull * (mask + 1), s, in, n, ks, shift,
                      mask, chunk, totals, block_counts, hot);
@@ -503,7 +516,7 @@ hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, con
   if (n >= (1ull << 32)) return hipErrorInvalidValue;  // the LDS bases are 32-bit record indices
   const size_t lds = 8ull * d_n + 12ull * kHotSlots;
   if (!kernel_lds_allowed(reinterpret_cast<const void *>(k_part_scatter), lds)) return hipErrorInvalidValue;
-  const uintptr_t a = reinterpret_cast<uintptr_t>(out);
+  const uintptr_t a = reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(in);
   const uint32_t vec = ks.rb % 16 == 0 && a % 16 == 0 ? 16 : ks.rb % 8 == 0 && a % 8 == 0 ? 8 : 4;
   hipLaunchKernelGGL(k_part_scatter, dim3((uint32_t)blocks), dim3(kPartBlock), lds, s, in, n, ks, shift, mask, d_lo,
                      d_n, chunk, block_counts, hot, cursors, out, vec);

@@ -13,7 +13,7 @@ import datagen
 from datagen import workloads
 from tests.gpu_util import assert_rows_equal, check_against_oracle, lib_spec_args, run_lib
 from tests.test_oracle import SPEC_MIX, SPEC_R16, SPEC_R24, _pool, _rand_mix, _rand_r16, _rand_r24
-from tests.wl import oracle_spec
+from tests.wl import make_spec, oracle_spec
 
 pytestmark = pytest.mark.gpu
 MIB = 1 << 20
@@ -57,6 +57,32 @@ def test_lds_narrow_columns(layout):
     k, c, st = run_lib(rec, **_lib_args(spec), est_groups=est, engine="lds", fanout_bits=1)
     check_against_oracle(rec, spec, k, c, f"lds narrow {layout}")
     assert st["engine"] == 2 and st["lds_narrow"] == 1 and st["lds_sweeps"] == 1
+
+
+@pytest.mark.parametrize("engine", ["lds", "tables"])
+@pytest.mark.parametrize("rb,keys,voff,vtype", [
+    (12, [(0, "u32"), (4, "u32")], 8, "i32"),   # 12-byte records: the key's fields are read one by one
+    (16, [(4, "u32"), (0, "u32")], 8, "i64"),   # fields in the other order: one by one
+    (16, [(8, "u32"), (12, "u32")], 0, "i64"),  # adjacent at an 8-byte offset: one 8-byte load
+])
+def test_composite_key_layouts(rb, keys, voff, vtype, engine):
+    """Two-field keys in several record layouts, against the oracle."""
+    rng = np.random.default_rng(rb + 31 * keys[0][0])
+    n = 60_000
+    dt = np.dtype({"names": ["ka", "kb", "v"], "formats": ["<u4", "<u4", "<i4" if vtype == "i32" else "<i8"],
+                   "offsets": [keys[0][0], keys[1][0], voff], "itemsize": rb})
+    pool = rng.integers(0, 1 << 32, size=(4000, 2), dtype=np.uint64)
+    pool[:3] = [[0, 0], [0xFFFFFFFF, 0xFFFFFFFF], [0xFFFFFFFF, 0xFFFFFFFE]]  # incl. the reserved key values
+    pick = pool[rng.integers(0, len(pool), size=n)]
+    rec = np.zeros(n, dtype=dt)
+    rec["ka"], rec["kb"] = pick[:, 0].astype(np.uint32), pick[:, 1].astype(np.uint32)
+    rec["v"] = rng.integers(-(1 << 31), (1 << 31) - 1, size=n)
+    aggs = [("COUNT", 0, "i64"), ("SUM", voff, vtype), ("MIN", voff, vtype), ("MAX", voff, vtype)]
+    spec = make_spec(rb, keys, aggs)
+    print(f"case: composite key rb={rb} keys={keys} {engine}", flush=True)
+    k, c, st = run_lib(rec, rb, keys, aggs, est_groups=4000, engine=engine)
+    check_against_oracle(rec, spec, k, c, f"composite key {rb} {keys} {engine}")
+    assert st["engine"] == (2 if engine == "lds" else 1)
 
 
 @pytest.mark.parametrize("bits", [2, 6])
