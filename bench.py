@@ -256,6 +256,8 @@ def main():
             "lds_sweeps": agg["lds_sweeps"] // args.steps,
             "lds_passes": agg["lds_passes"] // args.steps,
             "scatter_ms": round(agg["scatter_ms"] / args.steps, 3),
+            "lds_hot_keys": agg["lds_hot_keys"] // args.steps,
+            "lds_narrow": agg["lds_narrow"] // args.steps,
             "engine": agg["engine"] // args.steps,
             "preagg": agg["preagg"] // args.steps,
             "pool_high_water": agg["pool_high_water"] // args.steps,

@@ -246,8 +246,8 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
 // slot index uses the hash bits below both digits (slot_shift).
 // The table's aggregate columns follow its nslots keys, column a taking 4 bytes
 // a slot where kNarrow and lds_narrow allow, else 8; f(a, descriptor, narrow,
-// column) runs for each.  (Tables without narrow columns are compiled apart:
-// the per-column width test costs the common case some speed.)
+// column) runs for each.  (Tables without narrow columns are compiled apart, as
+// plain 8-byte column arrays: the per-column width test costs them some speed.)
 template <bool kNarrow, typename Fn>
 __device__ __forceinline__ void for_lds_cols(const KSpec &ks, uint8_t *cols, uint32_t nslots, Fn f) {
   uint32_t off = 0;  // LDS byte offsets fit 32 bits
@@ -303,12 +303,17 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
   uint8_t *t_cols = reinterpret_cast<uint8_t *>(t_key + nslots);
   const uint32_t tid = threadIdx.x, rb = ks.rb;
   const uint32_t part_bits = slot_shift - sweep_bits;
+  uint64_t *t_acc = t_key + nslots;  // all-8-byte columns
   for (uint32_t e = tid; e < nslots; e += blockDim.x) {
     t_key[e] = kEmpty;
-    for_lds_cols<kNarrow>(ks, t_cols, nslots, [&](int, uint32_t d, bool nw, uint8_t *c) {
-      if (nw) reinterpret_cast<uint32_t *>(c)[e] = narrow_identity(d);
-      else reinterpret_cast<uint64_t *>(c)[e] = identity_of(d);
-    });
+    if constexpr (kNarrow) {
+      for_lds_cols<kNarrow>(ks, t_cols, nslots, [&](int, uint32_t d, bool nw, uint8_t *c) {
+        if (nw) reinterpret_cast<uint32_t *>(c)[e] = narrow_identity(d);
+        else reinterpret_cast<uint64_t *>(c)[e] = identity_of(d);
+      });
+    } else {
+      for (uint32_t a = 0; a < ks.na; ++a) t_acc[(uint64_t)a * nslots + e] = identity_of(ks.agg[a]);
+    }
   }
   if (tid == 0) *s_groups = 0;
   __syncthreads();
@@ -366,7 +371,10 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
           }
           g = g + 1 == ng ? 0 : g + 1;
         }
-        if (slot != ~0u) fold_lds_cols<kNarrow>(t_cols, nslots, slot, ks, vals[u]);
+        if (slot != ~0u) {
+          if constexpr (kNarrow) fold_lds_cols<kNarrow>(t_cols, nslots, slot, ks, vals[u]);
+          else fold_lds(t_acc + slot, nslots, ks, vals[u]);
+        }
         to_spill = slot == ~0u;
       }
       // records of keys that found no room go to the spill run, one reservation per wave
@@ -397,15 +405,19 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
       const uint32_t e = j * blockDim.x + tid;
       if (r < out_cap) {
         out_keys[r] = t_key[e];
-        for_lds_cols<kNarrow>(ks, t_cols, nslots, [&](int a, uint32_t d, bool nw, uint8_t *c) {
-          if (!nw) {
-            out_cols.c[a][r] = (int64_t)reinterpret_cast<const uint64_t *>(c)[e];
-          } else {
-            const uint32_t x = reinterpret_cast<const uint32_t *>(c)[e];
-            // COUNT and unsigned fields widen with zeros, signed fields with their sign
-            out_cols.c[a][r] = desc_op(d) >= OP_MIN && type_signed(desc_type(d)) ? (int64_t)(int32_t)x : (int64_t)x;
-          }
-        });
+        if constexpr (kNarrow) {
+          for_lds_cols<kNarrow>(ks, t_cols, nslots, [&](int a, uint32_t d, bool nw, uint8_t *c) {
+            if (!nw) {
+              out_cols.c[a][r] = (int64_t)reinterpret_cast<const uint64_t *>(c)[e];
+            } else {
+              const uint32_t x = reinterpret_cast<const uint32_t *>(c)[e];
+              // COUNT and unsigned fields widen with zeros, signed fields with their sign
+              out_cols.c[a][r] = desc_op(d) >= OP_MIN && type_signed(desc_type(d)) ? (int64_t)(int32_t)x : (int64_t)x;
+            }
+          });
+        } else {
+          for (uint32_t a = 0; a < ks.na; ++a) out_cols.c[a][r] = (int64_t)t_acc[(uint64_t)a * nslots + e];
+        }
       }
       ++r;
     }
