@@ -19,6 +19,7 @@ namespace aggx {
 
 constexpr uint32_t kPartBlock = 1024;  // threads per block of the count and scatter kernels
 constexpr int kLdsUnroll = 2;          // records per thread read together by k_lds_agg
+constexpr int kPartUnroll = 4;         // keys per thread read together by the count and scatter kernels
 
 __device__ __forceinline__ uint32_t digit_of(uint64_t key, uint32_t shift, uint32_t mask) {
   return mask ? (uint32_t)(fmix64(key ^ kSeed0) >> shift) & mask : 0u;
@@ -100,12 +101,12 @@ __global__ void __launch_bounds__(kPartBlock) k_part_count(const uint8_t *__rest
     }
   };
   uint64_t i = lo + threadIdx.x;
-  for (; i + 3 * B < hi; i += 4 * B) {
-    uint64_t k[4];
+  for (; i + (kPartUnroll - 1) * B < hi; i += kPartUnroll * B) {
+    uint64_t k[kPartUnroll];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) k[u] = read_key(in + (i + u * B) * ks.rb, ks);
+    for (int u = 0; u < kPartUnroll; ++u) k[u] = read_key(in + (i + u * B) * ks.rb, ks);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) take(in + (i + u * B) * ks.rb, k[u]);
+    for (int u = 0; u < kPartUnroll; ++u) take(in + (i + u * B) * ks.rb, k[u]);
   }
   for (; i < hi; i += B) take(in + i * ks.rb, read_key(in + i * ks.rb, ks));
   __syncthreads();
@@ -144,7 +145,11 @@ __global__ void __launch_bounds__(256) k_part_offsets(const uint32_t *totals, ui
 // Pass 2: scatter.  Each block re-reads its chunk, reserves one contiguous
 // range per partition with one atomic, and writes its records there; a
 // block's records of one partition are therefore contiguous in the output.
-// Four keys per thread are read before their records are placed.
+// Four keys per thread are read before their records are placed; without
+// frequent keys all four loads are issued before any digit is computed (a pass
+// over a run of the partitions mostly reads records it skips; this measured 8%
+// faster), with them each key's set lookup follows its load (faster there).
+//
 // Write one record to its partition, read and written `vec` bytes at a time
 // (16, 8 or 4: the launch checked that the record size and both ends allow it).
 __device__ __forceinline__ void scatter_one(const uint8_t *rec, uint32_t d, uint32_t rb, uint32_t vec, uint32_t *lc,
@@ -192,12 +197,12 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
   }
   __syncthreads();
   // the digits, relative to d_lo (out of range: d_n or more, as unsigned)
-  for (; i + 3 * B < hi; i += 4 * B) {
-    uint64_t k[4];
+  for (; i + (kPartUnroll - 1) * B < hi; i += kPartUnroll * B) {
+    uint64_t k[kPartUnroll];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) k[u] = read_key(in + (i + u * B) * ks.rb, ks);
+    for (int u = 0; u < kPartUnroll; ++u) k[u] = read_key(in + (i + u * B) * ks.rb, ks);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kPartUnroll; ++u) {
       const uint32_t d = rel_digit(k[u]);
       if (d < d_n) atomicAdd(&lc[d], 1u);
     }
@@ -216,13 +221,27 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
   }
   __syncthreads();
   i = lo + threadIdx.x;
-  for (; i + 3 * B < hi; i += 4 * B) {
-    uint32_t d[4];
+  if (hot.n == 0) {
+    // all keys' loads first, then their digits
+    for (; i + (kPartUnroll - 1) * B < hi; i += kPartUnroll * B) {
+      uint64_t k[kPartUnroll];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) d[u] = rel_digit(read_key(in + (i + u * B) * ks.rb, ks));
+      for (int u = 0; u < kPartUnroll; ++u) k[u] = read_key(in + (i + u * B) * ks.rb, ks);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (d[u] < d_n) scatter_one(in + (i + u * B) * ks.rb, d[u], ks.rb, vec, lc, lbase, out);
+      for (int u = 0; u < kPartUnroll; ++u) {
+        const uint32_t d = digit_of(k[u], shift, mask) - d_lo;
+        if (d < d_n) scatter_one(in + (i + u * B) * ks.rb, d, ks.rb, vec, lc, lbase, out);
+      }
+    }
+  } else {
+    for (; i + (kPartUnroll - 1) * B < hi; i += kPartUnroll * B) {
+      uint32_t d[kPartUnroll];
+#pragma unroll
+      for (int u = 0; u < kPartUnroll; ++u) d[u] = rel_digit(read_key(in + (i + u * B) * ks.rb, ks));
+#pragma unroll
+      for (int u = 0; u < kPartUnroll; ++u)
+        if (d[u] < d_n) scatter_one(in + (i + u * B) * ks.rb, d[u], ks.rb, vec, lc, lbase, out);
+    }
   }
   for (; i < hi; i += B) {
     const uint8_t *rec = in + i * ks.rb;
