@@ -61,6 +61,10 @@ __host__ __device__ inline uint32_t lds_slot_bytes(const KSpec &ks, bool narrow)
   return w;
 }
 
+// The partition engine's per-block counts: `blocks` rows of F 16-bit counts,
+// then one 32-bit flag per block at this (4-byte aligned) 16-bit index.
+__host__ __device__ inline uint64_t block_flags_at(uint64_t blocks, uint64_t F) { return (blocks * F + 1) & ~1ull; }
+
 // One hybrid-hash pass ("level"): which digit of the hash selects the
 // partition, and the seed of the slot hash.
 struct KLevel {
@@ -194,13 +198,13 @@ hipError_t launch_digit_scatter(hipStream_t s, int kind, const uint8_t *in, uint
                                 uint32_t shift, uint32_t mask, unsigned long long *cursor, uint8_t *out);
 // Partition-first LDS engine.
 hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
-                             uint32_t mask, uint64_t chunk, uint32_t *totals, uint32_t *block_counts,
+                             uint32_t mask, uint64_t chunk, uint32_t *totals, uint16_t *block_counts,
                              const KHot &hot);
 hipError_t launch_part_offsets(hipStream_t s, const uint32_t *totals, uint32_t F, unsigned long long *offsets,
                                unsigned long long *cursors);
 hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
                                uint32_t mask, uint32_t d_lo, uint32_t d_n, uint64_t chunk,
-                               const uint32_t *block_counts, const KHot &hot, unsigned long long *cursors,
+                               const uint16_t *block_counts, const KHot &hot, unsigned long long *cursors,
                                uint8_t *out);
 hipError_t launch_hot_init(hipStream_t s, const KHot &hot, const KSpec &ks);
 hipError_t launch_hot_rows(hipStream_t s, const KHot &hot, const KSpec &ks, uint64_t *out_keys,

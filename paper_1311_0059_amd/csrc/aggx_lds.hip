@@ -67,13 +67,14 @@ __device__ __forceinline__ int hot_find(const unsigned long long *hk, const uint
 // digits in LDS and adds its counts to the per-partition totals.  Each thread
 // reads four keys before it counts them, so that their loads are in flight
 // together (the chunks are long and the blocks few).  With `block_counts`, the
-// block also stores its counts (one row of mask+1 per block), so that a scatter
+// block also stores its counts (one row of mask+1 16-bit counts per block, then
+// one 32-bit flag per block, set when a count did not fit), so that a scatter
 // over the same chunks need not count again.  Records of the frequent keys in
 // `hot` are not counted: they are folded into the block's LDS accumulators,
 // which are added to the global ones at the end.
 __global__ void __launch_bounds__(kPartBlock) k_part_count(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
                                                            uint32_t shift, uint32_t mask, uint64_t chunk,
-                                                           uint32_t *totals, uint32_t *block_counts, KHot hot) {
+                                                           uint32_t *totals, uint16_t *block_counts, KHot hot) {
   extern __shared__ uint32_t lh[];
   __shared__ unsigned long long hk[kHotSlots];
   __shared__ uint32_t hid[kHotSlots], hseen[kMaxHot];
@@ -110,9 +111,19 @@ __global__ void __launch_bounds__(kPartBlock) k_part_count(const uint8_t *__rest
   }
   for (; i < hi; i += B) take(in + i * ks.rb, read_key(in + i * ks.rb, ks));
   __syncthreads();
+  int over = 0;
   for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) {
-    if (lh[b]) __hip_atomic_fetch_add(totals + (uint64_t)b * kCntStride, lh[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (block_counts) block_counts[(uint64_t)blockIdx.x * (mask + 1) + b] = lh[b];
+    const uint32_t c = lh[b];
+    if (c) __hip_atomic_fetch_add(totals + (uint64_t)b * kCntStride, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (block_counts) {
+      over |= c > 0xffffu;
+      block_counts[(uint64_t)blockIdx.x * (mask + 1) + b] = (uint16_t)(c > 0xffffu ? 0xffffu : c);
+    }
+  }
+  if (block_counts) {
+    over = __syncthreads_or(over);
+    if (threadIdx.x == 0)
+      reinterpret_cast<uint32_t *>(block_counts + block_flags_at(gridDim.x, mask + 1ull))[blockIdx.x] = over ? 1u : 0u;
   }
   for (uint32_t x = threadIdx.x; x < hot.n; x += blockDim.x) {
     if (!hseen[x]) continue;
@@ -173,7 +184,7 @@ __device__ __forceinline__ void scatter_one(const uint8_t *rec, uint32_t d, uint
 __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
                                                              uint32_t shift, uint32_t mask, uint32_t d_lo,
                                                              uint32_t d_n, uint64_t chunk,
-                                                             const uint32_t *__restrict__ block_counts, KHot hot,
+                                                             const uint16_t *__restrict__ block_counts, KHot hot,
                                                              unsigned long long *cursors, uint8_t *out, uint32_t vec) {
   // d_n counts, d_n bases (record indices below 2^32), then the frequent-key set
   extern __shared__ uint32_t lc[];
@@ -188,7 +199,12 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
   };
   const uint64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n, B = blockDim.x;
   uint64_t i = lo + threadIdx.x;
-  if (block_counts) {
+  // the stored counts, unless one of this block's did not fit 16 bits (then it counts
+  // its chunk itself); the same chunks, so the same grid, as the count kernel's
+  const bool stored =
+      block_counts &&
+      reinterpret_cast<const uint32_t *>(block_counts + block_flags_at(gridDim.x, mask + 1ull))[blockIdx.x] == 0;
+  if (stored) {
     for (uint32_t b = threadIdx.x; b < d_n; b += blockDim.x)
       lc[b] = block_counts[(uint64_t)blockIdx.x * (mask + 1) + d_lo + b];
     i = hi;  // nothing to count
@@ -516,7 +532,7 @@ static bool kernel_lds_allowed(const void *fn, size_t lds) {
 }
 
 hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
-                             uint32_t mask, uint64_t chunk, uint32_t *totals, uint32_t *block_counts,
+                             uint32_t mask, uint64_t chunk, uint32_t *totals, uint16_t *block_counts,
                              const KHot &hot) {
   if (n == 0) return hipSuccess;
   if (hot.n > kMaxHot) return hipErrorInvalidValue;
@@ -538,7 +554,7 @@ hipError_t launch_part_offsets(hipStream_t s, const uint32_t *totals, uint32_t F
 
 hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
                                uint32_t mask, uint32_t d_lo, uint32_t d_n, uint64_t chunk,
-                               const uint32_t *block_counts, const KHot &hot, unsigned long long *cursors,
+                               const uint16_t *block_counts, const KHot &hot, unsigned long long *cursors,
                                uint8_t *out) {
   if (n == 0 || d_n == 0) return hipSuccess;
   if (hot.n > kMaxHot) return hipErrorInvalidValue;

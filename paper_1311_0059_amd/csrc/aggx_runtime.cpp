@@ -712,6 +712,13 @@ uint64_t part_chunk(uint64_t n) { return std::max<uint64_t>(1024, (n + 255) / 25
 // kLdsMaxPasses runs), and only that run's records are written to the buffer.
 // With an automatic fan-out the group count planned for is raised (see below),
 // so that a low estimate does not make the tables overflow.
+// The count kernel's per-block counts: 16 bits each (a block whose count of a
+// partition does not fit counts its chunk again in the scatter), and a flag per
+// block.  Half the size of 32-bit counts leaves the partition buffer more room.
+uint64_t lds_block_counts_bytes(uint64_t blocks, uint32_t F) {
+  return round_up(2ull * block_flags_at(blocks, F) + 4ull * blocks, 256);
+}
+
 // The shape of the partitions and tables for one slot layout (4-byte columns
 // where the values fit, or all 8-byte): fan-out bits, sweep bits and slots.
 bool lds_shape(const agg_handle *h, uint64_t n, double G, bool narrow, LdsPlan *lp) {
@@ -786,10 +793,11 @@ bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
   else
     return false;
   // counters and cursors on their own 128-byte lines, offsets, packed counts, and
-  // the count kernel's per-block counts (one row of F per block)
+  // the count kernel's per-block counts (one row of F 16-bit counts per block, then
+  // a flag per block)
   const uint64_t blocks = (n + part_chunk(n) - 1) / part_chunk(n);
   lp->aux_bytes = round_up(2ull * lp->F * 128 + 8ull * (lp->F + 1) + 4ull * lp->F, 256) +
-                  round_up(4ull * blocks * lp->F, 256) + round_up(8ull * kMaxHot * h->ks.na, 256);
+                  lds_block_counts_bytes(blocks, lp->F) + round_up(8ull * kMaxHot * h->ks.na, 256);
   lp->buf_bytes = round_up(n * rb, 256);
   lp->passes = false;
   if (!h->unlimited && lp->buf_bytes + lp->aux_bytes > h->arena_cap_bytes) {
@@ -819,8 +827,8 @@ agg_status grow_unlimited_pool(agg_handle *h, uint64_t arena_need) {
 }
 
 // The count kernel's per-block counts: after the counters, offsets and packed counts.
-uint32_t *lds_block_counts(uint8_t *arena, const LdsPlan &lp) {
-  return reinterpret_cast<uint32_t *>(arena + lp.buf_bytes +
+uint16_t *lds_block_counts(uint8_t *arena, const LdsPlan &lp) {
+  return reinterpret_cast<uint16_t *>(arena + lp.buf_bytes +
                                       round_up(2ull * lp.F * 128 + 8ull * (lp.F + 1) + 4ull * lp.F, 256));
 }
 
@@ -832,7 +840,7 @@ KHot lds_hot(agg_handle *h, uint8_t *arena, const LdsPlan &lp, uint64_t n) {
   hot.keys = h->d_ctrl->sample_hot;
   const uint64_t blocks = (n + part_chunk(n) - 1) / part_chunk(n);
   hot.acc = reinterpret_cast<uint64_t *>(reinterpret_cast<uint8_t *>(lds_block_counts(arena, lp)) +
-                                         round_up(4ull * blocks * lp.F, 256));
+                                         lds_block_counts_bytes(blocks, lp.F));
   return hot;
 }
 

@@ -140,3 +140,18 @@ def test_passes_with_sweeps_then_more_batches():
                        batches=3)
     check_against_oracle(rec, oracle_spec(wl), k, c, "passes sweeps batches")
     assert st["engine"] == 2 and st["lds_passes"] >= 2 and st["lds_sweeps"] >= 2
+
+
+def test_block_counts_beyond_16_bits():
+    """The count kernel stores each workgroup's partition counts in 16 bits; a workgroup
+    whose count of a partition is larger counts its chunk again in the scatter.  Sorted
+    keys, 2000 records each, over two partitions: about a third of the 256 workgroups
+    (125k records each) hold more than 65535 records of one partition, the others fewer."""
+    wl = workloads.Workload("sorted-blocks", "R16", 32_000_000, 16_000, datagen.UNIFORM, 0.0, -10**6, 10**6,
+                            workloads.AGGS_R16_ALL, 0, workloads.SEED_BASE + 43)
+    rec = wl.generate()
+    rec = rec[np.argsort(rec["key"], kind="stable")]
+    print("case: 16-bit block counts", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d, engine="lds", fanout_bits=1)
+    check_against_oracle(rec, oracle_spec(wl), k, c, "16-bit block counts")
+    assert st["engine"] == 2 and st["partitions"] == 2 and st["levels"] == 1
