@@ -25,6 +25,10 @@ constexpr uint32_t kLdsBlock = 1024;    // threads per workgroup of the LDS aggr
 // insert; each gets its own 128-byte line so that partitions never serialize
 // on a shared line at the memory-side atomic units.
 constexpr uint32_t kCntStride = 32;  // uint32 words per counter
+// The partition kernels' per-partition record counters and cursors take one
+// atomic per workgroup each, far fewer: half a line each (64 bytes) is enough,
+// and leaves the partition buffer more of the budget.
+constexpr uint32_t kPartStride = 16;  // uint32 words per partition counter
 constexpr int kHllBits = 12;                 // 4096 HyperLogLog registers per sketch
 constexpr uint32_t kHllRegs = 1u << kHllBits;
 

@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(kPartBlock) k_part_count(const uint8_t *__rest
   int over = 0;
   for (uint32_t b = threadIdx.x; b <= mask; b += blockDim.x) {
     const uint32_t c = lh[b];
-    if (c) __hip_atomic_fetch_add(totals + (uint64_t)b * kCntStride, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (c) __hip_atomic_fetch_add(totals + (uint64_t)b * kPartStride, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (block_counts) {
       over |= c > 0xffffu;
       block_counts[(uint64_t)blockIdx.x * (mask + 1) + b] = (uint16_t)(c > 0xffffu ? 0xffffu : c);
@@ -141,14 +141,14 @@ __global__ void __launch_bounds__(256) k_part_offsets(const uint32_t *totals, ui
   const uint32_t per = (F + blockDim.x - 1) / blockDim.x;
   const uint32_t b0 = threadIdx.x * per;
   uint32_t sum = 0;
-  for (uint32_t b = b0; b < b0 + per && b < F; ++b) sum += totals[(uint64_t)b * kCntStride];
+  for (uint32_t b = b0; b < b0 + per && b < F; ++b) sum += totals[(uint64_t)b * kPartStride];
   uint32_t total;
   const uint32_t pre = block_exclusive_scan(sum, &total, scratch);
   unsigned long long acc = pre;
   for (uint32_t b = b0; b < b0 + per && b < F; ++b) {
     offsets[b] = acc;
-    cursors[(uint64_t)b * (kCntStride / 2)] = acc;
-    acc += totals[(uint64_t)b * kCntStride];
+    cursors[(uint64_t)b * (kPartStride / 2)] = acc;
+    acc += totals[(uint64_t)b * kPartStride];
   }
   if (threadIdx.x == 0) offsets[F] = total;
 }
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
   __syncthreads();
   for (uint32_t b = threadIdx.x; b < d_n; b += blockDim.x) {
     if (lc[b])
-      lbase[b] = (uint32_t)__hip_atomic_fetch_add(cursors + (uint64_t)b * (kCntStride / 2),
+      lbase[b] = (uint32_t)__hip_atomic_fetch_add(cursors + (uint64_t)b * (kPartStride / 2),
                                                   (unsigned long long)lc[b], __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
     lc[b] = 0;

@@ -796,7 +796,7 @@ bool lds_plan(agg_handle *h, uint64_t n, double G, LdsPlan *lp) {
   // the count kernel's per-block counts (one row of F 16-bit counts per block, then
   // a flag per block)
   const uint64_t blocks = (n + part_chunk(n) - 1) / part_chunk(n);
-  lp->aux_bytes = round_up(2ull * lp->F * 128 + 8ull * (lp->F + 1) + 4ull * lp->F, 256) +
+  lp->aux_bytes = round_up(2ull * lp->F * 4 * kPartStride + 8ull * (lp->F + 1) + 4ull * lp->F, 256) +
                   lds_block_counts_bytes(blocks, lp->F) + round_up(8ull * kMaxHot * h->ks.na, 256);
   lp->buf_bytes = round_up(n * rb, 256);
   lp->passes = false;
@@ -829,7 +829,7 @@ agg_status grow_unlimited_pool(agg_handle *h, uint64_t arena_need) {
 // The count kernel's per-block counts: after the counters, offsets and packed counts.
 uint16_t *lds_block_counts(uint8_t *arena, const LdsPlan &lp) {
   return reinterpret_cast<uint16_t *>(arena + lp.buf_bytes +
-                                      round_up(2ull * lp.F * 128 + 8ull * (lp.F + 1) + 4ull * lp.F, 256));
+                                      round_up(2ull * lp.F * 4 * kPartStride + 8ull * (lp.F + 1) + 4ull * lp.F, 256));
 }
 
 // The frequent keys taken out of the partitions (keys in the control block,
@@ -852,10 +852,10 @@ agg_status lds_run_partitions(agg_handle *h, const uint8_t *in, uint64_t n, cons
   uint8_t *arena = reinterpret_cast<uint8_t *>(h->d_arena);
   uint8_t *buf = arena;
   uint32_t *totals = reinterpret_cast<uint32_t *>(arena + lp.buf_bytes);
-  unsigned long long *cursors = reinterpret_cast<unsigned long long *>(arena + lp.buf_bytes + 128ull * lp.F);
-  unsigned long long *offsets = cursors + (uint64_t)lp.F * (kCntStride / 2);
+  unsigned long long *cursors = reinterpret_cast<unsigned long long *>(arena + lp.buf_bytes + 4ull * kPartStride * lp.F);
+  unsigned long long *offsets = cursors + (uint64_t)lp.F * (kPartStride / 2);
   const uint32_t shift = lp.b ? 64 - lp.b : 0, mask = lp.F - 1;
-  HCK(h, launch_part_offsets(h->stream, totals + (uint64_t)d_lo * kCntStride, d_n, offsets, cursors));
+  HCK(h, launch_part_offsets(h->stream, totals + (uint64_t)d_lo * kPartStride, d_n, offsets, cursors));
   HCK(h, hipEventRecord(h->ev2, h->stream));
   HCK(h, launch_part_scatter(h->stream, in, n, h->ks, shift, mask, d_lo, d_n, part_chunk(n), lds_block_counts(arena, lp),
                              lds_hot(h, arena, lp, n), cursors, buf));
@@ -905,10 +905,10 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   }
   uint8_t *arena = reinterpret_cast<uint8_t *>(h->d_arena);
   uint32_t *totals = reinterpret_cast<uint32_t *>(arena + lp.buf_bytes);
-  uint32_t *packed = reinterpret_cast<uint32_t *>(arena + lp.buf_bytes + 2ull * lp.F * 128 + 8ull * (lp.F + 1));
+  uint32_t *packed = reinterpret_cast<uint32_t *>(arena + lp.buf_bytes + 2ull * lp.F * 4 * kPartStride + 8ull * (lp.F + 1));
   const uint32_t shift = lp.b ? 64 - lp.b : 0, mask = lp.F - 1;
   const KHot hot = lds_hot(h, arena, lp, n);
-  HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)lp.F * kCntStride, 0));
+  HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)lp.F * kPartStride, 0));
   HCK(h, launch_hot_init(h->stream, hot, h->ks));
   HCK(h, launch_part_count(h->stream, in, n, h->ks, shift, mask, part_chunk(n), totals, lds_block_counts(arena, lp),
                            hot));
@@ -917,7 +917,7 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   if (!lp.passes) {
     runs.push_back({lp.F, n});
   } else {
-    HCK(h, launch_gather_u32(h->stream, totals, kCntStride, lp.F, packed));
+    HCK(h, launch_gather_u32(h->stream, totals, kPartStride, lp.F, packed));
     HCK(h, hipMemcpyAsync(h->h_scratch, packed, 4ull * lp.F, hipMemcpyDeviceToHost, h->stream));
     HCK(h, hipStreamSynchronize(h->stream));
     const uint64_t cap = lp.buf_bytes / h->ks.rb;
@@ -1060,7 +1060,7 @@ agg_status run_owner_stream(agg_handle *h, const uint8_t *in, uint64_t n) {
       const uint64_t c = std::min(m, g - so);
       const uint8_t *src = in + (off + so) * rb;
       const uint64_t chunk = part_chunk(c);
-      HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)pl.F * kCntStride, 0));
+      HCK(h, launch_u32_fill(h->stream, totals, (uint64_t)pl.F * kPartStride, 0));
       HCK(h, launch_part_count(h->stream, src, c, h->ks, shift, mask, chunk, totals, nullptr, KHot{}));
       HCK(h, launch_part_offsets(h->stream, totals, pl.F, offsets, cursors));
       HCK(h, launch_part_scatter(h->stream, src, c, h->ks, shift, mask, 0, mask + 1, chunk, nullptr, KHot{}, cursors,
