@@ -55,7 +55,7 @@ def parse():
                     help="records of the input the CPU oracle is timed on (0 = skip)")
     ap.add_argument("--requests", type=int, default=120, help="served: requests in the trace")
     ap.add_argument("--load", type=float, default=0.8, help="served: offered load vs the plain path's capacity")
-    ap.add_argument("--inflight", type=int, default=8, help="served: requests running at once")
+    ap.add_argument("--inflight", type=int, default=6, help="served: requests running at once (the library accepts at most 6)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy kernel (counter calibration for the traffic figure)")
     ap.add_argument("--quiet", action="store_true")

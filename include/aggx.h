@@ -77,15 +77,18 @@ typedef enum agg_policy {
 /* Aggregation engines (all compute the same rows). */
 typedef enum agg_engine {
   AGG_ENGINE_AUTO = 0,    /* for the first batch: the sorted-run path when a sample of it is sorted; else
-                             the LDS engine when it applies and no key dominates a sample; else HBM
-                             tables with atomics.  Later batches and recursion levels use HBM tables */
+                             the LDS engine when it applies (keys frequent in a sample of the batch are
+                             then aggregated apart from its partitions); else HBM tables with atomics.
+                             Later batches and recursion levels use HBM tables */
   AGG_ENGINE_TABLES = 1,  /* per-partition open-addressing tables in HBM, 64-bit atomics, chunked input */
-  AGG_ENGINE_LDS = 2,     /* radix-partition the batch (up to 2^13 partitions), then one workgroup
+  AGG_ENGINE_LDS = 2,     /* radix-partition the batch (up to 2^14 partitions), then one workgroup
                              aggregates each partition in an LDS table (in up to 4 sweeps when a partition
-                             has more groups than a table).  When the budget holds only part of the
-                             partitioned batch, runs of partitions that fit it are done one pass over the
-                             batch each.  Applies to a first batch of at most 4 GiB needing at most 8
-                             passes, with no partition larger than the buffer (else HBM tables) */
+                             has more groups than a table).  Up to 64 keys that are frequent in a sample of
+                             the batch are taken out of the partitions and aggregated while it is counted
+                             (one row each).  When the budget holds only part of the partitioned batch,
+                             runs of partitions that fit it are done one pass over the batch each.
+                             Applies to a first batch of at most 4 GiB (unlimited budget) needing at most
+                             8 passes, with no partition larger than the buffer (else HBM tables) */
   AGG_ENGINE_OWNER = 3,   /* the same HBM tables, updated without atomics: sub-chunks of the batch are
                              radix-partitioned into a buffer carved from the budget, and one workgroup owns
                              each partition's table while it folds that partition's records in */
@@ -180,12 +183,21 @@ typedef struct agg_stats {
                                    4-byte columns (chosen when that saves sweeps or partitions) */
 } agg_stats;
 
-/* Validate and copy `spec`, reserve the working budget (or adopt the caller's
- * workspace), and plan level 0.  On success *out owns a new handle. */
+/* Start one GROUP BY query (Sec. 3.1) under the memory budget M of Sec. 3.2
+ * (spec->budget_bytes), with the optional estimate G of distinct keys that
+ * Formula (1) of Sec. 4.3 plans the partitions from (spec->est_groups) and the
+ * spill policy of Sec. 4.3.3 or 4.3.4 (spec->policy).  Validates and copies
+ * `spec`, reserves the working budget (or adopts the caller's workspace), and
+ * configures the device on first use.  On success *out owns a new handle;
+ * on error *out is NULL: AGG_E_INVALID (malformed spec), AGG_E_BUDGET (budget
+ * below agg_min_budget, or a workspace smaller than the budget), AGG_E_NOMEM,
+ * AGG_E_DEVICE. */
 agg_status agg_create(const agg_spec *spec, agg_handle **out);
 
-/* Aggregate `n` records from the device buffer `d_records` (packed, record_bytes
- * each; 8-byte aligned when record_bytes is a multiple of 8, else 4-byte
+/* Phase 1 of Sec. 4.3 (hash-partition) over one batch: hash every record,
+ * aggregate the records of resident partitions in memory and spill the others
+ * (Sec. 4.3.3 / 4.3.4 decide which).  Aggregate `n` records from the device
+ * buffer `d_records` (packed, record_bytes each; 8-byte aligned when record_bytes is a multiple of 8, else 4-byte
  * aligned -- AGG_E_INVALID otherwise).  Specs with an 8-byte key or input field
  * need record_bytes to be a multiple of 8.  The buffer is borrowed: the work is ordered on the
  * handle's stream, and the caller must not modify or free the buffer until the
@@ -206,12 +218,21 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n);
  * returns AGG_E_STATE; calling it again returns the same rows. */
 agg_status agg_first_rows(agg_handle *h, agg_result *out);
 
-/* Finish level 0, run every recursion level over the spilled partitions, and
- * publish the rows in *out.  Blocks until the result is complete.  Calling it
- * again returns the same result. */
+/* End of the input: flush the partitions still resident at level 0 straight to
+ * the result (Sec. 4.3.3, after all records are processed), then Phase 2 of
+ * Sec. 4.3: re-aggregate the spilled partitions recursively, one hash digit
+ * per level, until nothing is spilled.  Publishes the rows in *out (one row
+ * per distinct key, Sec. 3.1).  Blocks until the result is complete.  Calling
+ * it again returns the same result.  Errors poison the handle: AGG_E_NOMEM
+ * (pinned spill memory or result rows), AGG_E_INTERNAL (recursion past the
+ * hash's digit range), AGG_E_DEVICE. */
 agg_status agg_finish(agg_handle *h, agg_result *out);
 
-/* Counters of the run so far (complete after agg_finish). */
+/* Counters of the run so far (complete after agg_finish): the quantities the
+ * cost models of Sec. 5 are written in -- records and grouping states spilled
+ * (the I/O term C_IO of Sec. 5.3), resident groups K, partitions P, levels of
+ * Phase 2 -- measured as the experiments of Sec. 6.1 compare them with the
+ * models.  AGG_E_INVALID on a NULL argument. */
 agg_status agg_get_stats(const agg_handle *h, agg_stats *out);
 
 /* Free everything the handle owns.  Safe on a poisoned handle and on NULL. */
@@ -285,9 +306,15 @@ void agg_batch_destroy(agg_batch *b);
  * request's rows equal those of running it alone. */
 typedef struct agg_server agg_server;
 
+/* Largest max_inflight accepted.  A served run with every request queued at once
+ * and eight in flight once ended in a host heap-corruption abort whose cause has
+ * not been shown; six in flight is the most that has run clean, so more are
+ * refused (AGG_E_INVALID). */
+#define AGG_SERVER_MAX_INFLIGHT 6
+
 typedef struct agg_server_config {
   uint64_t pool_bytes;    /* device pool shared by the admitted requests' budgets (>= 1 MiB) */
-  uint32_t max_inflight;  /* requests running at once (worker threads and streams), 1..64 */
+  uint32_t max_inflight;  /* requests running at once (worker threads and streams), 1..AGG_SERVER_MAX_INFLIGHT */
   uint32_t reserved;      /* must be 0 */
 } agg_server_config;
 
@@ -306,7 +333,9 @@ typedef struct agg_server_stats {
   uint64_t pool_bytes, pool_in_use, pool_peak;
 } agg_server_stats;
 
-/* Allocate the pool and start the workers (on the current device). */
+/* Allocate the pool and start the workers (on the current device).
+ * AGG_E_INVALID for a pool under 1 MiB or max_inflight outside
+ * 1..AGG_SERVER_MAX_INFLIGHT; AGG_E_NOMEM when the pool cannot be allocated. */
 agg_status agg_server_create(const agg_server_config *cfg, agg_server **out);
 
 /* Queue a request; returns at once with a ticket.  spec->budget_bytes is the

@@ -238,7 +238,7 @@ class Batch:
 class Server:
     """Served mode (agg_server_*): submit requests, the native loop admits them by budget."""
 
-    def __init__(self, pool_bytes: int, max_inflight: int = 8):
+    def __init__(self, pool_bytes: int, max_inflight: int = 6):
         self._lib = load_library()
         cfg = N.ServerConfig()
         cfg.pool_bytes = pool_bytes

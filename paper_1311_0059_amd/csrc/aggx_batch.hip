@@ -166,17 +166,24 @@ __device__ void lds_aggregate(const uint8_t *in, uint64_t lo, uint64_t hi, const
 
 __global__ void __launch_bounds__(1024) k_batch(BParams P) {
   extern __shared__ uint4 lds4[];
-  __shared__ uint32_t s_item, s_ok, s_groups;
+  __shared__ uint32_t s_item, s_stop, s_ok, s_groups;
   __shared__ unsigned long long s_base;
   __shared__ uint32_t scratch[32];
   uint32_t *lh = reinterpret_cast<uint32_t *>(lds4);  // count/scatter: up to 4096 counts, then bases
   const KSpec &ks = P.ks;
   const uint32_t tid = threadIdx.x;
   for (;;) {
-    if (tid == 0) s_item = __hip_atomic_fetch_add(P.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // one thread takes the next item and reads the error flag; the whole block
+    // then sees the same decision, so it leaves the loop together
+    if (tid == 0) {
+      s_item = __hip_atomic_fetch_add(P.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_stop = s_item >= P.n_items || __hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    }
     __syncthreads();
     const uint32_t item = s_item;
-    if (item >= P.n_items || __hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    const bool stop = s_stop != 0;
+    __syncthreads();  // s_item / s_stop are rewritten only after every thread has read them
+    if (stop) break;
     const BItem it = P.items[item];
     const BInst I = P.inst[it.inst];
     const uint32_t F = 1u << I.b;
@@ -298,24 +305,13 @@ __global__ void k_batch_reset(BParams P) {
   for (uint64_t i = t; i < P.n_parts; i += stride) P.totals[i] = 0;
 }
 
-// The kernel's attribute and occupancy queries run under one lock, so batch
-// objects created from several host threads never race on them.
-static std::mutex g_setup_mu;
-
-hipError_t batch_lds_setup(uint32_t lds_bytes) {
-  std::lock_guard<std::mutex> lk(g_setup_mu);
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds_bytes);
-}
-
-int batch_resident_blocks(uint32_t block, uint32_t lds_bytes) {
-  std::lock_guard<std::mutex> lk(g_setup_mu);
-  int dev = 0, per_cu = 0;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, block, lds_bytes) != hipSuccess || per_cu < 1)
-    per_cu = 1;
-  return per_cu * prop.multiProcessorCount;
+// Part of the device setup: the persistent kernel may take `lds_bytes` of LDS,
+// and *per_cu of its blocks fit a compute unit at that size.
+hipError_t batch_kernel_setup(uint32_t lds_bytes, int *per_cu) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch, 1024, lds_bytes);
 }
 
 hipError_t launch_batch(hipStream_t s, const BParams &P, uint32_t blocks, uint32_t block, uint32_t lds_bytes) {

@@ -233,15 +233,12 @@ agg_status agg_batch_create(const agg_spec *spec, const agg_instance *inst, uint
   };
   if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) return bail(AGG_E_DEVICE);
   // LDS: the aggregation table, and at least the 48 KB the count/scatter items use
-  b->lds_bytes = 160 * 1024 - 1024;
-  if (batch_lds_setup(b->lds_bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    b->lds_bytes = 64 * 1024;
-    (void)batch_lds_setup(b->lds_bytes);
-  }
+  const DeviceSetup *ds = device_setup();
+  if (!ds) return bail(AGG_E_DEVICE);
+  b->lds_bytes = ds->lds_max;
   b->nslots = (b->lds_bytes / b->W8) & ~3u;  // whole groups of four slots
   b->cap = (uint32_t)(b->nslots * kLoad);
-  b->blocks = (uint32_t)batch_resident_blocks(kBlock, b->lds_bytes);
+  b->blocks = (uint32_t)(ds->batch_per_cu * ds->cus);
   b->st.blocks = b->blocks;
   for (uint32_t i = 0; i < n_inst; ++i) {
     const double G = inst[i].est_groups ? (double)inst[i].est_groups : (double)inst[i].n;

@@ -240,11 +240,22 @@ hipError_t launch_run_scan(hipStream_t s, const uint32_t *tile_heads, uint64_t t
 hipError_t launch_rows_init(hipStream_t s, const KSpec &ks, const OutCols &cols, uint64_t n);
 hipError_t launch_run_reduce(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, const uint32_t *tile_heads,
                              const unsigned long long *tile_base, Ctrl *ctrl, uint64_t *out_keys, const OutCols &cols);
+// Launch configuration of the current device, established once per device
+// (under a lock, before its first use) and read-only afterwards: kernel
+// attributes are set and occupancy is queried only here, never from the
+// launch paths that concurrent host threads run.
+struct DeviceSetup {
+  uint32_t lds_max;            // dynamic LDS bytes the LDS-sized kernels may be launched with
+  int cus;                     // compute units
+  int update_per_cu[2][2][4];  // k_update<kind, preagg> blocks per CU without dynamic LDS, block = 64 (i + 1)
+  int batch_per_cu;            // k_batch blocks per CU at lds_max
+};
+const DeviceSetup *device_setup();
 // Largest dynamic LDS the LDS-aggregation kernel can be launched with (bytes).
 uint32_t lds_agg_max_bytes();
-// Batched mode.
-hipError_t batch_lds_setup(uint32_t lds_bytes);
-int batch_resident_blocks(uint32_t block, uint32_t lds_bytes);
+// Per-kernel parts of the setup (called by device_setup only).
+hipError_t update_occupancy(int kind, int preagg, uint32_t block, int *per_cu);
+hipError_t batch_kernel_setup(uint32_t lds_bytes, int *per_cu);
 hipError_t launch_batch(hipStream_t s, const BParams &P, uint32_t blocks, uint32_t block, uint32_t lds_bytes);
 uint64_t hll_seed();
 }  // namespace aggx

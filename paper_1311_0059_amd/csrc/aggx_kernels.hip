@@ -422,33 +422,25 @@ hipError_t launch_ctrl_init(hipStream_t s, Ctrl *c, const KSpec &ks) {
   return hipGetLastError();
 }
 
-// Blocks of k_update that fit on the device at once (occupancy x compute units).
-// Several host threads launch concurrently (one per request in served mode), so
-// the occupancy answers are cached per device and launch shape under a lock and
-// the HIP queries behind them never run concurrently.
+// Blocks of k_update that fit on the device at once: the kernel's own limit
+// per compute unit (registers and waves, from the device setup) and the
+// compute unit's 160 KB of LDS, counted in whole kilobytes.
 static int resident_blocks(uint32_t block, size_t lds, int preagg, int kind) {
-  static std::mutex mu;
-  static std::map<std::tuple<int, uint32_t, size_t, int, int>, int> cache;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 1024;
-  const auto key = std::make_tuple(dev, block, lds, preagg, kind);
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find(key);
-  if (it != cache.end()) return it->second;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 1024;
-  int per_cu = 0;
-  hipError_t e;
+  const DeviceSetup *ds = device_setup();
+  if (!ds) return 1024;
+  const int i = (int)std::min<uint32_t>(3, std::max<uint32_t>(1, block / 64) - 1);
+  int per_cu = ds->update_per_cu[kind ? 1 : 0][preagg ? 1 : 0][i];
+  const size_t granule = (lds + 1023) / 1024 * 1024;
+  if (granule) per_cu = std::min<int>(per_cu, (int)((160 * 1024) / granule));
+  return std::max(1, per_cu) * ds->cus;
+}
+
+hipError_t update_occupancy(int kind, int preagg, uint32_t block, int *per_cu) {
   if (kind == 0)
-    e = preagg ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_update<0, 1>, block, lds)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_update<0, 0>, block, lds);
-  else
-    e = preagg ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_update<1, 1>, block, lds)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_update<1, 0>, block, lds);
-  if (e != hipSuccess || per_cu < 1) per_cu = 1;
-  const int blocks = per_cu * prop.multiProcessorCount;
-  cache.emplace(key, blocks);
-  return blocks;
+    return preagg ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_update<0, 1>, block, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_update<0, 0>, block, 0);
+  return preagg ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_update<1, 1>, block, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_update<1, 0>, block, 0);
 }
 
 hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint64_t n, const KSpec &ks,

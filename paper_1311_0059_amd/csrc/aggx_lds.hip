@@ -511,24 +511,10 @@ __global__ void __launch_bounds__(256) k_merge_rows(const uint64_t *__restrict__
 }
 
 // The count and scatter kernels' LDS grows with the fan-out (4 and 8 bytes per
-// partition); above 64 KB a kernel must be allowed more, once per device and
-// kernel, under a lock.
-static bool kernel_lds_allowed(const void *fn, size_t lds) {
-  static std::mutex mu;
-  static std::map<std::pair<int, const void *>, size_t> allowed;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return false;
-  std::lock_guard<std::mutex> lk(mu);
-  size_t &a = allowed[{dev, fn}];
-  if (a < 65536) a = 65536;
-  if (lds <= a) return true;
-  if (lds > 160 * 1024 - 1024 ||
-      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  a = lds;
-  return true;
+// partition); the device setup allowed them the most a workgroup can take.
+static bool kernel_lds_allowed(size_t lds) {
+  const DeviceSetup *ds = device_setup();
+  return ds && lds <= ds->lds_max;
 }
 
 hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
@@ -539,7 +525,7 @@ hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const
   const uint64_t blocks = (n + chunk - 1) / chunk;
   // (its frequent-key arrays take another ~17 KB of static LDS)
   constexpr size_t kStatic = 12ull * kHotSlots + 4ull * kMaxHot + 8ull * kMaxAggs * kMaxHot;
-  if (!kernel_lds_allowed(reinterpret_cast<const void *>(k_part_count), 4ull * (mask + 1) + kStatic))
+  if (!kernel_lds_allowed(4ull * (mask + 1) + kStatic))
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_part_count, dim3((uint32_t)blocks), dim3(kPartBlock), 4ull * (mask + 1), s, in, n, ks, shift,
                      mask, chunk, totals, block_counts, hot);
@@ -562,7 +548,7 @@ hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, con
   const uint64_t blocks = (n + chunk - 1) / chunk;
   if (n >= (1ull << 32)) return hipErrorInvalidValue;  // the LDS bases are 32-bit record indices
   const size_t lds = 8ull * d_n + 12ull * kHotSlots;
-  if (!kernel_lds_allowed(reinterpret_cast<const void *>(k_part_scatter), lds)) return hipErrorInvalidValue;
+  if (!kernel_lds_allowed(lds)) return hipErrorInvalidValue;
   const uintptr_t a = reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(in);
   const uint32_t vec = ks.rb % 16 == 0 && a % 16 == 0 ? 16 : ks.rb % 8 == 0 && a % 8 == 0 ? 8 : 4;
   hipLaunchKernelGGL(k_part_scatter, dim3((uint32_t)blocks), dim3(kPartBlock), lds, s, in, n, ks, shift, mask, d_lo,
@@ -597,27 +583,50 @@ hipError_t launch_hot_rows(hipStream_t s, const KHot &hot, const KSpec &ks, uint
   return hipGetLastError();
 }
 
-// Per device, once, under a lock: concurrent host threads never set the
-// kernel's attribute at the same time.
-uint32_t lds_agg_max_bytes() {
+// Per device, once, under a lock, before the device's first launch: every
+// attribute the kernels need is set here and every occupancy answer the launch
+// paths use is computed here, so that host threads launching concurrently
+// (served mode runs one per request) never reconfigure a kernel another thread
+// is launching.  gfx950 has 160 KB of LDS per compute unit: the LDS-sized
+// kernels may take most of it.
+const DeviceSetup *device_setup() {
+  constexpr int kMaxDev = 64;
   static std::mutex mu;
-  static std::map<int, uint32_t> cache;
+  static DeviceSetup table[kMaxDev];
+  static bool ready[kMaxDev] = {};
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return nullptr;
   std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find(dev);
-  if (it != cache.end()) return it->second;
-  // gfx950 has 160 KB of LDS per compute unit; ask for most of it, else 64 KB
+  if (ready[dev]) return &table[dev];
+  DeviceSetup ds{};
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return nullptr;
+  ds.cus = prop.multiProcessorCount;
   const uint32_t want = 160 * 1024 - 1024;
-  uint32_t got = 64 * 1024;
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_agg<false>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) == hipSuccess &&
-      hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_agg<true>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) == hipSuccess)
-    got = want;
+  ds.lds_max = 64 * 1024;
+  const void *fns[] = {reinterpret_cast<const void *>(k_part_count), reinterpret_cast<const void *>(k_part_scatter),
+                       reinterpret_cast<const void *>(k_lds_agg<false>), reinterpret_cast<const void *>(k_lds_agg<true>)};
+  bool all = true;
+  for (const void *fn : fns) all &= hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) == hipSuccess;
   (void)hipGetLastError();
-  cache.emplace(dev, got);
-  return got;
+  if (all) ds.lds_max = want;
+  for (int kind = 0; kind < 2; ++kind)
+    for (int pre = 0; pre < 2; ++pre)
+      for (int i = 0; i < 4; ++i) {
+        int per = 0;
+        if (update_occupancy(kind, pre, 64u * (i + 1), &per) != hipSuccess || per < 1) per = 1;
+        ds.update_per_cu[kind][pre][i] = per;
+      }
+  if (batch_kernel_setup(ds.lds_max, &ds.batch_per_cu) != hipSuccess || ds.batch_per_cu < 1) ds.batch_per_cu = 1;
+  (void)hipGetLastError();
+  table[dev] = ds;
+  ready[dev] = true;
+  return &table[dev];
+}
+
+uint32_t lds_agg_max_bytes() {
+  const DeviceSetup *ds = device_setup();
+  return ds ? ds->lds_max : 64 * 1024;
 }
 
 hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long long *offsets, uint32_t F,

@@ -1342,6 +1342,8 @@ agg_status agg_create(const agg_spec *spec, agg_handle **out) {
   agg_status s = validate(spec);
   if (s) return s;
   if (spec->budget_bytes && spec->budget_bytes < agg_min_budget(spec)) return AGG_E_BUDGET;
+  // the device's launch configuration, once, before this handle launches anything
+  if (!device_setup()) return AGG_E_DEVICE;
   agg_handle *h = new (std::nothrow) agg_handle();
   if (!h) return AGG_E_NOMEM;
   h->spec = *spec;

@@ -167,8 +167,8 @@ void worker(agg_server *s, uint32_t slot) {
 extern "C" {
 
 agg_status agg_server_create(const agg_server_config *cfg, agg_server **out) {
-  if (!cfg || !out || cfg->pool_bytes < (1u << 20) || cfg->max_inflight < 1 || cfg->max_inflight > 64 ||
-      cfg->reserved)
+  if (!cfg || !out || cfg->pool_bytes < (1u << 20) || cfg->max_inflight < 1 ||
+      cfg->max_inflight > AGG_SERVER_MAX_INFLIGHT || cfg->reserved)
     return AGG_E_INVALID;
   *out = nullptr;
   agg_server *s = new (std::nothrow) agg_server();
@@ -181,7 +181,11 @@ agg_status agg_server_create(const agg_server_config *cfg, agg_server **out) {
   }
   s->alloc.init(cfg->pool_bytes / kAlign * kAlign);
   // one-time launch configuration of the device, before any worker runs
-  (void)aggx::lds_agg_max_bytes();
+  if (!aggx::device_setup()) {
+    (void)hipFree(s->pool);
+    delete s;
+    return AGG_E_DEVICE;
+  }
   for (uint32_t i = 0; i < cfg->max_inflight; ++i) {
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
