@@ -7,6 +7,8 @@ its Python binding never do, and the two share no code.
 
 Contents:
   groupby(records, spec)        -- the result rows (the paper, Sec. 3.1; method of Sec. 4.1, Phase 2)
+  groupby_par(records, spec)    -- the same rows on all host threads (the sort split by leading key bits)
+  host_threads(), cpu_model()   -- the thread count groupby_par uses by default, and the host CPU's name
   rows_for_keys(records, spec, keys) -- the rows of chosen keys by one scan (sampled checks at full size)
   totals(records, spec)         -- whole-input COUNT / wrap-around SUM / MIN / MAX (invariants)
   yao_i_key, yao_i_raw          -- Appendix, input component (Yao's formula, draws without replacement)
@@ -37,10 +39,10 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile liboracle.so (gcc -O2, single-threaded) next to its source."""
+    """Compile liboracle.so (gcc -O2; pthreads for groupby_par) next to its source."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-pthread", "-o", tmp, _SRC])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -53,6 +55,8 @@ def _load():
         vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
         lib.oracle_groupby.argtypes = [vp, u64, u32, u32, vp, vp, u32, vp, vp, vp, u64, vp, vp]
         lib.oracle_groupby.restype = ctypes.c_int64
+        lib.oracle_groupby_par.argtypes = [vp, u64, u32, u32, vp, vp, u32, vp, vp, vp, u64, vp, vp, u32, u32]
+        lib.oracle_groupby_par.restype = ctypes.c_int64
         lib.oracle_rows_for_keys.argtypes = [vp, u64, u32, u32, vp, vp, u32, vp, vp, vp, vp, u64, vp, vp]
         lib.oracle_rows_for_keys.restype = ctypes.c_int
         lib.oracle_totals.argtypes = [vp, u64, u32, u32, vp, vp, vp, vp]
@@ -97,6 +101,48 @@ def groupby(records: np.ndarray, spec) -> tuple[np.ndarray, np.ndarray]:
     if rows < 0:
         raise ValueError("oracle: invalid spec")
     return keys[:rows].copy(), cols[:, :rows].copy()
+
+
+def host_threads() -> int:
+    """Threads for groupby_par: OMP_NUM_THREADS when set (the host's share of cores), else the
+    cores this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def groupby_par(records: np.ndarray, spec, threads: int | None = None, bits: int = 12):
+    """The rows of groupby (sorted by key), computed on `threads` threads (default host_threads()).
+    `bits` is the width of the leading-key-bits digit that splits the sort (1..16)."""
+    rb = spec["record_bytes"]
+    buf = _raw(records, rb)
+    n = buf.size // rb
+    koff, ktype, op, ioff, itype = _spec_arrays(spec)
+    na = len(spec["aggs"])
+    cap = max(n, 1)
+    keys = np.empty(cap, dtype=np.uint64)
+    cols = np.empty((na, cap), dtype=np.int64)
+    t = host_threads() if threads is None else threads
+    rows = _load().oracle_groupby_par(buf.ctypes.data, n, rb, len(spec["keys"]), koff.ctypes.data, ktype.ctypes.data,
+                                      na, op.ctypes.data, ioff.ctypes.data, itype.ctypes.data, cap, keys.ctypes.data,
+                                      cols.ctypes.data, t, bits)
+    if rows < 0:
+        raise ValueError("oracle: invalid spec, thread count or digit width, or out of memory")
+    return keys[:rows], cols[:, :rows]
 
 
 def rows_for_keys(records: np.ndarray, spec, qkeys) -> tuple[np.ndarray, np.ndarray, np.ndarray]:

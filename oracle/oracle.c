@@ -29,7 +29,12 @@
  *   - empty input gives zero rows.
  * Output: rows sorted by key ascending (unsigned 64-bit), each aggregate as a
  * 64-bit two's-complement value.
+ *
+ * oracle_groupby_par computes the same rows with several threads, for inputs
+ * too large for one: the sort step is split by the key's leading bits (see
+ * there); the grouping scan is the same.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -133,6 +138,178 @@ int64_t oracle_groupby(const void *records, uint64_t n, uint32_t rb, uint32_t nk
   for (uint32_t a = 0; a < na; ++a) out_cols[a * cap + rows] = (int64_t)acc[a];
   ++rows;
   free(p);
+  return rows;
+}
+
+/* ---- the same sort-then-scan on several threads ------------------------------------------------ */
+
+/* Run fn(arg, item) for item = 0..n_items-1 on `threads` threads; each thread
+ * takes the next unclaimed item until none is left. */
+typedef struct {
+  void (*fn)(void *, uint64_t);
+  void *arg;
+  uint64_t n_items;
+  uint64_t next;
+} or_pool;
+
+static void *or_worker(void *p) {
+  or_pool *w = (or_pool *)p;
+  for (;;) {
+    uint64_t it = __atomic_fetch_add(&w->next, 1, __ATOMIC_RELAXED);
+    if (it >= w->n_items) return NULL;
+    w->fn(w->arg, it);
+  }
+}
+
+static int or_run(uint32_t threads, uint64_t n_items, void (*fn)(void *, uint64_t), void *arg) {
+  or_pool w = {fn, arg, n_items, 0};
+  pthread_t *tid = (pthread_t *)malloc(sizeof(pthread_t) * threads);
+  if (!tid) return -1;
+  uint32_t started = 0;
+  for (; started < threads; ++started)
+    if (pthread_create(&tid[started], NULL, or_worker, &w)) break;
+  if (started == 0) or_worker(&w); /* no thread could start: do the work here */
+  for (uint32_t t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+  free(tid);
+  return 0;
+}
+
+typedef struct {
+  const uint8_t *base;
+  uint64_t n, chunk;
+  uint32_t rb, nk, na, bits, nchunks;
+  const uint32_t *koff, *ktype, *op, *in_off, *in_type;
+  uint64_t nb;         /* buckets: 2^bits */
+  or_pair *pairs;      /* (key, record index), input order */
+  or_pair *sorted;     /* the same pairs, bucket by bucket */
+  uint64_t *hist;      /* nchunks x nb counts, then scatter cursors */
+  uint64_t *bstart;    /* nb + 1 bucket starts in `sorted` */
+  uint64_t *brows;     /* rows per bucket, then each bucket's first output row */
+  uint64_t cap;
+  uint64_t *out_keys;
+  int64_t *out_cols;
+} or_par;
+
+/* bucket of a key: its leading `bits` bits (bucket order is key order) */
+static uint64_t or_bucket(uint64_t key, uint32_t bits) { return key >> (64 - bits); }
+
+/* pass 1, per chunk of records: canonical keys, and the chunk's bucket counts */
+static void or_par_keys(void *arg, uint64_t c) {
+  or_par *P = (or_par *)arg;
+  uint64_t lo = c * P->chunk, hi = lo + P->chunk < P->n ? lo + P->chunk : P->n;
+  uint64_t *h = P->hist + c * P->nb;
+  for (uint64_t i = lo; i < hi; ++i) {
+    uint64_t k = or_key(P->base + i * P->rb, P->nk, P->koff, P->ktype);
+    P->pairs[i].key = k;
+    P->pairs[i].idx = i;
+    h[or_bucket(k, P->bits)] += 1;
+  }
+}
+
+/* pass 2, per chunk: move each pair to its bucket (cursors prepared from the counts) */
+static void or_par_scatter(void *arg, uint64_t c) {
+  or_par *P = (or_par *)arg;
+  uint64_t lo = c * P->chunk, hi = lo + P->chunk < P->n ? lo + P->chunk : P->n;
+  uint64_t *cur = P->hist + c * P->nb;
+  for (uint64_t i = lo; i < hi; ++i) P->sorted[cur[or_bucket(P->pairs[i].key, P->bits)]++] = P->pairs[i];
+}
+
+/* pass 3, per bucket: sort it on the key and count its distinct keys */
+static void or_par_sort(void *arg, uint64_t b) {
+  or_par *P = (or_par *)arg;
+  or_pair *q = P->sorted + P->bstart[b];
+  uint64_t m = P->bstart[b + 1] - P->bstart[b];
+  qsort(q, m, sizeof(or_pair), or_cmp);
+  uint64_t rows = 0;
+  for (uint64_t i = 0; i < m; ++i) rows += (i == 0 || q[i].key != q[i - 1].key);
+  P->brows[b] = rows;
+}
+
+/* pass 4, per bucket: the grouping scan of oracle_groupby, rows written from the bucket's first row */
+static void or_par_scan(void *arg, uint64_t b) {
+  or_par *P = (or_par *)arg;
+  const or_pair *q = P->sorted + P->bstart[b];
+  uint64_t m = P->bstart[b + 1] - P->bstart[b], row = P->brows[b];
+  uint64_t acc[8];
+  for (uint64_t i = 0; i < m; ++i) {
+    const uint8_t *rec = P->base + q[i].idx * P->rb;
+    int first = (i == 0) || (q[i].key != q[i - 1].key);
+    if (first && i > 0) {
+      P->out_keys[row] = q[i - 1].key;
+      for (uint32_t a = 0; a < P->na; ++a) P->out_cols[a * P->cap + row] = (int64_t)acc[a];
+      ++row;
+    }
+    for (uint32_t a = 0; a < P->na; ++a)
+      or_fold(&acc[a], P->op[a], P->in_type[a], or_read(rec, P->in_off[a], P->in_type[a]), first);
+  }
+  if (m) {
+    P->out_keys[row] = q[m - 1].key;
+    for (uint32_t a = 0; a < P->na; ++a) P->out_cols[a * P->cap + row] = (int64_t)acc[a];
+  }
+}
+
+/*
+ * The rows of oracle_groupby (same arguments and output), computed on
+ * `threads` threads.  The sort step is split by the key's leading `bits` bits
+ * (1..16): bucket b holds exactly the keys k with k >> (64 - bits) == b, so
+ * the buckets taken in order hold the keys in order, and every record of a key
+ * is in one bucket.  The pairs (key, record index) are counted per bucket,
+ * moved into their buckets, each bucket is sorted (qsort) and scanned into
+ * rows exactly as in oracle_groupby; bucket b's rows follow bucket b-1's.
+ */
+int64_t oracle_groupby_par(const void *records, uint64_t n, uint32_t rb, uint32_t nk, const uint32_t *koff,
+                           const uint32_t *ktype, uint32_t na, const uint32_t *op, const uint32_t *in_off,
+                           const uint32_t *in_type, uint64_t cap, uint64_t *out_keys, int64_t *out_cols,
+                           uint32_t threads, uint32_t bits) {
+  if (or_check(rb, nk, koff, ktype, na, op, in_off, in_type)) return -1;
+  if (threads < 1 || bits < 1 || bits > 16) return -1;
+  if (n == 0) return 0;
+  if (cap < n) return -1;
+  or_par P;
+  memset(&P, 0, sizeof(P));
+  P.base = (const uint8_t *)records;
+  P.n = n;
+  P.rb = rb; P.nk = nk; P.na = na; P.bits = bits;
+  P.koff = koff; P.ktype = ktype; P.op = op; P.in_off = in_off; P.in_type = in_type;
+  P.nb = 1ull << bits;
+  P.nchunks = threads;
+  P.chunk = (n + threads - 1) / threads;
+  P.cap = cap; P.out_keys = out_keys; P.out_cols = out_cols;
+  P.pairs = (or_pair *)malloc(sizeof(or_pair) * n);
+  P.sorted = (or_pair *)malloc(sizeof(or_pair) * n);
+  P.hist = (uint64_t *)calloc((uint64_t)P.nchunks * P.nb, sizeof(uint64_t));
+  P.bstart = (uint64_t *)malloc(sizeof(uint64_t) * (P.nb + 1));
+  P.brows = (uint64_t *)malloc(sizeof(uint64_t) * P.nb);
+  int64_t rows = -1;
+  if (!P.pairs || !P.sorted || !P.hist || !P.bstart || !P.brows) goto done;
+  if (or_run(threads, P.nchunks, or_par_keys, &P)) goto done;
+  /* bucket starts, and each chunk's cursor inside each bucket (chunks in input order) */
+  uint64_t at = 0;
+  for (uint64_t b = 0; b < P.nb; ++b) {
+    P.bstart[b] = at;
+    for (uint32_t c = 0; c < P.nchunks; ++c) {
+      uint64_t cnt = P.hist[(uint64_t)c * P.nb + b];
+      P.hist[(uint64_t)c * P.nb + b] = at;
+      at += cnt;
+    }
+  }
+  P.bstart[P.nb] = at;
+  if (or_run(threads, P.nchunks, or_par_scatter, &P)) goto done;
+  if (or_run(threads, P.nb, or_par_sort, &P)) goto done;
+  uint64_t total = 0;
+  for (uint64_t b = 0; b < P.nb; ++b) {
+    uint64_t r = P.brows[b];
+    P.brows[b] = total;
+    total += r;
+  }
+  if (or_run(threads, P.nb, or_par_scan, &P)) goto done;
+  rows = (int64_t)total;
+done:
+  free(P.pairs);
+  free(P.sorted);
+  free(P.hist);
+  free(P.bstart);
+  free(P.brows);
   return rows;
 }
 

@@ -68,18 +68,44 @@ def _same(a, b):
     return ka.shape == kb.shape and np.array_equal(ka, kb) and np.array_equal(ca, cb)
 
 
+BRUTE_CASES = 3400  # per layout: 10,200 tiny inputs in all
+
+
+def _par(rec, spec, rng):
+    """The parallel path with a random thread count and digit width (many buckets on tiny inputs)."""
+    return oracle.groupby_par(rec, spec, threads=int(rng.integers(1, 6)), bits=int(rng.integers(1, 17)))
+
+
 @pytest.mark.parametrize("layout", ["R16", "R24", "MIX"])
 def test_oracle_matches_brute_force(layout):
-    """Many tiny seeded inputs with keys and values at the edges of their types."""
+    """Many tiny seeded inputs with keys and values at the edges of their types, through both the
+    single-threaded oracle and its parallel form."""
     rng = np.random.default_rng(1311 + len(layout))
     gen, spec = {"R16": (_rand_r16, SPEC_R16), "R24": (_rand_r24, SPEC_R24), "MIX": (_rand_mix, SPEC_MIX)}[layout]
-    for case in range(700):
-        n = int(rng.integers(0, 200 if case % 10 else 1500))
+    for case in range(BRUTE_CASES):
+        n = int(rng.integers(0, 120 if case % 10 else 1200))
         pool = _pool(rng, int(rng.integers(1, 50)))
         rec = gen(rng, n, pool)
-        got = oracle.groupby(rec, spec)
         want = brute_force(rec, spec)
-        assert _same(got, want), f"case {case} n={n}"
+        assert _same(oracle.groupby(rec, spec), want), f"case {case} n={n}"
+        assert _same(_par(rec, spec, rng), want), f"case {case} n={n} (parallel)"
+
+
+def test_parallel_oracle_on_workloads():
+    """The parallel form gives the single-threaded oracle's rows on generated workloads, for
+    several thread counts and digit widths, and rejects invalid arguments."""
+    for wl in (workloads.uniform_small().scaled(300_000, 20_000), workloads.zipf_composite().scaled(300_000, 30_000),
+               workloads.heavy_hitter(50_000, 300)):
+        rec = wl.generate()
+        spec = oracle_spec(wl)
+        want = oracle.groupby(rec, spec)
+        for threads, bits in ((1, 1), (2, 7), (7, 12), (16, 16)):
+            assert _same(oracle.groupby_par(rec, spec, threads=threads, bits=bits), want), (wl.name, threads, bits)
+    rec = datagen.r16(5, 100, 10)
+    for threads, bits in ((0, 8), (4, 0), (4, 17)):
+        with pytest.raises(ValueError):
+            oracle.groupby_par(rec, SPEC_R16, threads=threads, bits=bits)
+    assert oracle.groupby_par(np.empty(0, dtype=datagen.R16), SPEC_R16)[0].size == 0
 
 
 def test_empty_input_gives_no_rows():
@@ -244,6 +270,30 @@ def test_formula_one_partitions_cover_the_groups():
         oracle.hybrid_hash_partitions(10, 2)
 
 
+def test_spilled_fraction_against_simulation():
+    """Secs. 5.3.1 / 5.3.4: with uniform keys and K of the G_t groups resident, the records spilled
+    are R (1 - K / G_t).  Checked against simulated streams in which the first K distinct keys stay
+    resident (Pre-Partitioning's partition 0, Sec. 4.3.4) and every record of another key is
+    spilled, within 3%, for several K / G_t: keys drawn uniformly with replacement (200 records per
+    key, so the keys seen first are barely more frequent than the others), and the dataset D(n, m)
+    of the Appendix (every key exactly n / m times, in random order)."""
+    rng = np.random.default_rng(53)
+    G, N = 5_000, 1_000_000
+    streams = (rng.integers(0, G, size=N), rng.permutation(np.repeat(np.arange(G), N // G)))
+    for keys in streams:
+        first_seen = np.full(G, N)
+        np.minimum.at(first_seen, keys, np.arange(keys.size))
+        order = np.argsort(first_seen, kind="stable")
+        for frac in (0.1, 0.3, 0.55, 0.8):
+            K = int(frac * G)
+            resident = np.zeros(G, dtype=bool)
+            resident[order[:K]] = True
+            spilled = int(np.count_nonzero(~resident[keys]))
+            model = keys.size * oracle.spilled_fraction(K, G)
+            assert abs(spilled - model) / model < 0.03, (frac, spilled, model)
+    assert oracle.spilled_fraction(G, G) == 0.0 and oracle.spilled_fraction(2 * G, G) == 0.0
+
+
 # ---- planted mistakes: each mutant of the oracle must fail one of the pins above --------------------
 
 MUTANTS = {
@@ -256,6 +306,14 @@ MUTANTS = {
                    "case OR_MAX: if (first || or_less(v, *acc, type)) *acc = v; break;"),
     "i32_zero_extend": ("case OR_I32: { int32_t x; memcpy(&x, rec + off, 4); return (uint64_t)(int64_t)x; }",
                         "case OR_I32: { uint32_t x; memcpy(&x, rec + off, 4); return (uint64_t)x; }"),
+    # mistakes in the parallel form only
+    "par_bucket_low_bits": ("static uint64_t or_bucket(uint64_t key, uint32_t bits) { return key >> (64 - bits); }",
+                            "static uint64_t or_bucket(uint64_t key, uint32_t bits) { return key & ((1ull << bits) - 1); }"),
+    "par_bucket_start_late": ("      at += cnt;\n    }\n  }\n  P.bstart[P.nb] = at;",
+                              "      at += cnt;\n    }\n    P.bstart[b] = at;\n  }\n  P.bstart[P.nb] = at;"),
+    "par_drop_bucket_last_row": ("  if (m) {\n    P->out_keys[row] = q[m - 1].key;", "  if (m && 0) {\n    P->out_keys[row] = q[m - 1].key;"),
+    "par_skip_last_bucket": ("  if (or_run(threads, P.nb, or_par_scan, &P)) goto done;",
+                             "  if (or_run(threads, P.nb - 1, or_par_scan, &P)) goto done;"),
 }
 
 
@@ -269,12 +327,14 @@ def test_pins_catch_planted_mistakes(name, monkeypatch):
         path = os.path.join(tmp, "oracle.c")
         open(path, "w").write(src.replace(old, new))
         lib = os.path.join(tmp, "liboracle.so")
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-o", lib, path])
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-pthread", "-o", lib, path])
         import ctypes
         mut = ctypes.CDLL(lib)
         vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
         mut.oracle_groupby.argtypes = [vp, u64, u32, u32, vp, vp, u32, vp, vp, vp, u64, vp, vp]
         mut.oracle_groupby.restype = ctypes.c_int64
+        mut.oracle_groupby_par.argtypes = [vp, u64, u32, u32, vp, vp, u32, vp, vp, vp, u64, vp, vp, u32, u32]
+        mut.oracle_groupby_par.restype = ctypes.c_int64
         monkeypatch.setattr(oracle, "_lib", None)
         real_load = oracle._load
 
@@ -282,16 +342,21 @@ def test_pins_catch_planted_mistakes(name, monkeypatch):
             real = real_load()
             class L:
                 oracle_groupby = mut.oracle_groupby
+                oracle_groupby_par = mut.oracle_groupby_par
                 oracle_rows_for_keys = real.oracle_rows_for_keys
                 oracle_totals = real.oracle_totals
             return L
         monkeypatch.setattr(oracle, "_load", fake_load)
+        # a mutant of code both forms share must fail the single-threaded pin; one of the
+        # parallel form's own code must fail the parallel pin
+        form = oracle.groupby_par if name.startswith("par_") else oracle.groupby
         caught = False
         rng = np.random.default_rng(2024)
         for layout, gen, spec in (("R16", _rand_r16, SPEC_R16), ("R24", _rand_r24, SPEC_R24), ("MIX", _rand_mix, SPEC_MIX)):
             for _ in range(40):
                 rec = gen(rng, int(rng.integers(1, 120)), _pool(rng, int(rng.integers(1, 20))))
-                if not _same(oracle.groupby(rec, spec), brute_force(rec, spec)):
+                got = form(rec, spec, threads=3, bits=4) if form is oracle.groupby_par else form(rec, spec)
+                if not _same(got, brute_force(rec, spec)):
                     caught = True
                     break
             if caught:
