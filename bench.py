@@ -4,16 +4,22 @@
 A step is one whole query through the C ABI over one batch that is already
 resident in HBM: agg_create (on a preallocated workspace of the budget's size)
 + agg_consume + agg_finish (every recursion level, result rows in HBM) +
-agg_destroy.  Default workload: 200M R16 records {u64 key, i64 v}, 20M
-distinct uniform keys, v uniform in [-1e6, 1e6], COUNT+SUM+MIN+MAX, 1 GiB
-device budget (too small for the partitioned batch or for tables at the
-default load: the library reads the batch in passes of partitions, or with
-`--engine tables` packs its HBM tables to keep every group resident).
+agg_destroy.
 
-Prints one JSON line.  `roofline` describes the dominant kernel (the level-0
-aggregation/routing kernel), timed with HIP events recorded by the library on
-the stream it launches on; `cpu_baseline` is the CPU oracle timed on a bounded
-sample of the same input on this host.
+Default workload: 500M R24 records {u32 k1, u32 k2, i64 v1, i32 v2, i32 v3},
+50M distinct composite keys drawn Zipf s=1.0, SUM(v1) MIN(v2) MAX(v3) COUNT,
+4 GiB device budget -- the largest single query.  Beside it, under "extra",
+the 200M-record R16 query with 20M uniform keys and a 1 GiB budget (too small
+for the partitioned batch: the library reads the batch in passes of
+partitions).
+
+Prints one JSON line.  `roofline` describes the kernel that took the most
+device time, timed with HIP events recorded by the library on the stream it
+launches on; its algorithmic bytes are the query's algorithmic bytes per record
+(input read once + result rows written once, divided by the records) times the
+records its launches processed.  `step_frac` is the whole step's algorithmic
+bytes over its wall time, against the same peak.  `cpu_baseline` is the
+oracle's parallel sort-then-scan over the whole input on this host's cores.
 """
 from __future__ import annotations
 
@@ -29,9 +35,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 METRIC = "input records/s + % HBM peak (bit-exact); served p50/p99 latency vs plain path"
 
+DEFAULT_WORKLOAD = "zipf-composite"  # 500M R24 records, 50M Zipf keys, 4 GiB: the largest single query
+EXTRA_WORKLOAD = "uniform-spill"     # 200M R16 records, 20M uniform keys, 1 GiB
+
 WORKLOADS = {
     "uniform-spill": "uniform_spill",
     "uniform-small": "uniform_small",
+    "uniform-1g": "uniform_small_1g",
     "uniform-inmem": "uniform_inmem",
     "zipf-composite": "zipf_composite",
     "batched": "batched_mix",
@@ -47,12 +57,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="uniform-spill", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-extra", dest="extra", action="store_false",
+                    help=f"with the default workload, skip the {EXTRA_WORKLOAD} query reported under 'extra'")
     ap.add_argument("--policy", default="destage", choices=["destage", "prepart"])
     ap.add_argument("--engine", default="auto", choices=["auto", "tables", "lds", "owner", "sorted"],
                     help="engine for the first batch (auto = the library's choice)")
-    ap.add_argument("--cpu-sample", type=int, default=48_000_000,
-                    help="records of the input the CPU oracle is timed on (0 = skip)")
+    ap.add_argument("--cpu-runs", type=int, default=3,
+                    help="runs of the CPU oracle over the whole input (median reported; 0 = skip)")
     ap.add_argument("--requests", type=int, default=120, help="served: requests in the trace")
     ap.add_argument("--load", type=float, default=0.8, help="served: offered load vs the plain path's capacity")
     ap.add_argument("--inflight", type=int, default=6, help="served: requests running at once (the library accepts at most 6)")
@@ -75,13 +87,6 @@ def main():
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
 
-    import numpy as np
-    import torch
-
-    import datagen
-    import paper_1311_0059_amd as P
-    from datagen import workloads
-
     if args.calibrate_copy:
         return calibrate_copy(args)
     if args.workload == "batched":
@@ -92,7 +97,68 @@ def main():
         return bench_first_rows(args)
     if args.workload == "served":
         return bench_served(args)
-    wl = getattr(workloads, WORKLOADS[args.workload])()
+    out = bench_query(args, args.workload, with_cpu=rank == 0 and args.cpu_runs > 0)
+    if args.extra and args.workload == DEFAULT_WORKLOAD:
+        # the 200M-record / 1 GiB query beside the headline one, on the same GPU
+        extra = bench_query(args, EXTRA_WORKLOAD, with_cpu=False)
+        out["extra"] = {k: extra[k] for k in ("value", "unit", "ms_per_step", "config", "gbps_algorithmic",
+                                              "pct_hbm_peak", "rows_ok", "per_step", "roofline")}
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+def dominant_kernel(agg, steps, n, alg_per_record):
+    """The kernel that took the most device time in the steps, its launches, HIP-event time and
+    algorithmic bytes: the per-record algorithmic bytes of the query times the records the
+    launches processed (records they partitioned, aggregated or routed)."""
+    engine = agg["engine"] // steps
+    if engine == 5:  # on-chip engine: one pass reads every record once
+        return "k_onchip", steps, agg["onchip_ms"], n * steps * alg_per_record
+    if engine == 4:  # sorted runs: the check/count pass and the run reduction read every record
+        return "k_run_heads+k_run_reduce", steps, agg["sorted_ms"], n * steps * alg_per_record
+    if agg["update_launches_l0"]:
+        kname = "k_owner_update" if engine == 3 else f"k_update<0, {1 if agg['preagg'] else 0}>"
+        return kname, agg["update_launches_l0"], agg["update_ms_l0"], agg["update_records_l0"] * alg_per_record
+    # the partition-first LDS engine: each scatter launch reads the batch and writes one run of
+    # partitions; each aggregation launch reads that run back.  Both are charged the records of
+    # the run (every non-frequent record once per step), not the rest of the batch they skip.
+    recs = agg["scatter_records"]
+    if agg["scatter_ms"] > agg["lds_ms"]:
+        return "k_part_scatter", agg["scatter_launches"], agg["scatter_ms"], recs * alg_per_record
+    return "k_lds_agg", agg["lds_launches"], agg["lds_ms"], recs * alg_per_record
+
+
+def cpu_oracle_baseline(args, host, wl):
+    """The oracle (parallel sort-then-scan) on the whole input on this host's cores: median of
+    `--cpu-runs` runs, generation excluded."""
+    import oracle
+    from tests.wl import oracle_spec  # the oracle's own spec format
+    threads = oracle.host_threads()
+    times = []
+    for i in range(args.cpu_runs):
+        tc = time.perf_counter()
+        k, _ = oracle.groupby_par(host, oracle_spec(wl), threads=threads)
+        times.append(time.perf_counter() - tc)
+        log(args, f"[bench] CPU oracle run {i}: {times[-1]:.2f}s on {threads} threads, {k.size} rows")
+        del k
+    dt = sorted(times)[len(times) // 2]
+    return {"value": round(wl.n / dt, 1), "unit": "records/s", "cores": threads, "kind": "oracle",
+            "cpu_model": oracle.cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"whole input ({wl.n} records), median of {len(times)} runs "
+                      f"({', '.join(f'{t:.2f}' for t in times)} s); parallel sort-then-scan on {threads} threads"}
+
+
+def bench_query(args, workload, with_cpu):
+    """One query workload: a step is agg_create + agg_consume + agg_finish + agg_destroy over
+    the whole batch, resident in HBM before the timed region."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1311_0059_amd as P
+    from datagen import workloads
+
+    wl = getattr(workloads, WORKLOADS[workload])()
     log(args, f"[bench] generating {wl.name}: {wl.n} records x {wl.record_bytes} B, {wl.d} keys")
     t = time.perf_counter()
     host = wl.generate()
@@ -100,7 +166,7 @@ def main():
     log(args, f"[bench] generated in {time.perf_counter() - t:.1f}s, checksum {datagen.checksum(raw[: 1 << 24])}")
     dev = torch.empty(raw.size, dtype=torch.uint8, device="cuda")
     dev.copy_(torch.from_numpy(raw))
-    if args.workload == "uniform-sorted":
+    if workload == "uniform-sorted":
         # the same records in non-decreasing key order (the paper's sorted dataset), sorted on the
         # device before timing; int64 order of key ^ 2^63 is the unsigned order of the key
         assert wl.record_bytes == 16
@@ -118,7 +184,7 @@ def main():
             sys.exit("bench.py: building the sorted input on the device failed its checks")
         dev = out.view(torch.uint8).view(-1)
         del words, keys, vals, perm, sk, sv
-        host = dev.cpu().numpy().view(workloads.R16) if args.cpu_sample > 0 else host
+        host = dev.cpu().numpy().view(workloads.R16) if with_cpu else host
         wl = workloads.Workload(wl.name + "-sorted", wl.layout, wl.n, wl.d, wl.dist, wl.s, wl.lo, wl.hi, wl.aggs,
                                 wl.budget, wl.seed, "sorted by key")
     workspace = torch.empty(wl.budget, dtype=torch.uint8, device="cuda") if wl.budget else None
@@ -151,35 +217,15 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = 1000.0 * elapsed / args.steps
     value = wl.n * args.steps / elapsed
-    log(args, f"[bench] {args.steps} steps in {elapsed:.3f}s ({ms_per_step:.2f} ms/step)")
+    log(args, f"[bench] {wl.name}: {args.steps} steps in {elapsed:.3f}s ({ms_per_step:.2f} ms/step)")
 
-    # algorithmic bytes (per unit of work: input read once + result rows written once)
+    # algorithmic bytes of the query: input read once + result rows written once
     alg_bytes_step = wl.n * wl.record_bytes + wl.d * W8
-    # dominant kernel: the level-0 aggregation/routing kernel; its algorithmic bytes are the
-    # records it reads plus the grouping states it leaves in the resident tables
-    if agg["engine"] // args.steps == 4:  # sorted runs: the check/count pass and the run reduction
-        kname = "k_run_heads+k_run_reduce"
-        l0_bytes = wl.n * args.steps * wl.record_bytes + agg["resident_groups_l0"] * W8
-        l0_ms = agg["sorted_ms"]
-        launches = args.steps
-    elif agg["update_launches_l0"]:
-        kname = "k_owner_update" if agg["engine"] // args.steps == 3 else f"k_update<0, {1 if agg['preagg'] else 0}>"
-        l0_bytes = agg["update_records_l0"] * wl.record_bytes + agg["resident_groups_l0"] * W8
-        l0_ms = agg["update_ms_l0"]
-        launches = max(1, agg["update_launches_l0"])
-    elif agg["scatter_ms"] > agg["lds_ms"]:
-        # the partition-first LDS engine ran and its scatter took longer than its aggregation:
-        # each scatter launch (one per pass) reads the whole batch; together they write it once
-        kname = "k_part_scatter"
-        launches = max(1, agg["scatter_launches"])
-        l0_bytes = (launches + args.steps) * wl.n * wl.record_bytes
-        l0_ms = agg["scatter_ms"]
-    else:  # the partition-first LDS engine ran: its aggregation kernel reads the partitioned batch
-        kname = "k_lds_agg"
-        l0_bytes = wl.n * args.steps * wl.record_bytes + agg["resident_groups_l0"] * W8
-        l0_ms = agg["lds_ms"]
-        launches = max(1, agg["lds_launches"])
-    achieved = (l0_bytes / launches) / (l0_ms / launches * 1e-3) / 1e9 if l0_ms > 0 else 0.0
+    alg_per_record = alg_bytes_step / wl.n
+    kname, launches, k_ms, k_bytes = dominant_kernel(agg, args.steps, wl.n, alg_per_record)
+    launches = max(1, launches)
+    achieved = (k_bytes / launches) / (k_ms / launches * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    step_gbps = alg_bytes_step / (ms_per_step * 1e-3) / 1e9
     # HBM traffic per launch from the committed rocprofv3 counter summary of this kernel and
     # workload, used only while the kernel sources are the ones it was measured on
     from paper_1311_0059_amd import profiling
@@ -193,24 +239,27 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBPS, 4),
         "traffic": None if traffic is None else int(traffic),
-        "avg_launch_ms": round(l0_ms / launches, 4),
+        "avg_launch_ms": round(k_ms / launches, 4),
         "launches_per_step": launches / args.steps,
-        "bytes_per_launch": int(l0_bytes / launches),
+        "bytes_per_launch": int(k_bytes / launches),
+        "alg_bytes_per_record": round(alg_per_record, 3),
+        "records_per_launch": int(k_bytes / alg_per_record / launches),
+        "step_frac": round(step_gbps / HBM_PEAK_GBPS, 4),
     }
 
-    cpu = None
-    if rank == 0 and args.cpu_sample > 0:
-        import oracle
-        from tests.wl import oracle_spec  # the oracle's own spec format
-        s = min(args.cpu_sample, wl.n)
-        log(args, f"[bench] timing the CPU oracle on {s} records")
-        tc = time.perf_counter()
-        oracle.groupby(host[:s], oracle_spec(wl))
-        dt = time.perf_counter() - tc
-        cpu = {"value": round(s / dt, 1), "unit": "records/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {s} records of the same input, one run, {dt:.1f}s; single-threaded sort-then-scan"}
+    cpu = cpu_oracle_baseline(args, host, wl) if with_cpu else None
+    del host, raw
 
-    out = {
+    n_steps = args.steps
+    per_step = {k: (round(agg[k] / n_steps, 3) if isinstance(agg[k], float) else agg[k] // n_steps)
+                for k in ("levels", "records_spilled", "states_spilled", "bytes_spilled_d2h", "bytes_reloaded_h2d",
+                          "partitions", "partitions_spilled", "resident_groups_l0", "update_ms", "update_ms_l0",
+                          "flush_ms", "lds_ms", "partition_ms", "sorted_ms", "lds_sweeps", "lds_passes",
+                          "scatter_ms", "scatter_records", "lds_hot_keys", "lds_narrow", "onchip_ms",
+                          "onchip_classes", "onchip_workers", "onchip_direct", "engine", "preagg",
+                          "pool_high_water")}
+    per_step["levels"] = agg["levels"] / n_steps
+    return {
         "metric": METRIC,
         "value": round(value, 1),
         "unit": "records/s",
@@ -235,38 +284,13 @@ def main():
             "engine": args.engine,
             "parallelism": "1 GPU",
         },
-        "gbps_algorithmic": round(alg_bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
-        "pct_hbm_peak": round(100.0 * alg_bytes_step / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 2),
+        "gbps_algorithmic": round(step_gbps, 1),
+        "pct_hbm_peak": round(100.0 * step_gbps / HBM_PEAK_GBPS, 2),
         "rows_ok": bool(rows_ok),
-        "per_step": {
-            "levels": agg["levels"] / args.steps,
-            "records_spilled": agg["records_spilled"] // args.steps,
-            "states_spilled": agg["states_spilled"] // args.steps,
-            "bytes_spilled_d2h": agg["bytes_spilled_d2h"] // args.steps,
-            "bytes_reloaded_h2d": agg["bytes_reloaded_h2d"] // args.steps,
-            "partitions": agg["partitions"] // args.steps,
-            "partitions_spilled": agg["partitions_spilled"] // args.steps,
-            "resident_groups_l0": agg["resident_groups_l0"] // args.steps,
-            "update_ms": round(agg["update_ms"] / args.steps, 3),
-            "update_ms_l0": round(agg["update_ms_l0"] / args.steps, 3),
-            "flush_ms": round(agg["flush_ms"] / args.steps, 3),
-            "lds_ms": round(agg["lds_ms"] / args.steps, 3),
-            "partition_ms": round(agg["partition_ms"] / args.steps, 3),
-            "sorted_ms": round(agg["sorted_ms"] / args.steps, 3),
-            "lds_sweeps": agg["lds_sweeps"] // args.steps,
-            "lds_passes": agg["lds_passes"] // args.steps,
-            "scatter_ms": round(agg["scatter_ms"] / args.steps, 3),
-            "lds_hot_keys": agg["lds_hot_keys"] // args.steps,
-            "lds_narrow": agg["lds_narrow"] // args.steps,
-            "engine": agg["engine"] // args.steps,
-            "preagg": agg["preagg"] // args.steps,
-            "pool_high_water": agg["pool_high_water"] // args.steps,
-        },
+        "per_step": per_step,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    if rank == 0:
-        print(json.dumps(out), flush=True)
 
 
 def bench_g_sweep(args):

@@ -79,6 +79,13 @@ def uniform_small() -> Workload:
                     SEED_BASE + 1)
 
 
+def uniform_small_1g() -> Workload:
+    """The 1M-record workload's distribution at 1e9 records (16 GB): 10,000 uniform keys,
+    v in [0, 1000), COUNT+SUM+MIN+MAX, unlimited budget -- its bandwidth regime."""
+    return Workload("uniform-1G-10k", "R16", 1_000_000_000, 10_000, UNIFORM, 0.0, 0, 999, AGGS_R16_ALL, 0,
+                    SEED_BASE + 1)
+
+
 def uniform_spill() -> Workload:
     """200M R16 records, 20M uniform keys, v in [-1e6, 1e6], all four aggregates, 1 GiB budget."""
     return Workload("uniform-200M-20M-1GiB", "R16", 200_000_000, 20_000_000, UNIFORM, 0.0, -1_000_000, 1_000_000,

@@ -92,10 +92,17 @@ typedef enum agg_engine {
   AGG_ENGINE_OWNER = 3,   /* the same HBM tables, updated without atomics: sub-chunks of the batch are
                              radix-partitioned into a buffer carved from the budget, and one workgroup owns
                              each partition's table while it folds that partition's records in */
-  AGG_ENGINE_SORTED = 4   /* for a first batch whose keys are in non-decreasing order: every run of equal
+  AGG_ENGINE_SORTED = 4,  /* for a first batch whose keys are in non-decreasing order: every run of equal
                              keys becomes one row, no tables (verified in full; a batch that is not sorted
                              takes the engine AUTO would choose).  AUTO tries it when an evenly spaced
                              sample of the batch is sorted.  Needs at most 7 aggregates */
+  AGG_ENGINE_ONCHIP = 5   /* for a first batch whose groups (est_groups, else the record count) fit at most
+                             8 LDS tables: one pass with no partitioning.  The keys are split into classes;
+                             each class's records are aggregated in LDS by workgroups of their own that
+                             read the same tiles of the batch, and fold their groups into the level-0 HBM
+                             tables at the end (early aggregation, Sec. 4.2).  When the batch has more
+                             groups than those tables hold, it is run again on the engine AUTO would choose
+                             next.  AUTO tries it first (after the sorted-run check) */
 } agg_engine;
 
 #define AGG_MAX_AGGS 8
@@ -153,7 +160,7 @@ typedef struct agg_stats {
   uint32_t guard_trips;         /* levels whose spilled output kept more than 80% of their input */
   uint32_t preagg;              /* 1 if the workgroup hot-key cache was used (skew seen in a sample) */
   uint32_t engine;              /* engine used for the first batch: 1 HBM tables, 2 LDS, 3 owner-computed,
-                                   4 sorted runs */
+                                   4 sorted runs, 5 on-chip */
   uint64_t pool_high_water;     /* peak bytes of the working budget in use */
   uint64_t pool_bytes;          /* size of the working budget actually reserved */
   /* Device time of the two main kernels, measured with HIP events recorded on
@@ -181,6 +188,20 @@ typedef struct agg_stats {
                                    records are folded while the batch is counted; one row each) */
   uint32_t lds_narrow;          /* LDS engine: 1 when its tables kept COUNT and MIN/MAX of 32-bit fields in
                                    4-byte columns (chosen when that saves sweeps or partitions) */
+  uint64_t scatter_records;     /* LDS engine: records its scatter launches wrote into partitions (every
+                                   record once, over all passes, less those of frequent keys) */
+  uint32_t onchip_classes;      /* on-chip engine: key classes (LDS tables per group of workgroups) */
+  uint32_t onchip_workers;      /* on-chip engine: workgroups per class */
+  double onchip_ms;             /* on-chip engine: device time of its kernel (HIP events) */
+  uint32_t onchip_fallbacks;    /* on-chip engine: batches run again elsewhere (more groups than planned) */
+  uint32_t reserved_stats;
+  uint64_t onchip_direct;       /* on-chip engine: records whose key found no room in its class's LDS table
+                                   (folded straight into the HBM tables) */
+  uint64_t records_spilled_l0;  /* raw records spilled at level 0 (the spilled part of the input, the I/O
+                                   term R - (K / G_t) R of Secs. 5.3.1 and 5.3.4) */
+  uint64_t first_full_record;   /* HBM tables: input index of the first record whose partition's table was
+                                   full, i.e. records consumed before the first overflow (the Appendix's
+                                   I_raw); UINT64_MAX when no table filled */
 } agg_stats;
 
 /* Start one GROUP BY query (Sec. 3.1) under the memory budget M of Sec. 3.2

@@ -63,7 +63,7 @@ def make_spec(record_bytes: int, keys, aggs, budget: int = 0, est_groups: int = 
     s.load_pct = load_pct
     s.policy = N.POLICIES[policy]
     s.preagg = {"auto": 0, "on": 1, "off": 2}[preagg]
-    s.engine = {"auto": 0, "tables": 1, "lds": 2, "owner": 3, "sorted": 4}[engine]
+    s.engine = {"auto": 0, "tables": 1, "lds": 2, "owner": 3, "sorted": 4, "onchip": 5}[engine]
     return s
 
 

@@ -84,6 +84,15 @@ class Stats(ctypes.Structure):
         ("scatter_ms", ctypes.c_double),
         ("lds_hot_keys", ctypes.c_uint32),
         ("lds_narrow", ctypes.c_uint32),
+        ("scatter_records", ctypes.c_uint64),
+        ("onchip_classes", ctypes.c_uint32),
+        ("onchip_workers", ctypes.c_uint32),
+        ("onchip_ms", ctypes.c_double),
+        ("onchip_fallbacks", ctypes.c_uint32),
+        ("reserved_stats", ctypes.c_uint32),
+        ("onchip_direct", ctypes.c_uint64),
+        ("records_spilled_l0", ctypes.c_uint64),
+        ("first_full_record", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:

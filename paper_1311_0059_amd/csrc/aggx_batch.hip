@@ -307,11 +307,17 @@ __global__ void k_batch_reset(BParams P) {
 
 // Part of the device setup: the persistent kernel may take `lds_bytes` of LDS,
 // and *per_cu of its blocks fit a compute unit at that size.
-hipError_t batch_kernel_setup(uint32_t lds_bytes, int *per_cu) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds_bytes);
+hipError_t batch_kernel_setup(uint32_t total_bytes, uint32_t *lds_bytes, int *per_cu) {
+  // the dynamic part: what the workgroup may take in all, less the kernel's static LDS
+  hipFuncAttributes fa{};
+  hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_batch));
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch, 1024, lds_bytes);
+  if (fa.sharedSizeBytes >= total_bytes) return hipErrorInvalidValue;
+  *lds_bytes = (total_bytes - (uint32_t)fa.sharedSizeBytes) & ~15u;
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)*lds_bytes);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch, 1024, *lds_bytes);
 }
 
 hipError_t launch_batch(hipStream_t s, const BParams &P, uint32_t blocks, uint32_t block, uint32_t lds_bytes) {

@@ -234,8 +234,8 @@ agg_status agg_batch_create(const agg_spec *spec, const agg_instance *inst, uint
   if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) return bail(AGG_E_DEVICE);
   // LDS: the aggregation table, and at least the 48 KB the count/scatter items use
   const DeviceSetup *ds = device_setup();
-  if (!ds) return bail(AGG_E_DEVICE);
-  b->lds_bytes = ds->lds_max;
+  if (!ds || ds->batch_lds_max < 48 * 1024) return bail(AGG_E_DEVICE);
+  b->lds_bytes = ds->batch_lds_max;
   b->nslots = (b->lds_bytes / b->W8) & ~3u;  // whole groups of four slots
   b->cap = (uint32_t)(b->nslots * kLoad);
   b->blocks = (uint32_t)(ds->batch_per_cu * ds->cus);

@@ -77,6 +77,7 @@ struct KLevel {
   uint32_t fan_mask;
   uint32_t slot_shift;   // level 0: slot hash = h0 << slot_shift; deeper levels use seed_slot
   uint64_t seed_slot;
+  uint64_t rec_base = ~0ULL;  // level 0, raw records: input index of the launch's first record (else ~0)
 };
 
 // Per-partition table descriptor.  A partition is either resident (a table of
@@ -106,6 +107,9 @@ struct Ctrl {
   unsigned long long side[2][kMaxAggs];  // their side groups' aggregates
   unsigned long long sample_hot_n;        // keys seen at least kHotMin times in the sample (at most kMaxHot)
   unsigned long long sample_hot[kMaxHot];  // those keys (never a reserved value)
+  unsigned long long onchip_lost;  // on-chip engine: records / states that found no room in the HBM tables
+  unsigned long long onchip_direct;  // on-chip engine: records of keys its LDS tables had no room for
+  unsigned long long first_full;   // lowest input index of a level-0 record that found its table full (~0: none)
 };
 
 // Frequent keys taken out of the LDS engine's partitioning: they are folded
@@ -240,22 +244,38 @@ hipError_t launch_run_scan(hipStream_t s, const uint32_t *tile_heads, uint64_t t
 hipError_t launch_rows_init(hipStream_t s, const KSpec &ks, const OutCols &cols, uint64_t n);
 hipError_t launch_run_reduce(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, const uint32_t *tile_heads,
                              const unsigned long long *tile_base, Ctrl *ctrl, uint64_t *out_keys, const OutCols &cols);
+// On-chip engine (single pass for batches whose groups fit LDS tables): C key
+// classes x `workers` workgroups, each with an LDS table of nslots slots
+// holding at most cap groups (narrow: 4-byte COUNT and 32-bit MIN/MAX columns).
+struct OnchipPlan {
+  uint32_t C = 0, workers = 0, xcd_map = 0, nslots = 0, cap = 0, lds_bytes = 0;
+  bool narrow = false;
+};
+hipError_t launch_onchip(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, const KLevel &lv,
+                         const PartMeta *meta, uint32_t *cnt, uint64_t *arena, Ctrl *ctrl, const OnchipPlan &op);
+hipError_t onchip_setup(uint32_t total_bytes, uint32_t *lds_bytes);
+// records a workgroup of the on-chip kernel reads per tile, for na aggregates
+uint64_t onchip_tile_records(uint32_t na);
 // Launch configuration of the current device, established once per device
 // (under a lock, before its first use) and read-only afterwards: kernel
 // attributes are set and occupancy is queried only here, never from the
 // launch paths that concurrent host threads run.
 struct DeviceSetup {
-  uint32_t lds_max;            // dynamic LDS bytes the LDS-sized kernels may be launched with
+  uint32_t lds_max;            // dynamic LDS bytes the LDS aggregation kernels may be launched with
+  uint32_t count_lds_max;      // the same for the partition count kernel (it also has static LDS)
+  uint32_t scatter_lds_max;    // and for the partition scatter kernel
   int cus;                     // compute units
   int update_per_cu[2][2][4];  // k_update<kind, preagg> blocks per CU without dynamic LDS, block = 64 (i + 1)
-  int batch_per_cu;            // k_batch blocks per CU at lds_max
+  uint32_t onchip_lds_max;     // dynamic LDS bytes of the on-chip engine's kernel (0: not available)
+  uint32_t batch_lds_max;      // dynamic LDS bytes of the batched-mode kernel
+  int batch_per_cu;            // its blocks per CU at batch_lds_max
 };
 const DeviceSetup *device_setup();
 // Largest dynamic LDS the LDS-aggregation kernel can be launched with (bytes).
 uint32_t lds_agg_max_bytes();
 // Per-kernel parts of the setup (called by device_setup only).
 hipError_t update_occupancy(int kind, int preagg, uint32_t block, int *per_cu);
-hipError_t batch_kernel_setup(uint32_t lds_bytes, int *per_cu);
+hipError_t batch_kernel_setup(uint32_t total_bytes, uint32_t *lds_bytes, int *per_cu);
 hipError_t launch_batch(hipStream_t s, const BParams &P, uint32_t blocks, uint32_t block, uint32_t lds_bytes);
 uint64_t hll_seed();
 }  // namespace aggx

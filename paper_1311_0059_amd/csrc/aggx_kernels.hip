@@ -134,6 +134,10 @@ __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, 
               to_spill = true;
               __hip_atomic_store(ovf + p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               __hip_atomic_store(&ctrl->any_ovf, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              // records consumed before a table was first full (Appendix, I_raw)
+              if (KIND == 0 && lv.rec_base != ~0ULL)
+                __hip_atomic_fetch_min(&ctrl->first_full, (unsigned long long)(lv.rec_base + t0 + tid),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
           }
         }
@@ -266,6 +270,9 @@ __global__ void k_ctrl_init(Ctrl *c, KSpec ks) {
     c->state_ctr = 0;
     c->rows = 0;
     c->any_ovf = 0;
+    c->onchip_lost = 0;
+    c->onchip_direct = 0;
+    c->first_full = ~0ULL;
     for (int g = 0; g < 2; ++g) {
       c->side_n[g] = 0;
       for (int a = 0; a < kMaxAggs; ++a) c->side[g][a] = a < (int)ks.na ? identity_of(ks.agg[a]) : 0;

@@ -10,6 +10,7 @@
 // spills the records of its new keys raw, exactly like a full table of the
 // HBM-table kernels, and those records are re-aggregated at the next level.
 #include "aggx_device.h"
+#include "aggx_ldstab.h"
 
 #include <algorithm>
 #include <map>
@@ -279,54 +280,6 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
 // their rows before the next sweep.  Each sweep re-reads the partition; that
 // costs less than a second partition pass over the whole batch.  The table's
 // slot index uses the hash bits below both digits (slot_shift).
-// The table's aggregate columns follow its nslots keys, column a taking 4 bytes
-// a slot where kNarrow and lds_narrow allow, else 8; f(a, descriptor, narrow,
-// column) runs for each.  (Tables without narrow columns are compiled apart, as
-// plain 8-byte column arrays: the per-column width test costs them some speed.)
-template <bool kNarrow, typename Fn>
-__device__ __forceinline__ void for_lds_cols(const KSpec &ks, uint8_t *cols, uint32_t nslots, Fn f) {
-  uint32_t off = 0;  // LDS byte offsets fit 32 bits
-#pragma unroll
-  for (int a = 0; a < kMaxAggs; ++a) {
-    if (a >= (int)ks.na) break;
-    const uint32_t d = ks.agg[a];
-    const bool nw = kNarrow && lds_narrow(d);
-    f(a, d, nw, cols + off);
-    off += (nw ? 4u : 8u) * nslots;
-  }
-}
-
-// Identity of a 4-byte column (COUNT, or MIN/MAX of a 32-bit field).
-__device__ __forceinline__ uint32_t narrow_identity(uint32_t d) {
-  const bool sg = type_signed(desc_type(d));
-  switch (desc_op(d)) {
-    case OP_MIN: return sg ? 0x7fffffffu : 0xffffffffu;
-    case OP_MAX: return sg ? 0x80000000u : 0u;
-    default: return 0u;
-  }
-}
-
-// Fold one record's values into slot `e` of the table's columns.
-template <bool kNarrow>
-__device__ __forceinline__ void fold_lds_cols(uint8_t *cols, uint32_t nslots, uint32_t e, const KSpec &ks,
-                                              const uint64_t *vals) {
-  for_lds_cols<kNarrow>(ks, cols, nslots, [&](int a, uint32_t d, bool nw, uint8_t *c) {
-    const bool sg = type_signed(desc_type(d));
-    const uint64_t v = vals[a];
-    if (nw) {
-      uint32_t *w = reinterpret_cast<uint32_t *>(c) + e;
-      if (desc_op(d) <= OP_SUM) atomicAdd(w, (uint32_t)v);
-      else if (desc_op(d) == OP_MIN) sg ? (void)atomicMin(reinterpret_cast<int *>(w), (int)(uint32_t)v) : (void)atomicMin(w, (uint32_t)v);
-      else sg ? (void)atomicMax(reinterpret_cast<int *>(w), (int)(uint32_t)v) : (void)atomicMax(w, (uint32_t)v);
-    } else {
-      unsigned long long *w = reinterpret_cast<unsigned long long *>(c) + e;
-      if (desc_op(d) <= OP_SUM) atomicAdd(w, (unsigned long long)v);
-      else if (desc_op(d) == OP_MIN) sg ? (void)atomicMin(reinterpret_cast<long long *>(w), (long long)v) : (void)atomicMin(w, (unsigned long long)v);
-      else sg ? (void)atomicMax(reinterpret_cast<long long *>(w), (long long)v) : (void)atomicMax(w, (unsigned long long)v);
-    }
-  });
-}
-
 // One sweep of k_lds_agg over the partition's records [lo, hi).
 template <bool kNarrow>
 __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, uint64_t hi, const KSpec &ks,
@@ -377,35 +330,9 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
         fold_global(reinterpret_cast<uint64_t *>(ctrl->side[sg]), ks, vals[u]);
         __hip_atomic_fetch_add(&ctrl->side_n[sg], 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else if (mine) {
-        // linear probing over groups of four slots, whose keys come in two 16-byte reads;
-        // the fold comes after the loop, once per wave, whatever slot each lane ended on
-        const uint32_t ng = nslots / 4;
-        uint32_t g = (uint32_t)mulhi64(h0 << slot_shift, ng);
-        uint32_t slot = ~0u;
-        bool stop = false;
-        for (uint32_t t = 0; t < ng && !stop; ++t) {
-          const ulonglong2 *gk = reinterpret_cast<const ulonglong2 *>(t_key + 4 * g);
-          const ulonglong2 k01 = gk[0], k23 = gk[1];
-          const unsigned long long kv[4] = {k01.x, k01.y, k23.x, k23.y};
-#pragma unroll
-          for (uint32_t j = 0; j < 4; ++j) {
-            if (stop) break;
-            const uint32_t idx = 4 * g + j;
-            unsigned long long sk = kv[j];
-            if (sk == kEmpty) {
-              const bool full = *s_groups >= cap;
-              const unsigned long long desired = full ? kClosed : key;
-              sk = atomicCAS(reinterpret_cast<unsigned long long *>(t_key + idx), (unsigned long long)kEmpty, desired);
-              if (sk == kEmpty) {
-                if (!full) atomicAdd(s_groups, 1u);
-                sk = desired;
-              }
-            }
-            if (sk == key) slot = idx;
-            stop = sk == key || sk == kClosed;
-          }
-          g = g + 1 == ng ? 0 : g + 1;
-        }
+        // linear probing over groups of four slots; the fold comes after the probe loop,
+        // once per wave, whatever slot each lane ended on
+        const uint32_t slot = lds_find_or_insert(t_key, nslots, cap, s_groups, key, h0 << slot_shift);
         if (slot != ~0u) {
           if constexpr (kNarrow) fold_lds_cols<kNarrow>(t_cols, nslots, slot, ks, vals[u]);
           else fold_lds(t_acc + slot, nslots, ks, vals[u]);
@@ -510,11 +437,11 @@ __global__ void __launch_bounds__(256) k_merge_rows(const uint64_t *__restrict__
   }
 }
 
-// The count and scatter kernels' LDS grows with the fan-out (4 and 8 bytes per
-// partition); the device setup allowed them the most a workgroup can take.
-static bool kernel_lds_allowed(size_t lds) {
+// The count and scatter kernels' dynamic LDS grows with the fan-out (4 and 8
+// bytes per partition); the device setup allowed each the most it can take.
+static bool kernel_lds_allowed(size_t lds, bool scatter) {
   const DeviceSetup *ds = device_setup();
-  return ds && lds <= ds->lds_max;
+  return ds && lds <= (scatter ? ds->scatter_lds_max : ds->count_lds_max);
 }
 
 hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t shift,
@@ -525,8 +452,8 @@ hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const
   const uint64_t blocks = (n + chunk - 1) / chunk;
   // (its frequent-key arrays take another ~17 KB of static LDS)
   constexpr size_t kStatic = 12ull * kHotSlots + 4ull * kMaxHot + 8ull * kMaxAggs * kMaxHot;
-  if (!kernel_lds_allowed(4ull * (mask + 1) + kStatic))
-    return hipErrorInvalidValue;
+  static_assert(kStatic < 64 * 1024, "the count kernel's static LDS");
+  if (!kernel_lds_allowed(4ull * (mask + 1), false)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_part_count, dim3((uint32_t)blocks), dim3(kPartBlock), 4ull * (mask + 1), s, in, n, ks, shift,
                      mask, chunk, totals, block_counts, hot);
   return hipGetLastError();
@@ -548,7 +475,7 @@ hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, con
   const uint64_t blocks = (n + chunk - 1) / chunk;
   if (n >= (1ull << 32)) return hipErrorInvalidValue;  // the LDS bases are 32-bit record indices
   const size_t lds = 8ull * d_n + 12ull * kHotSlots;
-  if (!kernel_lds_allowed(lds)) return hipErrorInvalidValue;
+  if (!kernel_lds_allowed(lds, true)) return hipErrorInvalidValue;
   const uintptr_t a = reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(in);
   const uint32_t vec = ks.rb % 16 == 0 && a % 16 == 0 ? 16 : ks.rb % 8 == 0 && a % 8 == 0 ? 8 : 4;
   hipLaunchKernelGGL(k_part_scatter, dim3((uint32_t)blocks), dim3(kPartBlock), lds, s, in, n, ks, shift, mask, d_lo,
@@ -602,14 +529,27 @@ const DeviceSetup *device_setup() {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return nullptr;
   ds.cus = prop.multiProcessorCount;
+  // Each kernel may take `want` bytes of LDS in all: its static LDS plus the
+  // dynamic part allowed here (64 KB in all when the attribute cannot be set).
   const uint32_t want = 160 * 1024 - 1024;
-  ds.lds_max = 64 * 1024;
-  const void *fns[] = {reinterpret_cast<const void *>(k_part_count), reinterpret_cast<const void *>(k_part_scatter),
-                       reinterpret_cast<const void *>(k_lds_agg<false>), reinterpret_cast<const void *>(k_lds_agg<true>)};
-  bool all = true;
-  for (const void *fn : fns) all &= hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) == hipSuccess;
+  auto allow = [&](const void *fn, uint32_t *dyn_max) {
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, fn) != hipSuccess || fa.sharedSizeBytes >= 64 * 1024) {
+      *dyn_max = 0;
+      return;
+    }
+    const uint32_t st = (uint32_t)fa.sharedSizeBytes;
+    *dyn_max = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(want - st)) == hipSuccess
+                   ? want - st
+                   : 64 * 1024 - st;
+  };
+  uint32_t narrow_max = 0;
+  allow(reinterpret_cast<const void *>(k_part_count), &ds.count_lds_max);
+  allow(reinterpret_cast<const void *>(k_part_scatter), &ds.scatter_lds_max);
+  allow(reinterpret_cast<const void *>(k_lds_agg<false>), &ds.lds_max);
+  allow(reinterpret_cast<const void *>(k_lds_agg<true>), &narrow_max);
+  ds.lds_max = std::min(ds.lds_max, narrow_max);
   (void)hipGetLastError();
-  if (all) ds.lds_max = want;
   for (int kind = 0; kind < 2; ++kind)
     for (int pre = 0; pre < 2; ++pre)
       for (int i = 0; i < 4; ++i) {
@@ -617,7 +557,12 @@ const DeviceSetup *device_setup() {
         if (update_occupancy(kind, pre, 64u * (i + 1), &per) != hipSuccess || per < 1) per = 1;
         ds.update_per_cu[kind][pre][i] = per;
       }
-  if (batch_kernel_setup(ds.lds_max, &ds.batch_per_cu) != hipSuccess || ds.batch_per_cu < 1) ds.batch_per_cu = 1;
+  if (onchip_setup(want, &ds.onchip_lds_max) != hipSuccess) ds.onchip_lds_max = 0;
+  if (batch_kernel_setup(want, &ds.batch_lds_max, &ds.batch_per_cu) != hipSuccess || ds.batch_per_cu < 1) {
+    // 64 KB in all when more cannot be had
+    if (batch_kernel_setup(64 * 1024, &ds.batch_lds_max, &ds.batch_per_cu) != hipSuccess) ds.batch_lds_max = 0;
+    if (ds.batch_per_cu < 1) ds.batch_per_cu = 1;
+  }
   (void)hipGetLastError();
   table[dev] = ds;
   ready[dev] = true;

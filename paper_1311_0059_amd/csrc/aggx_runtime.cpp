@@ -241,6 +241,8 @@ struct agg_handle {
   int hot_key = 0;  // the sample showed one key with a large share of the records
   uint32_t hot_n = 0;  // then: the frequent keys the LDS engine takes out of its partitions
   int sample_sorted = 0;  // the sampled keys were in non-decreasing order
+  uint32_t sample_n = 0;     // keys the sampler read from the first batch
+  uint64_t sample_dups = 0;  // of them, repeats of a key read before
   int state = H_OPEN;
   bool l0_done = false;  // level 0 flushed (agg_first_rows or agg_finish); no more batches
   double l0_G = 0.0;     // estimated distinct keys of what level 0 spilled
@@ -292,7 +294,7 @@ agg_status validate(const agg_spec *s) {
   if (wide && s->record_bytes % 8) return AGG_E_INVALID;
   if (s->fanout_bits > (uint32_t)kMaxFanBits) return AGG_E_INVALID;
   if (s->load_pct != 0 && (s->load_pct < 10 || s->load_pct > 95)) return AGG_E_INVALID;
-  if (s->policy > AGG_POLICY_PREPART || s->preagg > 2 || s->engine > AGG_ENGINE_SORTED) return AGG_E_INVALID;
+  if (s->policy > AGG_POLICY_PREPART || s->preagg > 2 || s->engine > AGG_ENGINE_ONCHIP) return AGG_E_INVALID;
   if (s->device_workspace && (s->workspace_bytes < s->budget_bytes || ((uintptr_t)s->device_workspace & 255)))
     return AGG_E_BUDGET;
   if (s->device_workspace && s->budget_bytes == 0) return AGG_E_INVALID;
@@ -578,6 +580,8 @@ agg_status run_stream(agg_handle *h, const uint8_t *in, uint64_t n, int kind) {
     if (!h->next.reserve(c * in_bytes, &dst)) return AGG_E_NOMEM;
     HCK(h, launch_u64_set(h->stream, kind == 0 ? &h->d_ctrl->raw_ctr : &h->d_ctrl->state_ctr, 1, 0));
     KSpill sp = spill_target(h, kind == 0 ? dst : nullptr, kind == 0 ? nullptr : dst);
+    // level-0 raw records come from agg_consume, whose batch follows the records counted before it
+    lv.rec_base = h->plan.level == 0 && kind == 0 ? h->st.records_in - n + off : ~0ULL;
     const bool preagg = h->preagg > 0 && h->plan.arena_slots < (1ull << 32);
     if (preagg) h->st.preagg = 1;
     HCK(h, hipEventRecord(h->ev0, h->stream));
@@ -598,6 +602,10 @@ agg_status run_stream(agg_handle *h, const uint8_t *in, uint64_t n, int kind) {
     }
     const uint64_t got = kind == 0 ? h->h_ctrl->raw_ctr : h->h_ctrl->state_ctr;
     h->next.commit(dst, got, in_bytes, kind == 1);
+    if (h->plan.level == 0 && kind == 0) {
+      h->st.records_spilled_l0 += got;
+      h->st.first_full_record = std::min<uint64_t>(h->st.first_full_record, h->h_ctrl->first_full);
+    }
     if (kind == 0)
       h->st.records_spilled += got;
     else
@@ -874,8 +882,13 @@ agg_status lds_run_partitions(agg_handle *h, const uint8_t *in, uint64_t n, cons
                         lp.lds_bytes, h->d_ctrl, spill_target(h, dst, nullptr), h->r_keys + h->r_rows, oc,
                         h->r_cap - h->r_rows));
   HCK(h, hipEventRecord(h->ev1, h->stream));
+  // records this pass's scatter wrote: the run's total from the offsets scan
+  HCK(h, hipMemcpyAsync(h->h_scratch, offsets + d_n, 8, hipMemcpyDeviceToHost, h->stream));
   s = read_ctrl(h);
   if (s) return s;
+  uint64_t scattered = 0;
+  memcpy(&scattered, h->h_scratch, 8);
+  h->st.scatter_records += scattered;
   float ms = 0.f;
   HCK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
   h->st.lds_launches += 1;
@@ -885,6 +898,7 @@ agg_status lds_run_partitions(agg_handle *h, const uint8_t *in, uint64_t n, cons
   h->st.scatter_ms += ms;
   h->next.commit(dst, h->h_ctrl->raw_ctr, h->ks.rb, false);
   h->st.records_spilled += h->h_ctrl->raw_ctr;
+  h->st.records_spilled_l0 += h->h_ctrl->raw_ctr;
   h->st.bytes_spilled_d2h += h->h_ctrl->raw_ctr * h->ks.rb;
   if (h->h_ctrl->rows > h->r_cap - h->r_rows) return AGG_E_INTERNAL;
   h->r_rows += h->h_ctrl->rows;
@@ -958,6 +972,148 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   h->st.lds_passes = (uint32_t)runs.size();
   h->used_bits = std::max(h->used_bits, lp.b + lp.sbits);
   return AGG_OK;
+}
+
+// ---- on-chip engine ---------------------------------------------------------
+// Groups of a batch of uniform keys from a sample: ns keys drawn from G groups
+// repeat an expected ns - G (1 - exp(-ns / G)) of them; solved for G by
+// bisection (infinity when nothing repeated).
+double sample_groups(uint32_t ns, uint64_t dups) {
+  if (dups == 0) return HUGE_VAL;
+  if (dups >= ns) return 1.0;
+  auto rep = [&](double G) { return ns - G * (1.0 - std::exp(-(double)ns / G)); };
+  double lo = 1.0, hi = 1e15;  // rep() falls as G grows
+  for (int it = 0; it < 200 && hi / lo > 1.0 + 1e-9; ++it) {
+    const double mid = std::sqrt(lo * hi);
+    if (rep(mid) > (double)dups) lo = mid;
+    else hi = mid;
+  }
+  return std::sqrt(lo * hi);
+}
+
+
+// A first batch whose groups fit a few LDS tables is aggregated in one pass
+// (no partition pass): C key classes, each aggregated by its own workgroups in
+// LDS, folded into the level-0 HBM tables at the end (aggx_onchip.hip).
+constexpr uint32_t kOnchipMaxClasses = 8;     // each tile is read from L2 once per class
+constexpr double kOnchipLoad = 0.8;           // LDS table load
+constexpr uint64_t kOnchipRecordsPerGroup = 16;  // records per worker and group before another worker pays
+
+bool onchip_plan(const KSpec &ks, uint64_t n, double G, OnchipPlan *op) {
+  const DeviceSetup *ds = device_setup();
+  if (!ds || ds->onchip_lds_max == 0 || n == 0) return false;
+  *op = OnchipPlan();
+  op->lds_bytes = ds->onchip_lds_max;
+  const uint64_t T = onchip_tile_records(ks.na);
+  const uint64_t tiles = (n + T - 1) / T;
+  // narrow columns when they hold more groups; the records a workgroup reads stay below 2^32
+  const uint32_t wide = lds_slot_bytes(ks, false), thin = lds_slot_bytes(ks, true);
+  auto fit = [&](uint32_t slot_bytes, uint32_t *nslots, uint32_t *cap, uint32_t *C) {
+    *nslots = (op->lds_bytes / slot_bytes) & ~3u;
+    *cap = (uint32_t)std::min<double>(*nslots - 1, std::floor(*nslots * kOnchipLoad));
+    for (uint32_t c = 1; c <= kOnchipMaxClasses; ++c) {
+      const double g = G / c;
+      if (g + 4.0 * std::sqrt(g) + 16.0 <= *cap) {
+        *C = c;
+        return true;
+      }
+    }
+    return false;
+  };
+  uint32_t nslots = 0, cap = 0, C = 0;
+  bool narrow = false;
+  if (thin < wide && fit(thin, &nslots, &cap, &C)) {
+    narrow = true;
+    uint32_t n2, c2, C2;
+    if (fit(wide, &n2, &c2, &C2) && C2 == C) {  // no class saved: 8-byte columns
+      narrow = false;
+      nslots = n2;
+      cap = c2;
+    }
+  } else if (!fit(wide, &nslots, &cap, &C)) {
+    return false;
+  }
+  // workers per class: each reads at least kOnchipRecordsPerGroup records per group, and
+  // every workgroup of the launch is resident at once (one per compute unit: the table
+  // takes the LDS)
+  const uint64_t max_w = std::max<uint64_t>(1, (uint64_t)ds->cus / C);
+  uint64_t w = (uint64_t)std::ceil((double)n / (kOnchipRecordsPerGroup * std::max(1.0, G)));
+  w = std::max<uint64_t>(1, std::min<uint64_t>({w, max_w, tiles}));
+  op->xcd_map = 0;
+  if (w >= 8) {
+    w = w / 8 * 8;
+    op->xcd_map = 1;
+  }
+  if (narrow && ((tiles + w - 1) / w) * T >= (1ull << 32)) {
+    narrow = false;  // a 4-byte COUNT could not count one workgroup's records
+    if (!fit(wide, &nslots, &cap, &C)) return false;
+    w = std::min<uint64_t>(w, std::max<uint64_t>(1, (uint64_t)ds->cus / C));
+    if (op->xcd_map) w = std::max<uint64_t>(8, w / 8 * 8);
+    if (w * C > (uint64_t)ds->cus) return false;
+  }
+  op->C = C;
+  op->workers = (uint32_t)w;
+  op->nslots = nslots;
+  op->cap = cap;
+  op->narrow = narrow;
+  return true;
+}
+
+// *applied is false when the engine does not apply, or when the batch had more
+// groups than the plan's tables held: the tables and side groups are then reset
+// and the batch goes to the other engines.
+agg_status run_onchip(agg_handle *h, const uint8_t *in, uint64_t n, bool *applied) {
+  *applied = false;
+  double G = std::min<double>((double)n, h->spec.est_groups ? (double)h->spec.est_groups : (double)n);
+  if (h->spec.engine == AGG_ENGINE_AUTO && h->sample_n >= 256) {
+    // the sampler's repeated keys tell how many groups the batch holds (uniform keys):
+    // without an estimate they give one; an estimate far below them is not trusted
+    const double Gs = sample_groups(h->sample_n, h->sample_dups);
+    if (!h->spec.est_groups) G = std::min(G, 1.25 * Gs);
+    else if (Gs > 4.0 * G) return AGG_OK;
+  }
+  OnchipPlan op;
+  if (!onchip_plan(h->ks, n, G, &op)) return AGG_OK;
+  h->plan_hint_n = n;
+  agg_status s = make_plan(h, 0, G, 0);
+  if (s) return s;
+  if (h->plan.planned_spilled) {  // every partition's table must be resident
+    h->planned = false;
+    return AGG_OK;
+  }
+  s = start_level(h);
+  if (s) return s;
+  KLevel lv;
+  lv.level = 0;
+  lv.digit_shift = h->plan.digit_shift;
+  lv.fan_mask = h->plan.F - 1;
+  lv.slot_shift = h->plan.fan_bits;
+  lv.seed_slot = h->plan.seed_slot;
+  HCK(h, hipEventRecord(h->ev0, h->stream));
+  HCK(h, launch_onchip(h->stream, in, n, h->ks, lv, h->d_meta, h->d_cnt, h->d_arena, h->d_ctrl, op));
+  HCK(h, hipEventRecord(h->ev1, h->stream));
+  s = read_ctrl(h);
+  if (s) return s;
+  float ms = 0.f;
+  HCK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  h->st.onchip_ms += ms;
+  if (h->h_ctrl->onchip_lost) {
+    // more groups than planned: start over on another engine
+    h->st.onchip_fallbacks += 1;
+    HCK(h, launch_ctrl_init(h->stream, h->d_ctrl, h->ks));
+    HCK(h, hipStreamSynchronize(h->stream));
+    h->planned = false;
+    return AGG_OK;
+  }
+  *applied = true;
+  h->used_bits = std::max(h->used_bits, h->plan.fan_bits);
+  h->st.partitions = h->plan.F;
+  h->st.partitions_spilled = 0;
+  h->st.onchip_direct = h->h_ctrl->onchip_direct;
+  h->st.onchip_classes = op.C;
+  h->st.onchip_workers = op.workers;
+  h->st.lds_narrow = op.narrow ? 1u : 0u;
+  return handle_overflow(h);
 }
 
 // ---- sorted runs ------------------------------------------------------------
@@ -1088,6 +1244,7 @@ agg_status run_owner_stream(agg_handle *h, const uint8_t *in, uint64_t n) {
     const uint64_t got = h->h_ctrl->raw_ctr;
     h->next.commit(dst, got, rb, false);
     h->st.records_spilled += got;
+    h->st.records_spilled_l0 += got;
     h->st.bytes_spilled_d2h += got * rb;
     s = handle_overflow(h);
     if (s) return s;
@@ -1316,6 +1473,7 @@ agg_status finish_impl(agg_handle *h) {
 
 }  // namespace
 
+
 extern "C" {
 
 const char *agg_strerror(agg_status s) {
@@ -1385,6 +1543,7 @@ agg_status agg_create(const agg_spec *spec, agg_handle **out) {
   }
   carve(h);
   h->st.pool_bytes = h->pool_bytes;
+  h->st.first_full_record = ~0ULL;
   if (launch_ctrl_init(h->stream, h->d_ctrl, h->ks) != hipSuccess ||
       launch_u32_fill(h->stream, h->d_hll, kHllRegs, 0) != hipSuccess) {
     agg_destroy(h);
@@ -1415,6 +1574,8 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     if (s) return s;
     // repeated keys in more than 5% of the sample: pre-aggregate; one key in more
     // than 2% of it: a hot key that would unbalance a partition-per-workgroup pass
+    h->sample_n = ns;
+    h->sample_dups = h->h_ctrl->sample_dups;
     if (h->preagg < 0) h->preagg = ns >= 256 && h->h_ctrl->sample_dups * 20 > ns ? 1 : 0;
     h->hot_key = ns >= 256 && h->h_ctrl->sample_max * 50 > ns;
     h->hot_n = h->hot_key ? (uint32_t)h->h_ctrl->sample_hot_n : 0;
@@ -1426,6 +1587,17 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     bool applied = false;
     agg_status s = run_sorted(h, (const uint8_t *)d_records, n, &applied);
     if (s || applied) return s;
+  }
+  if (h->engine == 0 && !h->planned &&
+      (h->spec.engine == AGG_ENGINE_ONCHIP || (h->spec.engine == AGG_ENGINE_AUTO && h->spec.preagg != 1))) {
+    bool applied = false;
+    agg_status s = run_onchip(h, (const uint8_t *)d_records, n, &applied);
+    if (s) return s;
+    if (applied) {
+      h->engine = 5;
+      h->st.engine = 5;
+      return AGG_OK;
+    }
   }
   if (h->engine == 0) {
     // First batch: partition-first with LDS tables when the input shows no

@@ -5,7 +5,6 @@ from __future__ import annotations
 import numpy as np
 
 import oracle
-from tests.wl import oracle_spec
 
 
 def lib_spec_args(wl):
@@ -53,28 +52,3 @@ def assert_rows_equal(got_keys, got_cols, want_keys, want_cols, label=""):
 def check_against_oracle(records, spec_oracle, got_keys, got_cols, label=""):
     want_keys, want_cols = oracle.groupby(records, spec_oracle)
     assert_rows_equal(got_keys, got_cols, want_keys, want_cols, label)
-
-
-def check_sampled(records, wl, got_keys, got_cols, n_sample=64, seed=0):
-    """Full-size check: rows of sampled keys recomputed by the oracle one by one, plus the
-    invariants that hold at any size (row count, COUNT total, wrap-around SUM, global MIN/MAX)."""
-    spec = oracle_spec(wl)
-    assert got_keys.size == wl.d, f"{got_keys.size} rows, expected {wl.d}"
-    assert np.all(np.diff(got_keys) > 0), "duplicate keys in the result"
-    rng = np.random.default_rng(seed)
-    pick = np.sort(rng.choice(got_keys.size, size=min(n_sample, got_keys.size), replace=False))
-    q, found, qcols = oracle.rows_for_keys(records, spec, got_keys[pick])
-    assert np.all(found > 0), "a result key does not occur in the input"
-    idx = np.searchsorted(got_keys, q)
-    assert np.array_equal(got_cols[:, idx], qcols)
-    tot = oracle.totals(records, spec)
-    for a, (op, _, _) in enumerate(wl.aggs):
-        col = got_cols[a]
-        if op == "COUNT":
-            assert int(col.sum()) == wl.n and col.min() >= 1
-        elif op == "SUM":
-            assert int(col.astype(np.uint64).sum(dtype=np.uint64)) == int(np.int64(tot[a]).astype(np.uint64))
-        elif op == "MIN":
-            assert col.min() == tot[a]
-        else:
-            assert col.max() == tot[a]

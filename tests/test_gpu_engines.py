@@ -131,12 +131,19 @@ def test_lds_passes_or_refused_by_budget():
 
 
 def test_automatic_engine_choice():
+    """10k keys fit the on-chip engine's LDS tables; 300k keys take the partition-first LDS
+    engine, with a heavy hitter's key aggregated apart from the partitions."""
     wl = workloads.uniform_small()
     rec = wl.generate()
     k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d)
     check_against_oracle(rec, oracle_spec(wl), k, c, "auto uniform")
+    assert st["engine"] == 5, "10k keys should take the on-chip engine"
+    wl = workloads.uniform_small().scaled(1_000_000, 300_000)
+    rec = wl.generate()
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d)
+    check_against_oracle(rec, oracle_spec(wl), k, c, "auto uniform 300k")
     assert st["engine"] == 2, "uniform keys with an ample budget should take the LDS engine"
-    hh = workloads.heavy_hitter(400_000, 5_000)
+    hh = workloads.heavy_hitter(400_000, 100_000)
     rec = hh.generate()
     k, c, st = run_lib(rec, **lib_spec_args(hh), est_groups=hh.d)
     check_against_oracle(rec, oracle_spec(hh), k, c, "auto heavy hitter")

@@ -32,7 +32,9 @@ def test_zipf_hot_keys_exact(n, d, s, budget_mib):
     wl = _zipf_r16(workloads.SEED_BASE + 21 + n % 7, n, d, s)
     rec = wl.generate()
     print(f"case: hot keys zipf n={n} d={d} s={s} budget={budget_mib}MiB", flush=True)
-    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=budget_mib * MIB, est_groups=d)
+    # (5k keys alone would take the on-chip engine: the LDS engine is asked for)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=budget_mib * MIB, est_groups=d,
+                       engine="lds" if d < 30_000 else "auto")
     check_against_oracle(rec, oracle_spec(wl), k, c, f"hot zipf {n} {d} {s}")
     assert st["engine"] == 2 and st["lds_hot_keys"] > 0 and st["records_spilled"] == 0
     if budget_mib:

@@ -1,0 +1,110 @@
+"""GPU parity of the on-chip engine (one pass, key classes aggregated in LDS,
+folded into the level-0 HBM tables), against the oracle row by row.
+
+Cases: the 1M-record / 10k-key workload in its default configuration, narrow
+and wide LDS columns, two-field keys, the reserved key values, one key only,
+keys that all fall in one class (the class's LDS table overflows into the HBM
+tables), an estimate too low for the tables (the batch runs again on another
+engine), later batches on the same tables, a budget, and tiny inputs.
+"""
+import numpy as np
+import pytest
+
+import datagen
+from datagen import workloads
+from tests.gpu_util import check_against_oracle, lib_spec_args, run_lib
+from tests.test_oracle import SPEC_R24, _pool, _rand_r24
+from tests.wl import oracle_spec
+
+pytestmark = pytest.mark.gpu
+SPEC_R16 = {"record_bytes": 16, "keys": [(0, "u64")], "aggs": workloads.AGGS_R16_ALL}
+
+
+def _r16(keys, vals):
+    rec = np.zeros(len(keys), dtype=datagen.R16)
+    rec["key"] = np.asarray(keys, dtype=np.uint64)
+    rec["v"] = np.asarray(vals, dtype=np.int64)
+    return rec
+
+
+def test_uniform_1m_10k_default_engine_is_onchip():
+    wl = workloads.uniform_small()
+    rec = wl.generate()
+    print("case: onchip uniform-1M-10k", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d)
+    check_against_oracle(rec, oracle_spec(wl), k, c, "onchip 1M/10k")
+    assert st["engine"] == 5 and st["onchip_fallbacks"] == 0 and st["onchip_classes"] >= 2
+    assert st["records_spilled"] == 0 and st["levels"] == 1
+
+
+@pytest.mark.parametrize("n,d", [(1, 1), (100, 7), (5000, 5000), (300_000, 2500), (3_000_000, 3000)])
+def test_sizes(n, d):
+    """From one record to enough records for eight or more workers per class (XCD-aware roles)."""
+    wl = workloads.uniform_small().scaled(n, d)
+    rec = wl.generate()
+    print(f"case: onchip n={n} d={d}", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=d, engine="onchip")
+    check_against_oracle(rec, oracle_spec(wl), k, c, f"onchip n={n}")
+    assert st["engine"] == 5
+
+
+def test_r24_narrow_and_extremes():
+    """Two-field keys, MIN/MAX of int32 fields at their extremes in 4-byte LDS columns."""
+    rng = np.random.default_rng(11)
+    # 12k groups: four classes of 8-byte columns, three of narrow ones
+    rec = _rand_r24(rng, 300_000, _pool(rng, 11_900))
+    print("case: onchip R24", flush=True)
+    k, c, st = run_lib(rec, 24, SPEC_R24["keys"], SPEC_R24["aggs"], est_groups=12_000, engine="onchip")
+    check_against_oracle(rec, SPEC_R24, k, c, "onchip R24")
+    assert st["engine"] == 5 and st["lds_narrow"] == 1 and st["onchip_classes"] == 3
+
+
+def test_reserved_keys_and_one_key():
+    rng = np.random.default_rng(5)
+    keys = rng.choice(np.array([0, 1, 2**63, 2**64 - 1, 2**64 - 2, 12345], dtype=np.uint64), size=50_000)
+    vals = rng.integers(-2**63, 2**63 - 1, size=keys.size, dtype=np.int64)
+    rec = _r16(keys, vals)
+    print("case: onchip reserved keys", flush=True)
+    k, c, st = run_lib(rec, 16, [(0, "u64")], workloads.AGGS_R16_ALL, est_groups=6, engine="onchip")
+    check_against_oracle(rec, SPEC_R16, k, c, "onchip reserved")
+    assert st["engine"] == 5
+    one = _r16(np.full(70_000, 77, dtype=np.uint64), rng.integers(-10**9, 10**9, size=70_000))
+    # (one key is also sorted input: the on-chip engine is asked for)
+    k, c, st = run_lib(one, 16, [(0, "u64")], workloads.AGGS_R16_ALL, est_groups=1, engine="onchip")
+    check_against_oracle(one, SPEC_R16, k, c, "onchip one key")
+    assert st["engine"] == 5
+
+
+def test_one_class_overflows_into_tables():
+    """Keys x * 2^32 + x share their class (the class hash folds the two halves), so one
+    class's LDS table overflows and its extra keys go straight to the HBM tables."""
+    rng = np.random.default_rng(9)
+    x = rng.choice(2**31, size=9000, replace=False).astype(np.uint64)
+    pool = (x << np.uint64(32)) | x
+    keys = pool[rng.integers(0, pool.size, size=400_000)]
+    rec = _r16(keys, rng.integers(-10**6, 10**6, size=keys.size))
+    print("case: onchip one class", flush=True)
+    k, c, st = run_lib(rec, 16, [(0, "u64")], workloads.AGGS_R16_ALL, est_groups=9000, engine="onchip")
+    check_against_oracle(rec, SPEC_R16, k, c, "onchip one class")
+    assert st["engine"] == 5 and st["onchip_classes"] > 1 and st["onchip_fallbacks"] == 0
+
+
+def test_low_estimate_runs_the_batch_again():
+    """50k keys with an estimate of 2k: the tables planned for the estimate overflow, the
+    on-chip result is dropped and the batch runs on another engine."""
+    wl = workloads.uniform_small().scaled(1_000_000, 50_000)
+    rec = wl.generate()
+    print("case: onchip low estimate", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=2000, engine="onchip")
+    check_against_oracle(rec, oracle_spec(wl), k, c, "onchip low estimate")
+    assert st["onchip_fallbacks"] == 1 and st["engine"] != 5
+
+
+def test_later_batches_and_budget():
+    """Three batches (the first on-chip, the others into the same HBM tables), under a budget."""
+    wl = workloads.uniform_small().scaled(600_000, 8000)
+    rec = wl.generate()
+    print("case: onchip three batches", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), batches=3, est_groups=wl.d, budget=4 << 20)
+    check_against_oracle(rec, oracle_spec(wl), k, c, "onchip batches")
+    assert st["engine"] == 5 and st["pool_high_water"] <= 4 << 20
