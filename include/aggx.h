@@ -266,6 +266,34 @@ const char *agg_strerror(agg_status s);
  * given): the working set below which AGG_E_BUDGET is returned. */
 uint64_t agg_min_budget(const agg_spec *spec);
 
+/* ---- One query without allocation -----------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  One whole
+ * GROUP BY (agg_create + agg_consume + agg_finish + agg_destroy) on the on-chip
+ * engine's kernels, with every byte of working memory in a fixed device array
+ * of AGG_NOALLOC_SCRATCH_BYTES that each GPU holds from the first call until
+ * the process ends.  It calls no hipMalloc, hipFree or other allocating routine.
+ *
+ * spec: as for agg_create, with budget_bytes 0, device_workspace NULL and
+ *   engine AUTO or ONCHIP; est_groups (0: the record count) plans the launch;
+ *   work is ordered on spec->stream (NULL: the null stream) and the call
+ *   returns when the rows are written.
+ * d_records: n packed records (device, alignment as for agg_consume), read only.
+ * d_keys, d_cols: caller-owned device output, out_cap rows each: d_keys[r] the
+ *   canonical key, d_cols[a][r] aggregate a (d_cols is a host array of n_aggs
+ *   device pointers); row order unspecified, as for agg_finish.
+ * *n_rows: rows of the result (also when they exceed out_cap).
+ * Errors: AGG_E_INVALID (malformed spec or arguments, or more rows than
+ *   out_cap: *n_rows says how many), AGG_E_BUDGET (the estimate, or the groups
+ *   found, exceed what the array's table or the on-chip engine take: about
+ *   AGG_NOALLOC_SCRATCH_BYTES / (8 (1 + n_aggs)) groups, at most 8 LDS tables'
+ *   worth), AGG_E_DEVICE.
+ * Every call on one GPU uses that GPU's array (cleared at the start of each
+ * call): calls that overlap on one GPU race and must not be made. */
+#define AGG_NOALLOC_SCRATCH_BYTES (4u << 20)
+agg_status agg_query_noalloc(const agg_spec *spec, const void *d_records, uint64_t n, uint64_t *d_keys,
+                             int64_t *const *d_cols, uint64_t out_cap, uint64_t *n_rows);
+
 /* ---- Batched mode ---------------------------------------------------------
  * Many independent GROUP BY instances with one record layout and aggregate
  * list, run in one persistent launch captured in a hipGraph.  The paper

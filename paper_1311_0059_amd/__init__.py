@@ -14,7 +14,8 @@ import torch  # noqa: F401  (must be loaded before the native library)
 
 from . import _native as N
 
-__all__ = ["AggError", "GroupBy", "Batch", "Server", "make_spec", "load_library", "min_budget", "EXPORTS"]
+__all__ = ["AggError", "GroupBy", "Batch", "Server", "make_spec", "load_library", "min_budget", "query_noalloc",
+           "EXPORTS"]
 
 EXPORTS = N.EXPORTS
 
@@ -181,6 +182,24 @@ def _copy_rows(res, na: int, device: str):
         for a in range(na):
             _check(rt.hipMemcpy(cols[a].data_ptr(), res.d_cols[a], n * 8, 3), "hipMemcpy")
     return keys.to(device), cols.to(device)
+
+
+def query_noalloc(spec: N.Spec, ptr: int, n: int, out_keys, out_cols) -> int:
+    """One whole query through agg_query_noalloc (no allocation in the library): `out_keys`
+    (int64 device tensor) and `out_cols` (int64 device tensor [n_aggs, cap]) receive the rows;
+    returns the row count.  Raises AggError (its .status) on a library error."""
+    cap = out_keys.numel()
+    if out_cols.shape[0] != spec.n_aggs or out_cols.shape[1] != cap or not out_cols.is_contiguous():
+        raise ValueError("out_cols must be a contiguous [n_aggs, len(out_keys)] tensor")
+    cols = (ctypes.c_void_p * max(1, spec.n_aggs))(*[out_cols[a].data_ptr() for a in range(spec.n_aggs)])
+    rows = ctypes.c_uint64()
+    rc = load_library().agg_query_noalloc(ctypes.byref(spec), ctypes.c_void_p(ptr), n,
+                                          ctypes.c_void_p(out_keys.data_ptr()), cols, cap, ctypes.byref(rows))
+    if rc != 0:
+        err = AggError(rc, "agg_query_noalloc")
+        err.rows = rows.value
+        raise err
+    return rows.value
 
 
 class Batch:

@@ -147,7 +147,7 @@ class ServerStats(ctypes.Structure):
 EXPORTS = ["agg_create", "agg_consume", "agg_first_rows", "agg_finish", "agg_get_stats", "agg_destroy", "agg_strerror",
            "agg_min_budget", "agg_batch_create", "agg_batch_run", "agg_batch_result", "agg_batch_get_stats",
            "agg_batch_destroy", "agg_server_create", "agg_server_submit", "agg_server_wait",
-           "agg_server_release", "agg_server_get_stats", "agg_server_destroy"]
+           "agg_server_release", "agg_server_get_stats", "agg_server_destroy", "agg_query_noalloc"]
 
 _lib = None
 
@@ -196,6 +196,8 @@ def load(path: str = LIB_PATH):
     lib.agg_server_wait.restype = ctypes.c_int
     lib.agg_server_release.argtypes = [vp, u64]
     lib.agg_server_release.restype = ctypes.c_int
+    lib.agg_query_noalloc.argtypes = [ctypes.POINTER(Spec), vp, u64, vp, ctypes.POINTER(vp), u64, ctypes.POINTER(u64)]
+    lib.agg_query_noalloc.restype = ctypes.c_int
     lib.agg_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.agg_server_get_stats.restype = ctypes.c_int
     lib.agg_server_destroy.argtypes = [vp]

@@ -1473,6 +1473,13 @@ agg_status finish_impl(agg_handle *h) {
 
 }  // namespace
 
+namespace aggx {
+// The runtime's spec checks and on-chip planning, for the entry point that
+// allocates nothing (aggx_noalloc.hip).
+agg_status spec_check(const agg_spec *s) { return validate(s); }
+KSpec spec_kernels(const agg_spec &s) { return make_kspec(s); }
+bool onchip_shape(const KSpec &ks, uint64_t n, double G, OnchipPlan *op) { return onchip_plan(ks, n, G, op); }
+}  // namespace aggx
 
 extern "C" {
 
