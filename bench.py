@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--no-extra", dest="extra", action="store_false",
                     help=f"with the default workload, skip the {EXTRA_WORKLOAD} query reported under 'extra'")
     ap.add_argument("--policy", default="destage", choices=["destage", "prepart"])
-    ap.add_argument("--engine", default="auto", choices=["auto", "tables", "lds", "owner", "sorted"],
+    ap.add_argument("--engine", default="auto", choices=["auto", "tables", "lds", "owner", "sorted", "onchip"],
                     help="engine for the first batch (auto = the library's choice)")
     ap.add_argument("--cpu-runs", type=int, default=3,
                     help="runs of the CPU oracle over the whole input (median reported; 0 = skip)")

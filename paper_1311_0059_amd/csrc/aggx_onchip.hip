@@ -26,22 +26,96 @@ namespace aggx {
 
 constexpr uint32_t kOnBlock = 1024;  // threads per workgroup
 
-// The kernel holds the values of the records a thread reads together in
-// registers: it is compiled for at most kA aggregates (2, 4 or 8), reading four
-// records at a time below eight aggregates and two at eight, so that 1024
-// threads per workgroup keep everything in registers.
-__host__ __device__ constexpr int onchip_unroll(int kA) { return kA <= 4 ? 4 : 2; }
+// Each thread reads kOnKeys keys of a tile together; a wave keeps the records of
+// its class in a ring of kOnRing entries and folds them 64 at a time, so that
+// every lane of the fold has a record (a wave's own class is about 1/C of what
+// it reads).  The kernel is compiled for at most kA aggregates (2, 4 or 8).
+constexpr int kOnKeys = 3;
+constexpr uint32_t kOnRing = 256;  // holds a carry of 63 plus kOnKeys * 64 new entries
+static_assert(63 + kOnKeys * 64 <= kOnRing && kOnKeys * kOnBlock <= 0x8000, "ring entries");
 __host__ __device__ constexpr int onchip_aggs_for(uint32_t na) { return na <= 2 ? 2 : na <= 4 ? 4 : 8; }
 
-// The values a record contributes (COUNT: 1), for ks.na <= kA aggregates.
-template <int kA>
-__device__ __forceinline__ void record_vals(const uint8_t *rec, const KSpec &ks, uint64_t *vals) {
+// A column of the kernel's LDS table, as the fold sees it: an add or an
+// unsigned maximum, 4 or 8 bytes a slot.  MIN and MAX keep t = v ^ mask, whose
+// unsigned maximum is the wanted extreme (mask: all ones for MIN, plus the sign
+// bit for a signed compare), so every column starts at zero and takes one of
+// two operations.  Built from the spec, which every thread holds alike: the
+// branches on these fields do not diverge.
+struct OnCol {
+  uint32_t off;      // byte offset of the column from the first column
+  uint32_t in_off;   // the input field's offset in the record
+  bool narrow;       // 4-byte column
+  bool is_max;       // MIN or MAX (else COUNT or SUM: an add)
+  bool is_count;
+  bool in_w4;        // 32-bit input field
+  bool in_signed;
+  uint64_t mask;     // MIN/MAX transform (the low 32 bits for a narrow column)
+};
+
+template <bool kNarrow, int kA>
+__device__ __forceinline__ void onchip_cols(const KSpec &ks, uint32_t nslots, OnCol *cols) {
+  uint32_t off = 0;
 #pragma unroll
   for (int a = 0; a < kA; ++a) {
     if (a >= (int)ks.na) break;
     const uint32_t d = ks.agg[a];
-    vals[a] = desc_op(d) == OP_COUNT ? 1ULL : read_field(rec, desc_off(d), desc_type(d));
+    OnCol c;
+    c.narrow = kNarrow && lds_narrow(d);
+    c.is_max = desc_op(d) >= OP_MIN;
+    c.is_count = desc_op(d) == OP_COUNT;
+    c.in_w4 = desc_type(d) == T_U32 || desc_type(d) == T_I32;
+    c.in_signed = type_signed(desc_type(d));
+    c.in_off = desc_off(d);
+    const uint64_t sign = c.narrow ? 0x80000000ull : 0x8000000000000000ull;
+    const uint64_t ones = c.narrow ? 0xffffffffull : ~0ull;
+    c.mask = (desc_op(d) == OP_MIN ? ones : 0) ^ (c.in_signed ? sign : 0);
+    c.off = off;
+    off += (c.narrow ? 4u : 8u) * nslots;
+    cols[a] = c;
   }
+}
+
+// The value a record contributes to a column (COUNT: 1; 32-bit fields widened).
+__device__ __forceinline__ uint64_t onchip_val(const uint8_t *rec, const OnCol &c) {
+  if (c.is_count) return 1;
+  if (!c.in_w4) return ld64(rec + c.in_off);
+  const uint32_t x = ld32(rec + c.in_off);
+  return c.in_signed ? (uint64_t)(int64_t)(int32_t)x : (uint64_t)x;
+}
+
+// Fold one value into slot e of a column; a maximum reads first and issues its
+// atomic only when the value wins (a stale read never exceeds the true value).
+__device__ __forceinline__ void onchip_fold(uint8_t *t_cols, uint32_t e, const OnCol &c, uint64_t v) {
+  if (c.narrow) {
+    uint32_t *w = reinterpret_cast<uint32_t *>(t_cols + c.off) + e;
+    uint32_t x = (uint32_t)v;
+    if (!c.is_max) {
+      atomicAdd(w, x);
+    } else {
+      x ^= (uint32_t)c.mask;
+      if (x > __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) atomicMax(w, x);
+    }
+  } else {
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(t_cols + c.off) + e;
+    if (!c.is_max) {
+      atomicAdd(w, (unsigned long long)v);
+    } else {
+      v ^= c.mask;
+      if (v > __hip_atomic_load(reinterpret_cast<uint64_t *>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+        atomicMax(w, (unsigned long long)v);
+    }
+  }
+}
+
+// The grouping state of slot e in a column (MIN/MAX transformed back, 32-bit widened).
+__device__ __forceinline__ uint64_t onchip_state(const uint8_t *t_cols, uint32_t e, const OnCol &c) {
+  if (!c.narrow) {
+    const uint64_t t = reinterpret_cast<const uint64_t *>(t_cols + c.off)[e];
+    return c.is_max ? t ^ c.mask : t;
+  }
+  uint32_t x = reinterpret_cast<const uint32_t *>(t_cols + c.off)[e];
+  if (c.is_max) x ^= (uint32_t)c.mask;
+  return c.is_max && c.in_signed ? (uint64_t)(int64_t)(int32_t)x : (uint64_t)x;
 }
 
 // Class of a key: which workgroup of a group aggregates it.  A 32-bit
@@ -50,44 +124,6 @@ __device__ __forceinline__ void record_vals(const uint8_t *rec, const KSpec &ks,
 __device__ __forceinline__ uint32_t key_class(uint64_t key, uint32_t C) {
   const uint32_t f = (uint32_t)key ^ (uint32_t)(key >> 32);
   return __umulhi(f * 0x9E3779B1u, C);
-}
-
-// Fold one record into LDS slot `e`, reading MIN/MAX first and issuing their
-// atomics only when the value can still win (a stale read is never past the
-// true value: those words move one way).
-template <bool kNarrow, int kA>
-__device__ __forceinline__ void fold_lds_checked(uint8_t *cols, uint32_t nslots, uint32_t e, const KSpec &ks,
-                                                 const uint64_t *vals) {
-  for_lds_cols<kNarrow, kA>(ks, cols, nslots, [&](int a, uint32_t d, bool nw, uint8_t *c) {
-    const bool sg = type_signed(desc_type(d));
-    const uint32_t op = desc_op(d);
-    const uint64_t v = vals[a];
-    if (nw) {
-      uint32_t *w = reinterpret_cast<uint32_t *>(c) + e;
-      if (op <= OP_SUM) {
-        atomicAdd(w, (uint32_t)v);
-      } else {
-        const uint32_t cur = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        const uint32_t x = (uint32_t)v;
-        if (op == OP_MIN && (sg ? (int32_t)x < (int32_t)cur : x < cur))
-          sg ? (void)atomicMin(reinterpret_cast<int *>(w), (int)x) : (void)atomicMin(w, x);
-        if (op == OP_MAX && (sg ? (int32_t)x > (int32_t)cur : x > cur))
-          sg ? (void)atomicMax(reinterpret_cast<int *>(w), (int)x) : (void)atomicMax(w, x);
-      }
-    } else {
-      unsigned long long *w = reinterpret_cast<unsigned long long *>(c) + e;
-      if (op <= OP_SUM) {
-        atomicAdd(w, (unsigned long long)v);
-      } else {
-        const uint64_t cur = __hip_atomic_load(reinterpret_cast<uint64_t *>(w), __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (op == OP_MIN && (sg ? (int64_t)v < (int64_t)cur : v < cur))
-          sg ? (void)atomicMin(reinterpret_cast<long long *>(w), (long long)v) : (void)atomicMin(w, v);
-        if (op == OP_MAX && (sg ? (int64_t)v > (int64_t)cur : v > cur))
-          sg ? (void)atomicMax(reinterpret_cast<long long *>(w), (long long)v) : (void)atomicMax(w, v);
-      }
-    }
-  });
 }
 
 // A record's values in a full-size array, for the helpers that take kMaxAggs of them.
@@ -118,6 +154,26 @@ __device__ __forceinline__ bool fold_into_tables(uint64_t key, uint64_t h0, cons
   return true;
 }
 
+// The rare paths of the main loop: a record of a reserved key value goes to its
+// side group, and a record whose key found no room in the LDS table goes to the
+// HBM tables.  The unrolled loop only marks such records; they are read again
+// and folded afterwards in a loop that is not unrolled, so that fold_global's
+// code appears once in the kernel, not once per record read together.  Returns
+// false when the record found no room in the HBM tables either.
+__device__ __forceinline__ bool onchip_cold(const uint8_t *rec, const KSpec &ks, const KLevel &lv,
+                                            const PartMeta *meta, uint32_t *cnt, uint64_t *arena, Ctrl *ctrl) {
+  uint64_t vals[kMaxAggs];
+  const uint64_t key = read_key(rec, ks);
+  in_vals<0>(rec, ks, vals);
+  if (key >= kClosed) {
+    const int sg = key == kEmpty ? 0 : 1;
+    fold_global(reinterpret_cast<uint64_t *>(ctrl->side[sg]), ks, vals);
+    __hip_atomic_fetch_add(&ctrl->side_n[sg], 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+  }
+  return fold_into_tables(key, fmix64(key ^ kSeed0), vals, ks, lv, meta, cnt, arena);
+}
+
 // Block b -> (class, worker).  With xcd_map, the C workgroups of a worker are
 // b = x + 8 (C w' + c) for c < C: one XCD x, consecutive in dispatch order.
 __device__ __forceinline__ void onchip_role(uint32_t C, uint32_t xcd_map, uint32_t *cls, uint32_t *worker) {
@@ -131,6 +187,33 @@ __device__ __forceinline__ void onchip_role(uint32_t C, uint32_t xcd_map, uint32
   }
 }
 
+// Fold record i (read again: the class pass read its key moments before) into
+// the workgroup's LDS table, or, for a reserved key value or a key the table
+// has no room for, into its side group or the HBM tables.
+template <bool kNarrow, int kA>
+__device__ __forceinline__ void onchip_take(const uint8_t *rec, const KSpec &ks, const KLevel &lv,
+                                            const PartMeta *meta, uint32_t *cnt, uint64_t *arena, Ctrl *ctrl,
+                                            const OnCol *cols, uint64_t *t_key, uint8_t *t_cols, uint32_t nslots,
+                                            uint32_t cap, uint32_t *s_groups, unsigned long long *direct,
+                                            unsigned long long *lost) {
+  const uint64_t key = read_key(rec, ks);
+  if (key < kClosed) {
+    // The LDS slot comes from Fibonacci hashing (one 64-bit multiply; the HBM tables use the
+    // full hash).  The table is a cache of partial states: a key's records may be folded
+    // partly here and partly straight into the HBM tables, which add this table's states
+    // at the end, so a key that finds no room here simply goes there.
+    const uint32_t slot = lds_find_or_insert(t_key, nslots, cap, s_groups, key, key * 0x9E3779B97F4A7C15ull);
+    if (slot != ~0u) {
+#pragma unroll
+      for (int a = 0; a < kA; ++a)
+        if (a < (int)ks.na) onchip_fold(t_cols, slot, cols[a], onchip_val(rec, cols[a]));
+      return;
+    }
+    ++*direct;
+  }
+  if (!onchip_cold(rec, ks, lv, meta, cnt, arena, ctrl)) ++*lost;
+}
+
 template <bool kNarrow, int kA>
 __global__ void __launch_bounds__(kOnBlock) k_onchip(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
                                                      KLevel lv, const PartMeta *__restrict__ meta, uint32_t *cnt,
@@ -138,72 +221,86 @@ __global__ void __launch_bounds__(kOnBlock) k_onchip(const uint8_t *__restrict__
                                                      uint32_t xcd_map, uint32_t nslots, uint32_t cap) {
   extern __shared__ uint4 lds4[];
   __shared__ uint32_t s_groups;
+  // per wave: its own-class records waiting to be folded, as 16-bit entries (the
+  // record's index in its tile, bit 15 set when that tile is the one before the
+  // current one: a wave carries at most 63 entries into the next tile)
+  __shared__ uint16_t s_ring[kOnBlock / 64][kOnRing];
   uint64_t *t_key = reinterpret_cast<uint64_t *>(lds4);
   uint8_t *t_cols = reinterpret_cast<uint8_t *>(t_key + nslots);
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = __lane_id();
+  uint16_t *ring = s_ring[tid >> 6];
   uint32_t cls, worker;
   onchip_role(C, xcd_map, &cls, &worker);
-  for (uint32_t e = tid; e < nslots; e += blockDim.x) {
-    t_key[e] = kEmpty;
-    for_lds_cols<kNarrow>(ks, t_cols, nslots, [&](int, uint32_t d, bool nw, uint8_t *c) {
-      if (nw) reinterpret_cast<uint32_t *>(c)[e] = narrow_identity(d);
-      else reinterpret_cast<uint64_t *>(c)[e] = identity_of(d);
-    });
-  }
+  OnCol cols[kA];
+  onchip_cols<kNarrow, kA>(ks, nslots, cols);
+  // keys empty, every column zero (the transformed identity of all four aggregates)
+  const uint32_t col_words = (lds_slot_bytes(ks, kNarrow) - 8) / 4 * nslots;
+  for (uint32_t e = tid; e < nslots; e += blockDim.x) t_key[e] = kEmpty;
+  for (uint32_t w = tid; w < col_words; w += blockDim.x) reinterpret_cast<uint32_t *>(t_cols)[w] = 0;
   if (tid == 0) s_groups = 0;
   __syncthreads();
-  constexpr int U = onchip_unroll(kA);
-  const uint64_t B = blockDim.x, T = U * B;
+  const uint64_t T = (uint64_t)kOnKeys * kOnBlock;
   unsigned long long lost = 0, direct = 0;
+  uint32_t head = 0, tail = 0;  // the wave's ring (the same in every lane)
+  const uint8_t *prev_tile = in;
+  // records are addressed from the tile's first record with 32-bit offsets (a tile is
+  // under 1 MB); the tiles of a worker lie workers * T records apart
   for (uint64_t t0 = (uint64_t)worker * T; t0 < n; t0 += (uint64_t)workers * T) {
-    uint64_t keys[U], vals[U][kA];
+    const uint8_t *tile = in + t0 * ks.rb;
+    const uint32_t nt = (uint32_t)(n - t0 < T ? n - t0 : T);
+    // the class pass: every key of the tile, the wave's own-class records into its ring
+    uint64_t keys[kOnKeys];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint64_t i = t0 + u * B + tid;
-      const uint8_t *rec = in + (i < n ? i : 0) * ks.rb;
-      keys[u] = read_key(rec, ks);
-      record_vals<kA>(rec, ks, vals[u]);
+    for (int u = 0; u < kOnKeys; ++u) {
+      const uint32_t l = u * kOnBlock + tid;
+      keys[u] = read_key(tile + (l < nt ? l : 0) * ks.rb, ks);
     }
+    // the entries still in the ring (fewer than 64, all of the previous tile) now carry bit 15
+    const uint32_t carried = tail - head;
+    if (lane < carried) ring[(head + lane) & (kOnRing - 1)] |= 0x8000;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint64_t i = t0 + u * B + tid;
+    for (int u = 0; u < kOnKeys; ++u) {
+      const uint32_t l = u * kOnBlock + tid;
       const uint64_t key = keys[u];
-      if (i >= n) continue;
-      if (key >= kClosed) {
-        // the two reserved key values: side groups, taken by class 0
-        if (cls == 0) {
-          const int sg = key == kEmpty ? 0 : 1;
-          fold_global(reinterpret_cast<uint64_t *>(ctrl->side[sg]), ks, widen<kA>(vals[u], ks).v);
-          __hip_atomic_fetch_add(&ctrl->side_n[sg], 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        continue;
-      }
-      if (key_class(key, C) != cls) continue;
-      const uint64_t h0 = fmix64(key ^ kSeed0);
-      const uint32_t slot = lds_find_or_insert(t_key, nslots, cap, &s_groups, key, h0);
-      if (slot != ~0u) {
-        fold_lds_checked<kNarrow, kA>(t_cols, nslots, slot, ks, vals[u]);
-      } else {
-        ++direct;
-        if (!fold_into_tables(key, h0, widen<kA>(vals[u], ks).v, ks, lv, meta, cnt, arena)) ++lost;
-      }
+      const bool mine = l < nt && (key >= kClosed ? cls == 0 : key_class(key, C) == cls);
+      const uint64_t m = __ballot(mine);
+      if (mine) ring[(tail + __popcll(m & lanemask_lt())) & (kOnRing - 1)] = (uint16_t)l;
+      tail += __popcll(m);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // fold them a whole wave at a time; entries of the previous tile must not wait
+    // for another one (bit 15 names only the tile before), so while any are left a
+    // last, partial batch takes everything
+    uint32_t old_left = carried;
+    while (tail - head >= 64 || old_left) {
+      if (head + lane < tail) {
+        const uint32_t e = ring[(head + lane) & (kOnRing - 1)];
+        onchip_take<kNarrow, kA>((e & 0x8000 ? prev_tile : tile) + (e & 0x7fff) * ks.rb, ks, lv, meta, cnt, arena,
+                                 ctrl, cols, t_key, t_cols, nslots, cap, &s_groups, &direct, &lost);
+      }
+      head = tail - head >= 64 ? head + 64 : tail;
+      old_left = old_left > 64 ? old_left - 64 : 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    prev_tile = tile;
+  }
+  // the rest (fewer than a wave), all from the last tile
+  if (head + lane < tail) {
+    const uint32_t e = ring[(head + lane) & (kOnRing - 1)];
+    onchip_take<kNarrow, kA>(prev_tile + (e & 0x7fff) * ks.rb, ks, lv, meta, cnt, arena, ctrl, cols, t_key, t_cols,
+                             nslots, cap, &s_groups, &direct, &lost);
   }
   __syncthreads();
   // the workgroup's groups, as grouping states, into the HBM tables
   for (uint32_t e = tid; e < nslots; e += blockDim.x) {
     const uint64_t key = t_key[e];
     if (key >= kClosed) continue;
-    uint64_t st[kMaxAggs];
-    for_lds_cols<kNarrow>(ks, t_cols, nslots, [&](int a, uint32_t d, bool nw, uint8_t *c) {
-      if (!nw) {
-        st[a] = reinterpret_cast<const uint64_t *>(c)[e];
-      } else {
-        const uint32_t x = reinterpret_cast<const uint32_t *>(c)[e];
-        st[a] = desc_op(d) >= OP_MIN && type_signed(desc_type(d)) ? (uint64_t)(int64_t)(int32_t)x : (uint64_t)x;
-      }
-    });
-    if (!fold_into_tables(key, fmix64(key ^ kSeed0), st, ks, lv, meta, cnt, arena)) ++lost;
+    Vals8 st;
+#pragma unroll
+    for (int a = 0; a < kA; ++a)
+      if (a < (int)ks.na) st.v[a] = onchip_state(t_cols, e, cols[a]);
+    if (!fold_into_tables(key, fmix64(key ^ kSeed0), st.v, ks, lv, meta, cnt, arena)) ++lost;
   }
   if (lost) __hip_atomic_fetch_add(&ctrl->onchip_lost, lost, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (direct) __hip_atomic_fetch_add(&ctrl->onchip_direct, direct, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -231,7 +328,7 @@ hipError_t onchip_setup(uint32_t total_bytes, uint32_t *lds_bytes) {
   return hipSuccess;
 }
 
-uint64_t onchip_tile_records(uint32_t na) { return (uint64_t)onchip_unroll(onchip_aggs_for(na)) * kOnBlock; }
+uint64_t onchip_tile_records(uint32_t) { return (uint64_t)kOnKeys * kOnBlock; }
 
 hipError_t launch_onchip(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, const KLevel &lv,
                          const PartMeta *meta, uint32_t *cnt, uint64_t *arena, Ctrl *ctrl, const OnchipPlan &op) {

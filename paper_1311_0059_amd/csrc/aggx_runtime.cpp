@@ -996,8 +996,9 @@ double sample_groups(uint32_t ns, uint64_t dups) {
 // (no partition pass): C key classes, each aggregated by its own workgroups in
 // LDS, folded into the level-0 HBM tables at the end (aggx_onchip.hip).
 constexpr uint32_t kOnchipMaxClasses = 8;     // each tile is read from L2 once per class
-constexpr double kOnchipLoad = 0.8;           // LDS table load
+constexpr double kOnchipLoad = 0.85;          // LDS table load
 constexpr uint64_t kOnchipRecordsPerGroup = 16;  // records per worker and group before another worker pays
+constexpr double kOnchipAutoRatio = 256;         // records per group from which AUTO prefers this engine
 
 bool onchip_plan(const KSpec &ks, uint64_t n, double G, OnchipPlan *op) {
   const DeviceSetup *ds = device_setup();
@@ -1072,6 +1073,11 @@ agg_status run_onchip(agg_handle *h, const uint8_t *in, uint64_t n, bool *applie
     if (!h->spec.est_groups) G = std::min(G, 1.25 * Gs);
     else if (Gs > 4.0 * G) return AGG_OK;
   }
+  // AUTO takes it where it pays: many records per group (each workgroup's LDS table then
+  // absorbs most updates), or a batch the partition-first engine does not take
+  if (h->spec.engine == AGG_ENGINE_AUTO && (double)n < kOnchipAutoRatio * G &&
+      !(h->unlimited && n * h->ks.rb > kLdsMaxInput))
+    return AGG_OK;
   OnchipPlan op;
   if (!onchip_plan(h->ks, n, G, &op)) return AGG_OK;
   h->plan_hint_n = n;

@@ -27,19 +27,30 @@ def _r16(keys, vals):
     return rec
 
 
-def test_uniform_1m_10k_default_engine_is_onchip():
+def test_uniform_1m_10k_and_automatic_choice():
+    """The 1M-record / 10k-key workload on the on-chip engine; AUTO takes this engine when a
+    batch has many records per group (3M records, 5k keys) and not at 100 per group."""
     wl = workloads.uniform_small()
     rec = wl.generate()
     print("case: onchip uniform-1M-10k", flush=True)
-    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d, engine="onchip")
     check_against_oracle(rec, oracle_spec(wl), k, c, "onchip 1M/10k")
     assert st["engine"] == 5 and st["onchip_fallbacks"] == 0 and st["onchip_classes"] >= 2
     assert st["records_spilled"] == 0 and st["levels"] == 1
+    _, _, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d)
+    assert st["engine"] == 2
+    wl = workloads.uniform_small().scaled(3_000_000, 5_000)
+    rec = wl.generate()
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d)
+    check_against_oracle(rec, oracle_spec(wl), k, c, "auto onchip")
+    assert st["engine"] == 5
 
 
-@pytest.mark.parametrize("n,d", [(1, 1), (100, 7), (5000, 5000), (300_000, 2500), (3_000_000, 3000)])
+@pytest.mark.parametrize("n,d", [(1, 1), (100, 7), (5000, 5000), (300_000, 2500), (3_000_000, 3000),
+                                 (400_000, 25_000), (2_500_000, 27_000)])
 def test_sizes(n, d):
-    """From one record to enough records for eight or more workers per class (XCD-aware roles)."""
+    """From one record to enough records for eight or more workers per class (XCD-aware roles),
+    and up to eight classes (a wave's own class then a small share of what it reads)."""
     wl = workloads.uniform_small().scaled(n, d)
     rec = wl.generate()
     print(f"case: onchip n={n} d={d}", flush=True)
@@ -105,6 +116,6 @@ def test_later_batches_and_budget():
     wl = workloads.uniform_small().scaled(600_000, 8000)
     rec = wl.generate()
     print("case: onchip three batches", flush=True)
-    k, c, st = run_lib(rec, **lib_spec_args(wl), batches=3, est_groups=wl.d, budget=4 << 20)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), batches=3, est_groups=wl.d, budget=4 << 20, engine="onchip")
     check_against_oracle(rec, oracle_spec(wl), k, c, "onchip batches")
     assert st["engine"] == 5 and st["pool_high_water"] <= 4 << 20

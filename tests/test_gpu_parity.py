@@ -33,7 +33,7 @@ def test_small_workload_exact():
     print("case: uniform-1M-10k", flush=True)
     k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d)
     check_against_oracle(rec, oracle_spec(wl), k, c, "uniform-1M-10k")
-    assert st["levels"] == 1 and st["records_spilled"] == 0 and st["engine"] == 5
+    assert st["levels"] == 1 and st["records_spilled"] == 0
 
 
 def test_small_workload_without_estimate():
