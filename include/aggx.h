@@ -202,6 +202,14 @@ typedef struct agg_stats {
   uint64_t first_full_record;   /* HBM tables: input index of the first record whose partition's table was
                                    full, i.e. records consumed before the first overflow (the Appendix's
                                    I_raw); UINT64_MAX when no table filled */
+  /* Pre-Partitioning's one-byte filter per slot (Sec. 4.3.4), built for each partition whose table filled:
+   * records of filtered partitions whose key it showed absent (spilled without a probe), and those that
+   * passed it but whose key was absent all the same (its false positives, the alpha of Sec. 5.3.4). */
+  uint64_t filter_rejects;
+  uint64_t filter_false;
+  uint32_t partitions_filtered;  /* partitions whose filter was built (all levels) */
+  uint32_t reserved_stats2;
+  uint64_t table_slots_l0;      /* HBM tables: slots of the level-0 tables (the paper's H, summed) */
 } agg_stats;
 
 /* Start one GROUP BY query (Sec. 3.1) under the memory budget M of Sec. 3.2

@@ -14,6 +14,7 @@ Contents:
   yao_i_key, yao_i_raw          -- Appendix, input component (Yao's formula, draws without replacement)
   hybrid_hash_partitions        -- Sec. 4.3, Formula (1)
   spilled_fraction              -- Sec. 5.3.1 / 5.3.4 I/O model: share of records spilled, 1 - K/G_t
+  slot_filter_false_positive    -- Sec. 4.3.4 / 5.3.4: alpha of a one-byte filter per hash-table slot
 
 A spec here is the oracle's own plain description:
   {"record_bytes": int, "keys": [(offset, type)], "aggs": [(op, offset, type)]}
@@ -195,6 +196,15 @@ def hybrid_hash_partitions(G: float, M: float, F: float = 1.2) -> int:
     if M <= 2:
         raise ValueError("Formula (1) needs M > 2")
     return max(0, math.ceil((G * F - M) / (M - 2)))
+
+
+def slot_filter_false_positive(K: float, H: float, bits: int = 8) -> float:
+    """Sec. 4.3.4 / 5.3.4: the false-positive ratio alpha of a filter of `bits` bits per slot of
+    a table of H slots holding K keys, where each key sets one bit (chosen by its hash) in the
+    filter of its home slot.  An absent key tests the bit its own hash chooses in its own home
+    slot's filter; with independent uniform hashes that bit is set with probability
+    1 - (1 - 1/(bits H))^K."""
+    return 1.0 - (1.0 - 1.0 / (bits * H)) ** K
 
 
 def spilled_fraction(K: float, G_t: float) -> float:

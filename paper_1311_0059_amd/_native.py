@@ -93,6 +93,11 @@ class Stats(ctypes.Structure):
         ("onchip_direct", ctypes.c_uint64),
         ("records_spilled_l0", ctypes.c_uint64),
         ("first_full_record", ctypes.c_uint64),
+        ("filter_rejects", ctypes.c_uint64),
+        ("filter_false", ctypes.c_uint64),
+        ("partitions_filtered", ctypes.c_uint32),
+        ("reserved_stats2", ctypes.c_uint32),
+        ("table_slots_l0", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:

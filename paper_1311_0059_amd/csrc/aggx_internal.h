@@ -78,6 +78,9 @@ struct KLevel {
   uint32_t slot_shift;   // level 0: slot hash = h0 << slot_shift; deeper levels use seed_slot
   uint64_t seed_slot;
   uint64_t rec_base = ~0ULL;  // level 0, raw records: input index of the launch's first record (else ~0)
+  // Pre-Partitioning's per-slot filters (one byte per arena slot), consulted for the
+  // partitions whose meta has filt set; nullptr under Dynamic Destaging
+  const uint8_t *filter = nullptr;
 };
 
 // Per-partition table descriptor.  A partition is either resident (a table of
@@ -87,11 +90,12 @@ struct PartMeta {
   uint32_t nslots;
   uint32_t cap;      // groups allowed in the table (its load limit)
   uint32_t spilled;  // 1: every record of this partition goes to the spill run
-  uint32_t pad;
+  uint32_t filt;     // 1: the table is full and its per-slot filter is built (Pre-Partitioning)
 };
 
 // Control block in device memory (inside the working budget).
-constexpr uint32_t kMaxHot = 64;  // keys the sampler can report as frequent
+constexpr uint32_t kMaxHot = 256;  // keys the samplers can report as frequent
+constexpr uint32_t kHotSample = 16384;  // keys the frequent-key sampler reads (a power of two)
 constexpr uint32_t kHotMin = 3;    // occurrences in the 2048-record sample that make a key frequent
 
 struct Ctrl {
@@ -110,6 +114,8 @@ struct Ctrl {
   unsigned long long onchip_lost;  // on-chip engine: records / states that found no room in the HBM tables
   unsigned long long onchip_direct;  // on-chip engine: records of keys its LDS tables had no room for
   unsigned long long first_full;   // lowest input index of a level-0 record that found its table full (~0: none)
+  unsigned long long filter_rejects;  // records whose key the per-slot filter showed absent (no probe)
+  unsigned long long filter_false;    // records that passed the filter but whose key was absent
 };
 
 // Frequent keys taken out of the LDS engine's partitioning: they are folded
@@ -191,11 +197,19 @@ hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint6
 // multiplicity, and whether the sampled keys are out of order (out[0..2]).
 hipError_t launch_sample_dups(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t ns,
                               Ctrl *ctrl);
+// The frequent keys of a batch from min(n, kHotSample) evenly spaced records: the keys
+// seen at least kHotMin times, most frequent first, at most kMaxHot (ctrl->sample_hot).
+hipError_t launch_sample_hot(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, Ctrl *ctrl);
+hipError_t sample_hot_setup();
 hipError_t launch_flush(hipStream_t s, const uint64_t *arena, uint64_t nslots, const KSpec &ks, uint64_t *out_keys,
                         const OutCols &out_cols, uint64_t out_cap, Ctrl *ctrl);
 hipError_t launch_u64_set(hipStream_t s, unsigned long long *p, uint32_t n, unsigned long long v);
 // dst[i] = src[i * stride] for i < n (packs the padded per-partition counters).
 hipError_t launch_gather_u32(hipStream_t s, const uint32_t *src, uint32_t stride, uint32_t n, uint32_t *dst);
+// Pre-Partitioning's per-slot filter of a full partition: for each resident key,
+// bit (hs & 7) of the byte of its home slot (the slot its probe starts from).
+hipError_t launch_filter_build(hipStream_t s, const uint64_t *arena, uint8_t *filter, uint64_t base, uint32_t nslots,
+                               const KSpec &ks, const KLevel &lv);
 hipError_t launch_extract(hipStream_t s, uint64_t *arena, uint64_t base, uint64_t nslots, const KSpec &ks,
                           Ctrl *ctrl, KSpill spill);
 // Grace partitioning of a run: histogram of the digit (h0 >> shift) & mask,
@@ -267,6 +281,7 @@ struct DeviceSetup {
   int cus;                     // compute units
   int update_per_cu[2][2][4];  // k_update<kind, preagg> blocks per CU without dynamic LDS, block = 64 (i + 1)
   uint32_t onchip_lds_max;     // dynamic LDS bytes of the on-chip engine's kernel (0: not available)
+  bool sample_hot_ok;          // the frequent-key sampler could be given its LDS
   uint32_t batch_lds_max;      // dynamic LDS bytes of the batched-mode kernel
   int batch_per_cu;            // its blocks per CU at batch_lds_max
 };

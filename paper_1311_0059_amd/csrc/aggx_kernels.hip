@@ -65,6 +65,7 @@ __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, 
   uint8_t *region = KIND == 0 ? spill.raw : spill.state;
   unsigned long long *ctr = KIND == 0 ? &ctrl->raw_ctr : &ctrl->state_ctr;
   const uint32_t tid = threadIdx.x;
+  uint32_t f_rej = 0, f_false = 0;  // filter outcomes of this thread's records
   if (tid == 0) s_n = 0;
   if (PREAGG) {
     for (uint32_t e = tid; e < cache_n; e += blockDim.x) {
@@ -114,7 +115,19 @@ __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, 
             to_spill = true;
           } else {
             const uint64_t hs = lv.level == 0 ? (h0 << lv.slot_shift) : fmix64(key ^ lv.seed_slot);
-            const uint64_t s = find_or_insert(key, hs, pm, p, W, cnt, arena);
+            uint64_t s;
+            // the filter bit: low bits of the unshifted hash (the home slot and the
+            // partition digit take its high bits)
+            const uint32_t fbit = 1u << (uint32_t)((lv.level == 0 ? h0 : hs) & 7);
+            if (pm.filt && !(lv.filter[pm.base + mulhi64(hs, pm.nslots)] & fbit)) {
+              // Pre-Partitioning, full table: the per-slot filter says the key is not
+              // there, so the record spills without a probe (Sec. 4.3.4)
+              s = ~0ULL;
+              ++f_rej;
+            } else {
+              s = find_or_insert(key, hs, pm, p, W, cnt, arena);
+              if (pm.filt && s == ~0ULL) ++f_false;
+            }
             if (s != ~0ULL) {
               fold_global(arena + s * W + 1, ks, vals);
               if (PREAGG) {
@@ -173,6 +186,19 @@ __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, 
       for (int a = 0; a < kMaxAggs; ++a)
         if (a < (int)ks.na) vals[a] = c_acc[(uint64_t)a * cache_n + e];
       fold_global(arena + (uint64_t)c_slot[e] * W + 1, ks, vals);
+    }
+  }
+  if (lv.filter) {
+    // the filter counts, summed over the wave, one atomic each per wave
+    for (int o = 32; o > 0; o >>= 1) {
+      f_rej += __shfl_xor(f_rej, o);
+      f_false += __shfl_xor(f_false, o);
+    }
+    if (__lane_id() == 0 && (f_rej | f_false)) {
+      __hip_atomic_fetch_add(&ctrl->filter_rejects, (unsigned long long)f_rej, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&ctrl->filter_false, (unsigned long long)f_false, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -238,6 +264,66 @@ __global__ void __launch_bounds__(256) k_sample_dups(const uint8_t *__restrict__
   }
 }
 
+// The frequent keys of a skewed batch: the keys of ns = kHotSample evenly spaced
+// records (all records of a smaller batch) are sorted in LDS (bitonic network),
+// each run of equal keys is one sampled key with its count, and the keys seen at
+// least kHotMin times become the frequent keys -- the most frequent first, by
+// bands of counts, at most kMaxHot.  One block.
+constexpr uint32_t kHotCand = 2048;  // candidate keys kept for the selection
+__global__ void __launch_bounds__(1024) k_sample_hot(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
+                                                     Ctrl *ctrl) {
+  extern __shared__ unsigned long long sk[];  // kHotSample keys
+  __shared__ unsigned long long cand_key[kHotCand];
+  __shared__ uint32_t cand_cnt[kHotCand];
+  __shared__ uint32_t ncand, nhot;
+  const uint32_t tid = threadIdx.x, N = kHotSample;
+  const uint64_t ns = n < N ? n : N;
+  for (uint32_t j = tid; j < N; j += blockDim.x)
+    sk[j] = j < ns ? read_key(in + ((uint64_t)j * n / ns) * ks.rb, ks) : kEmpty;  // padding sorts last
+  if (tid == 0) ncand = nhot = 0;
+  __syncthreads();
+  for (uint32_t k = 2; k <= N; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = tid; i < N; i += blockDim.x) {
+        const uint32_t p = i ^ j;
+        if (p > i) {
+          const unsigned long long a = sk[i], b = sk[p];
+          if ((a > b) == ((i & k) == 0)) {
+            sk[i] = b;
+            sk[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // runs of equal keys: the thread holding a run's first element measures it
+  for (uint32_t i = tid; i < ns; i += blockDim.x) {
+    const unsigned long long key = sk[i];
+    if (key >= kClosed || (i > 0 && sk[i - 1] == key)) continue;
+    uint32_t e = i + 1;
+    while (e < ns && sk[e] == key) ++e;
+    if (e - i < kHotMin) continue;
+    const uint32_t c = atomicAdd(&ncand, 1u);
+    if (c < kHotCand) {
+      cand_key[c] = key;
+      cand_cnt[c] = e - i;
+    }
+  }
+  __syncthreads();
+  const uint32_t nc = ncand < kHotCand ? ncand : kHotCand;
+  const uint32_t bands[6] = {~0u, 512, 128, 32, 8, kHotMin};
+  for (int band = 1; band < 6; ++band) {
+    for (uint32_t c = tid; c < nc; c += blockDim.x) {
+      if (cand_cnt[c] < bands[band] || cand_cnt[c] >= bands[band - 1]) continue;
+      const uint32_t pos = atomicAdd(&nhot, 1u);
+      if (pos < kMaxHot) ctrl->sample_hot[pos] = cand_key[c];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) ctrl->sample_hot_n = nhot < kMaxHot ? nhot : kMaxHot;
+}
+
 __global__ void k_table_init(uint64_t *arena, uint64_t nslots, KSpec ks) {
   const uint32_t W = 1 + ks.na;
   for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < nslots; s += (uint64_t)gridDim.x * blockDim.x) {
@@ -272,6 +358,8 @@ __global__ void k_ctrl_init(Ctrl *c, KSpec ks) {
     c->any_ovf = 0;
     c->onchip_lost = 0;
     c->onchip_direct = 0;
+    c->filter_rejects = 0;
+    c->filter_false = 0;
     c->first_full = ~0ULL;
     for (int g = 0; g < 2; ++g) {
       c->side_n[g] = 0;
@@ -319,6 +407,25 @@ __global__ void __launch_bounds__(256) k_flush(const uint64_t *__restrict__ aren
       ++r;
     }
     __syncthreads();
+  }
+}
+
+// Pre-Partitioning's per-slot filter (Sec. 4.3.4) of one full partition: the
+// byte of each resident key's home slot gets the bit that the low 3 bits of the
+// key's unshifted slot hash choose (independent of the home slot, which the high
+// bits choose).  The bytes start at zero (cleared when the level starts) and only
+// gain bits; a full table gains no keys, so the filter stays exact afterwards.
+__global__ void __launch_bounds__(256) k_filter_build(const uint64_t *__restrict__ arena, uint8_t *filter,
+                                                      uint64_t base, uint32_t nslots, KSpec ks, KLevel lv) {
+  const uint32_t W = 1 + ks.na;
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < nslots; e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = arena[(base + e) * W];
+    if (key >= kClosed) continue;
+    const uint64_t h = fmix64(key ^ (lv.level == 0 ? kSeed0 : lv.seed_slot));
+    const uint64_t hs = lv.level == 0 ? h << lv.slot_shift : h;
+    const uint64_t at = base + mulhi64(hs, nslots);
+    // the byte's bit, set through its aligned 32-bit word
+    atomicOr(reinterpret_cast<uint32_t *>(filter + (at & ~3ull)), (1u << (uint32_t)(h & 7)) << (8 * (at & 3)));
   }
 }
 
@@ -488,6 +595,19 @@ hipError_t launch_update(hipStream_t s, int input_kind, const uint8_t *in, uint6
   return hipGetLastError();
 }
 
+hipError_t sample_hot_setup() {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(k_sample_hot), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(8 * kHotSample));
+}
+
+hipError_t launch_sample_hot(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, Ctrl *ctrl) {
+  if (n == 0) return hipSuccess;
+  const DeviceSetup *ds = device_setup();
+  if (!ds || !ds->sample_hot_ok) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sample_hot, dim3(1), dim3(1024), 8 * kHotSample, s, in, n, ks, ctrl);
+  return hipGetLastError();
+}
+
 hipError_t launch_sample_dups(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t ns,
                               Ctrl *ctrl) {
   hipLaunchKernelGGL(k_sample_dups, dim3(1), dim3(256), 0, s, in, n, ks, ns, ctrl);
@@ -499,6 +619,14 @@ hipError_t launch_flush(hipStream_t s, const uint64_t *arena, uint64_t nslots, c
   if (nslots == 0) return hipSuccess;
   hipLaunchKernelGGL(k_flush, dim3(grid_for(nslots, 256 * kFlushPerThread, 256 * 16)), dim3(256), 0, s, arena, nslots,
                      ks, out_keys, out_cols, out_cap, ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_build(hipStream_t s, const uint64_t *arena, uint8_t *filter, uint64_t base, uint32_t nslots,
+                               const KSpec &ks, const KLevel &lv) {
+  if (nslots == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_filter_build, dim3(grid_for(nslots, 256, 1024)), dim3(256), 0, s, arena, filter, base, nslots,
+                     ks, lv);
   return hipGetLastError();
 }
 

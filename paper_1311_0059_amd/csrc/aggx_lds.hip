@@ -26,12 +26,12 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t key, uint32_t shift, uint3
   return mask ? (uint32_t)(fmix64(key ^ kSeed0) >> shift) & mask : 0u;
 }
 
-// The frequent keys in LDS: an open-addressing set of 1024 slots mapping a key to
+// The frequent keys in LDS: an open-addressing set of 2048 slots mapping a key to
 // its index in KHot.  Built by the whole block; hot keys are never reserved values.
-// At most 64 keys in 1024 slots: a lookup, made for every record, almost always
+// At most 256 keys in 2048 slots: a lookup, made for every record, almost always
 // ends at its first slot, so the lanes of a wave rarely wait on each other.
-constexpr uint32_t kHotSlots = 1024;
-constexpr uint32_t kHotHashShift = 54;  // 64 - log2(kHotSlots)
+constexpr uint32_t kHotSlots = 2048;
+constexpr uint32_t kHotHashShift = 53;  // 64 - log2(kHotSlots)
 
 __device__ __forceinline__ void hot_build(const KHot &hot, unsigned long long *hk, uint32_t *hid) {
   for (uint32_t e = threadIdx.x; e < kHotSlots; e += blockDim.x) hk[e] = kEmpty;
@@ -178,10 +178,58 @@ __device__ __forceinline__ void scatter_one(const uint8_t *rec, uint32_t d, uint
   }
 }
 
+// Records of RW 32-bit words are read whole into registers with 8-byte loads
+// (one 16-byte load for 16-byte records when both buffers allow), their key
+// taken from those registers, and written from them: every load of a step is
+// issued before any digit is computed, and no record is read twice.
+template <int RW>
+__device__ __forceinline__ void rec_load(const uint8_t *rec, uint32_t vec, uint32_t *w) {
+  if (RW == 4 && vec == 16) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(rec);
+    w[0] = v.x, w[1] = v.y, w[2] = v.z, w[3] = v.w;
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < RW / 2; ++j) {
+    const uint2 v = reinterpret_cast<const uint2 *>(rec)[j];
+    w[2 * j] = v.x, w[2 * j + 1] = v.y;
+  }
+}
+
+template <int RW>
+__device__ __forceinline__ void rec_store(uint8_t *dst, uint32_t vec, const uint32_t *w) {
+  if (RW == 4 && vec == 16) {
+    *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < RW / 2; ++j) reinterpret_cast<uint2 *>(dst)[j] = make_uint2(w[2 * j], w[2 * j + 1]);
+}
+
+// Word idx of a record held in registers (idx < RW; a select chain, not an indexed access).
+template <int RW>
+__device__ __forceinline__ uint32_t rec_word(const uint32_t *w, uint32_t idx) {
+  uint32_t r = w[0];
+#pragma unroll
+  for (int j = 1; j < RW; ++j) r = idx == (uint32_t)j ? w[j] : r;
+  return r;
+}
+
+// The canonical key of a record held in registers (as read_key).
+template <int RW>
+__device__ __forceinline__ uint64_t rec_key(const uint32_t *w, const KSpec &ks) {
+  const uint32_t lo = rec_word<RW>(w, ks.koff0 / 4);
+  if (ks.nk == 2) return ((uint64_t)lo << 32) | rec_word<RW>(w, ks.koff1 / 4);
+  if (ks.ktype0 == T_U32) return lo;
+  if (ks.ktype0 == T_I32) return (uint64_t)(int64_t)(int32_t)lo;
+  return ((uint64_t)rec_word<RW>(w, ks.koff0 / 4 + 1) << 32) | lo;
+}
+
 // Only partitions [d_lo, d_lo + d_n) are written (a pass of the LDS engine over
 // part of the digit range); `cursors` and the output are relative to d_lo.
 // With `block_counts` (stored by k_part_count over the same chunks) the block
 // takes its counts from there instead of reading its keys twice.
+template <int RW>
 __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
                                                              uint32_t shift, uint32_t mask, uint32_t d_lo,
                                                              uint32_t d_n, uint64_t chunk,
@@ -238,7 +286,22 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
   }
   __syncthreads();
   i = lo + threadIdx.x;
-  if (hot.n == 0) {
+  if constexpr (RW > 0) {
+    // whole records into registers, then their digits and places
+    for (; i + (kPartUnroll - 1) * B < hi; i += kPartUnroll * B) {
+      uint32_t w[kPartUnroll][RW];
+#pragma unroll
+      for (int u = 0; u < kPartUnroll; ++u) rec_load<RW>(in + (i + u * B) * ks.rb, vec, w[u]);
+#pragma unroll
+      for (int u = 0; u < kPartUnroll; ++u) {
+        const uint32_t d = rel_digit(rec_key<RW>(w[u], ks));
+        if (d < d_n) {
+          const uint32_t r = atomicAdd(&lc[d], 1u);
+          rec_store<RW>(out + ((uint64_t)lbase[d] + r) * ks.rb, vec, w[u]);
+        }
+      }
+    }
+  } else if (hot.n == 0) {
     // all keys' loads first, then their digits
     for (; i + (kPartUnroll - 1) * B < hi; i += kPartUnroll * B) {
       uint64_t k[kPartUnroll];
@@ -450,7 +513,7 @@ hipError_t launch_part_count(hipStream_t s, const uint8_t *in, uint64_t n, const
   if (n == 0) return hipSuccess;
   if (hot.n > kMaxHot) return hipErrorInvalidValue;
   const uint64_t blocks = (n + chunk - 1) / chunk;
-  // (its frequent-key arrays take another ~17 KB of static LDS)
+  // (its frequent-key arrays take another ~41 KB of static LDS)
   constexpr size_t kStatic = 12ull * kHotSlots + 4ull * kMaxHot + 8ull * kMaxAggs * kMaxHot;
   static_assert(kStatic < 64 * 1024, "the count kernel's static LDS");
   if (!kernel_lds_allowed(4ull * (mask + 1), false)) return hipErrorInvalidValue;
@@ -478,8 +541,16 @@ hipError_t launch_part_scatter(hipStream_t s, const uint8_t *in, uint64_t n, con
   if (!kernel_lds_allowed(lds, true)) return hipErrorInvalidValue;
   const uintptr_t a = reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(in);
   const uint32_t vec = ks.rb % 16 == 0 && a % 16 == 0 ? 16 : ks.rb % 8 == 0 && a % 8 == 0 ? 8 : 4;
-  hipLaunchKernelGGL(k_part_scatter, dim3((uint32_t)blocks), dim3(kPartBlock), lds, s, in, n, ks, shift, mask, d_lo,
-                     d_n, chunk, block_counts, hot, cursors, out, vec);
+  // 24-byte records (8-byte aligned) are moved whole through registers: the scatter
+  // of the 500M-record Zipf batch went from 27.5 to 22.4 ms a step.  (16-byte records
+  // measured slower that way, 5.2 to 7.8 ms a step on the 200M-record batch: for
+  // them the record is read again only when it is written.)
+  if (ks.rb == 24 && vec >= 8)
+    hipLaunchKernelGGL(k_part_scatter<6>, dim3((uint32_t)blocks), dim3(kPartBlock), lds, s, in, n, ks, shift, mask,
+                       d_lo, d_n, chunk, block_counts, hot, cursors, out, vec);
+  else
+    hipLaunchKernelGGL(k_part_scatter<0>, dim3((uint32_t)blocks), dim3(kPartBlock), lds, s, in, n, ks, shift, mask,
+                       d_lo, d_n, chunk, block_counts, hot, cursors, out, vec);
   return hipGetLastError();
 }
 
@@ -545,7 +616,10 @@ const DeviceSetup *device_setup() {
   };
   uint32_t narrow_max = 0;
   allow(reinterpret_cast<const void *>(k_part_count), &ds.count_lds_max);
-  allow(reinterpret_cast<const void *>(k_part_scatter), &ds.scatter_lds_max);
+  uint32_t sc6 = 0;
+  allow(reinterpret_cast<const void *>(k_part_scatter<0>), &ds.scatter_lds_max);
+  allow(reinterpret_cast<const void *>(k_part_scatter<6>), &sc6);
+  ds.scatter_lds_max = std::min(ds.scatter_lds_max, sc6);
   allow(reinterpret_cast<const void *>(k_lds_agg<false>), &ds.lds_max);
   allow(reinterpret_cast<const void *>(k_lds_agg<true>), &narrow_max);
   ds.lds_max = std::min(ds.lds_max, narrow_max);
@@ -558,6 +632,7 @@ const DeviceSetup *device_setup() {
         ds.update_per_cu[kind][pre][i] = per;
       }
   if (onchip_setup(want, &ds.onchip_lds_max) != hipSuccess) ds.onchip_lds_max = 0;
+  ds.sample_hot_ok = sample_hot_setup() == hipSuccess;
   if (batch_kernel_setup(want, &ds.batch_lds_max, &ds.batch_per_cu) != hipSuccess || ds.batch_per_cu < 1) {
     // 64 KB in all when more cannot be had
     if (batch_kernel_setup(64 * 1024, &ds.batch_lds_max, &ds.batch_per_cu) != hipSuccess) ds.batch_lds_max = 0;

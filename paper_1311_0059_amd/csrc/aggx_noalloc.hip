@@ -55,7 +55,7 @@ __global__ void k_noalloc_begin(PartMeta *meta, uint32_t *cnt, uint32_t nslots, 
     m.nslots = nslots;
     m.cap = cap;
     m.spilled = 0;
-    m.pad = 0;
+    m.filt = 0;
     *meta = m;
   }
   if (threadIdx.x < kCntStride) cnt[threadIdx.x] = 0;

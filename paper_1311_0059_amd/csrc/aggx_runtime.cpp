@@ -25,6 +25,7 @@ using namespace aggx;
 namespace {
 
 constexpr uint64_t kCtrlBytes = 4096;
+static_assert(sizeof(Ctrl) <= kCtrlBytes, "control block");
 constexpr uint64_t kHllBytes = kHllRegs * 4;
 constexpr uint64_t kMetaBytes = (uint64_t)kMaxFan * sizeof(PartMeta);
 constexpr uint64_t kCntBytes = (uint64_t)kMaxFan * 4 * kCntStride;  // counters, one 128-byte line each
@@ -212,6 +213,7 @@ struct agg_handle {
   uint32_t *d_pack = nullptr;
   uint64_t *d_arena = nullptr;
   uint64_t arena_cap_bytes = 0;
+  uint8_t *d_filter = nullptr;  // Pre-Partitioning: one filter byte per slot of the current level's tables
 
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // kernel timing on the handle's stream
   hipEvent_t ev2 = nullptr, ev3 = nullptr;  // a second pair, for the LDS engine's scatter
@@ -387,6 +389,10 @@ agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_
   // table bytes: the arena minus, at level 0 of the owner engine, its buffer area
   const uint64_t reserve = level == 0 ? h->owner_reserve : 0;
   uint64_t cap_bytes = h->arena_cap_bytes > reserve ? (h->arena_cap_bytes - reserve) / 256 * 256 : 0;
+  // Pre-Partitioning keeps a one-byte filter per slot after the tables (Sec. 4.3.4:
+  // o' = o + 1/b), so its slots cost W8 + 1 bytes
+  const bool filt = h->spec.policy == AGG_POLICY_PREPART;
+  if (filt) cap_bytes = cap_bytes > 512 ? (cap_bytes - 512) / (W8 + 1) * W8 / 256 * 256 : 0;
   // The estimate may be low.  A first batch of n records can hold up to n
   // groups: plan level 0 for at least min(n, what the budget holds at the
   // default load), so an underestimate does not leave the tables (and the
@@ -422,7 +428,7 @@ agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_
   uint64_t T = pl.F;
   uint64_t slots = slots_need;
   if (h->unlimited) {
-    const uint64_t need = (uint64_t)pl.F * slots * W8;
+    const uint64_t need = (uint64_t)pl.F * slots * (W8 + (filt ? 1 : 0)) + (filt ? 512 : 0);
     if (need + reserve > h->arena_cap_bytes) {
       // grow the library-owned pool (unlimited budget); the control block and
       // the sketch carry over (the side group accumulates across levels)
@@ -485,8 +491,9 @@ agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_
   }
   pl.arena_slots = base;
   pl.planned_spilled = pl.F - (uint32_t)T;
+  if (level == 0) h->st.table_slots_l0 = base;
   h->planned = true;
-  const uint64_t used = kOverhead + base * W8;
+  const uint64_t used = kOverhead + base * W8 + (filt ? round_up(base, 256) : 0);
   h->st.pool_high_water = std::max(h->st.pool_high_water, used);
   return AGG_OK;
 }
@@ -498,6 +505,12 @@ agg_status start_level(agg_handle *h) {
   HCK(h, launch_u32_fill(h->stream, h->d_cnt, (uint64_t)pl.F * kCntStride, 0));
   HCK(h, launch_u32_fill(h->stream, h->d_ovf, pl.F, 0));
   HCK(h, launch_table_init(h->stream, h->d_arena, pl.arena_slots, h->ks));
+  h->d_filter = nullptr;
+  if (h->spec.policy == AGG_POLICY_PREPART) {
+    // the per-slot filters follow the tables, all bits clear
+    h->d_filter = reinterpret_cast<uint8_t *>(h->d_arena) + round_up(pl.arena_slots * h->W8, 256);
+    HCK(h, launch_u32_fill(h->stream, reinterpret_cast<uint32_t *>(h->d_filter), (pl.arena_slots + 3) / 4, 0));
+  }
   HCK(h, launch_u64_set(h->stream, &h->d_ctrl->raw_ctr, 4, 0));  // raw_ctr, state_ctr, rows, any_ovf
   // the meta upload reads host memory: wait before the vector can change
   HCK(h, hipStreamSynchronize(h->stream));
@@ -523,8 +536,11 @@ KSpill spill_target(agg_handle *h, uint8_t *raw, uint8_t *state) {
 // written out as states, its table is released, and all its later records go
 // to the spill run.  With equal per-partition tables, the partition that hit
 // its limit is the fullest one, i.e. the victim the paper's rule picks.
-// Pre-Partitioning (Sec. 4.3.4): nothing to do -- the full table keeps its
-// groups, hits keep aggregating, misses keep spilling.
+// Pre-Partitioning (Sec. 4.3.4): the full table keeps its groups, hits keep
+// aggregating, misses keep spilling; its per-slot filter is built so that
+// later records of absent keys spill without probing the table.  (A partition
+// flagged because a probe hit the probe limit below its group limit can still
+// gain keys: it gets no filter.)
 agg_status handle_overflow(agg_handle *h) {
   if (h->h_ctrl->any_ovf == 0) return AGG_OK;
   LevelPlan &pl = h->plan;
@@ -555,6 +571,20 @@ agg_status handle_overflow(agg_handle *h) {
       if (pl.level == 0) h->st.partitions_spilled += 1;
     }
   }
+  if (h->spec.policy == AGG_POLICY_PREPART && h->d_filter) {
+    KLevel lv;
+    lv.level = pl.level;
+    lv.slot_shift = pl.fan_bits;
+    lv.seed_slot = pl.seed_slot;
+    for (uint32_t p : victims) {
+      PartMeta &m = pl.meta[p];
+      if (m.filt || m.nslots == 0 || h->h_scratch[kMaxFan + p] < m.cap) continue;
+      HCK(h, launch_filter_build(h->stream, h->d_arena, h->d_filter, m.base, m.nslots, h->ks, lv));
+      m.filt = 1;
+      HCK(h, hipMemcpyAsync(h->d_meta + p, &m, sizeof(PartMeta), hipMemcpyHostToDevice, h->stream));
+      h->st.partitions_filtered += 1;
+    }
+  }
   HCK(h, launch_u32_fill(h->stream, h->d_ovf, pl.F, 0));
   HCK(h, launch_u64_set(h->stream, &h->d_ctrl->any_ovf, 1, 0));
   HCK(h, hipStreamSynchronize(h->stream));
@@ -582,6 +612,7 @@ agg_status run_stream(agg_handle *h, const uint8_t *in, uint64_t n, int kind) {
     KSpill sp = spill_target(h, kind == 0 ? dst : nullptr, kind == 0 ? nullptr : dst);
     // level-0 raw records come from agg_consume, whose batch follows the records counted before it
     lv.rec_base = h->plan.level == 0 && kind == 0 ? h->st.records_in - n + off : ~0ULL;
+    lv.filter = h->d_filter;
     const bool preagg = h->preagg > 0 && h->plan.arena_slots < (1ull << 32);
     if (preagg) h->st.preagg = 1;
     HCK(h, hipEventRecord(h->ev0, h->stream));
@@ -1471,6 +1502,8 @@ agg_status finish_impl(agg_handle *h) {
   }
   s = read_ctrl(h);
   if (s) return s;
+  h->st.filter_rejects = h->h_ctrl->filter_rejects;
+  h->st.filter_false = h->h_ctrl->filter_false;
   s = append_side_rows(h);
   if (s) return s;
   h->st.groups_out = h->r_rows;
@@ -1591,7 +1624,14 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     h->sample_dups = h->h_ctrl->sample_dups;
     if (h->preagg < 0) h->preagg = ns >= 256 && h->h_ctrl->sample_dups * 20 > ns ? 1 : 0;
     h->hot_key = ns >= 256 && h->h_ctrl->sample_max * 50 > ns;
-    h->hot_n = h->hot_key ? (uint32_t)h->h_ctrl->sample_hot_n : 0;
+    h->hot_n = 0;
+    if (h->hot_key) {
+      // a skewed batch: its frequent keys from a larger sample (sorted in LDS)
+      HCK(h, launch_sample_hot(h->stream, (const uint8_t *)d_records, n, h->ks, h->d_ctrl));
+      s = read_ctrl(h);
+      if (s) return s;
+      h->hot_n = (uint32_t)h->h_ctrl->sample_hot_n;
+    }
     h->sample_sorted = ns >= 2 && h->h_ctrl->sample_unsorted == 0;
   }
   h->st.records_in += n;

@@ -32,7 +32,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 # the sources whose change invalidates a measured traffic figure
 KERNEL_SOURCES = ["csrc/aggx_kernels.hip", "csrc/aggx_device.h", "csrc/aggx_internal.h", "csrc/aggx_lds.hip",
-                  "csrc/aggx_owner.hip", "csrc/aggx_sorted.hip", "csrc/aggx_runtime.cpp"]
+                  "csrc/aggx_ldstab.h", "csrc/aggx_onchip.hip", "csrc/aggx_owner.hip", "csrc/aggx_sorted.hip",
+                  "csrc/aggx_runtime.cpp"]
 
 
 def sources_hash() -> str:
@@ -138,19 +139,71 @@ def summarize_trace(a) -> str:
                      f"{float(r['Percentage']):.2f} |")
     by_grid = {}
     with open(a.trace, newline="") as f:
-        for r in csv.DictReader(f):
-            if a.kernel not in r["Kernel_Name"]:
-                continue
-            g = int(r["Grid_Size_X"]) * int(r.get("Grid_Size_Y", 1)) * int(r.get("Grid_Size_Z", 1))
-            dt = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
-            by_grid.setdefault(g, []).append(dt)
-    lines += ["", f"Per-dispatch durations of `{a.kernel}` (End - Start), by grid size:", "",
+        rows = [r for r in csv.DictReader(f) if a.kernel in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    rows = rows[a.skip:]
+    if a.first:
+        rows = rows[: a.first]
+    for r in rows:
+        g = int(r["Grid_Size_X"]) * int(r.get("Grid_Size_Y", 1)) * int(r.get("Grid_Size_Z", 1))
+        dt = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+        by_grid.setdefault(g, []).append(dt)
+    which = f"dispatches {a.skip + 1}-{a.skip + len(rows)} in time order" if a.skip or a.first else "all dispatches"
+    lines += ["", f"Per-dispatch durations of `{a.kernel}` (End - Start, {which}), by grid size:", "",
               "| grid (threads) | dispatches | avg ms | min ms | max ms |", "|---|---|---|---|---|"]
     for g in sorted(by_grid, reverse=True):
         v = by_grid[g]
         lines.append(f"| {g} | {len(v)} | {sum(v) / len(v):.4f} | {min(v):.4f} | {max(v):.4f} |")
     if a.note:
         lines += ["", *a.note]
+    lines.append("")
+    return "\n".join(lines)
+
+
+def summarize_counters(a) -> str:
+    """Per-kernel sums of any counters over one or more `--pmc` runs of the same command
+    (each run a `*_counter_collection.csv`), with derived ratios for the SQ counters."""
+    tot = {}
+    durs = {}
+    for path in a.csv:
+        for r in csv.DictReader(open(path, newline="")):
+            name = r["Kernel_Name"].split("(")[0]
+            if not any(k in name for k in a.kernel):
+                continue
+            key = (path, int(r["Dispatch_Id"]))
+            tot.setdefault(name, {})
+            tot[name][r["Counter_Name"]] = tot[name].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            durs.setdefault(name, {})[key] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+    lines = [f"# Counters: {a.workload}", "", "Commands (repository root on the GPU host; "
+             "`cd /tmp && export TMPDIR=/tmp` first), one run per counter set:", "", "```", *a.command, "```", ""]
+    for name, c in tot.items():
+        d = durs[name]
+        lines += [f"## `{name}`", "", f"dispatches counted: {len(d)} (over {len(a.csv)} runs); "
+                  f"average duration under the profiler {sum(d.values()) / len(d):.3f} ms", "",
+                  "| counter | sum over the runs' dispatches |", "|---|---|"]
+        for k in sorted(c):
+            lines.append(f"| {k} | {c[k]:.4g} |")
+        derived = []
+        if c.get("SQ_WAVE_CYCLES") and "SQ_WAIT_ANY" in c:
+            derived.append(f"waiting share of wave time (SQ_WAIT_ANY / SQ_WAVE_CYCLES): {c['SQ_WAIT_ANY'] / c['SQ_WAVE_CYCLES']:.2f}")
+        if c.get("SQ_WAVE_CYCLES") and "SQ_WAIT_INST_LDS" in c:
+            derived.append(f"LDS-wait share (SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES): {c['SQ_WAIT_INST_LDS'] / c['SQ_WAVE_CYCLES']:.3f}")
+        if c.get("SQ_INSTS_LDS") and "SQ_LDS_BANK_CONFLICT" in c:
+            derived.append(f"LDS bank-conflict cycles per LDS instruction: {c['SQ_LDS_BANK_CONFLICT'] / c['SQ_INSTS_LDS']:.2f}")
+        if c.get("SQ_INSTS_LDS") and "SQ_LDS_ADDR_CONFLICT" in c:
+            derived.append(f"LDS address-conflict cycles per LDS instruction: {c['SQ_LDS_ADDR_CONFLICT'] / c['SQ_INSTS_LDS']:.2f}")
+        if c.get("SQ_WAVES") and "SQ_INSTS_VALU" in c:
+            derived.append(f"VALU instructions per wave: {c['SQ_INSTS_VALU'] / c['SQ_WAVES']:.4g}")
+        if "TCC_HIT_sum" in c and c.get("TCC_HIT_sum", 0) + c.get("TCC_MISS_sum", 0):
+            derived.append(f"L2 hit rate: {c['TCC_HIT_sum'] / (c['TCC_HIT_sum'] + c.get('TCC_MISS_sum', 0)):.3f}")
+        if "SQC_ICACHE_MISSES" in c and c.get("SQC_ICACHE_HITS"):
+            derived.append(f"instruction-cache miss rate: {c['SQC_ICACHE_MISSES'] / (c['SQC_ICACHE_HITS'] + c['SQC_ICACHE_MISSES']):.2e}")
+        if derived:
+            lines += ["", *[f"* {x}" for x in derived]]
+        lines.append("")
+    if a.note:
+        lines += [*a.note, ""]
+    lines.append(f"sources_sha256: {sources_hash()}")
     lines.append("")
     return "\n".join(lines)
 
@@ -175,12 +228,21 @@ def main(argv=None):
     t.add_argument("--trace", required=True)
     t.add_argument("--kernel", required=True)
     t.add_argument("--top", type=int, default=10)
+    t.add_argument("--skip", type=int, default=0, help="leave out the kernel's first N dispatches (time order)")
+    t.add_argument("--first", type=int, default=0, help="then use only the next N dispatches")
     t.add_argument("--workload", default="")
     t.add_argument("--command", action="append", default=[])
     t.add_argument("--note", action="append", default=[])
     t.add_argument("--out", required=True)
+    c = sub.add_parser("counters", help="per-kernel sums of --pmc counter runs")
+    c.add_argument("--csv", action="append", required=True, help="a *_counter_collection.csv (repeat per run)")
+    c.add_argument("--kernel", action="append", required=True, help="substring of a kernel name (repeatable)")
+    c.add_argument("--workload", default="")
+    c.add_argument("--command", action="append", default=[])
+    c.add_argument("--note", action="append", default=[])
+    c.add_argument("--out", required=True)
     a = ap.parse_args(argv)
-    text = summarize_pmc(a) if a.cmd == "pmc" else summarize_trace(a)
+    text = {"pmc": summarize_pmc, "trace": summarize_trace, "counters": summarize_counters}[a.cmd](a)
     with open(a.out, "w") as f:
         f.write(text)
     print(text)

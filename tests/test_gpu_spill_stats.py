@@ -57,3 +57,23 @@ def test_prepartitioning_spill_counters_follow_the_models(d, c, budget_mib):
     got = st["first_full_record"]
     print(f"  K={K} ({K / d:.3f} of the keys), first full at {got} records, I_raw {want:.0f}", flush=True)
     assert abs(got - want) <= 0.03 * want
+
+
+def test_prepartitioning_slot_filter_false_positives():
+    """Sec. 4.3.4: once a table is full, Pre-Partitioning consults a one-byte filter per slot
+    before probing it, and a record whose key the filter shows absent spills with no probe.
+    The rows match the oracle, and the share of absent keys' records that pass the filter (its
+    false positives, the alpha of Sec. 5.3.4) matches 1 - (1 - 1/(8H))^K within 5%, with K the
+    resident groups and H the table slots (every partition's table full)."""
+    d, c = 400_000, 10
+    rec = _equal_counts(workloads.SEED_BASE + 71, d, c)
+    print("case: slot filter", flush=True)
+    k, cols, st = run_lib(rec, 16, SPEC["keys"], SPEC["aggs"], budget=6 * MIB, est_groups=d, engine="tables",
+                          policy="prepart", batches=20)
+    check_against_oracle(rec, SPEC, k, cols, "slot filter")
+    assert st["partitions_filtered"] >= st["partitions"] and st["filter_rejects"] > 0
+    K, H = st["resident_groups_l0"], st["table_slots_l0"]
+    got = st["filter_false"] / (st["filter_rejects"] + st["filter_false"])
+    want = oracle.slot_filter_false_positive(K, H)
+    print(f"  K={K} H={H} filter passes of absent keys {got:.4f}, model {want:.4f}", flush=True)
+    assert abs(got - want) <= 0.05 * want

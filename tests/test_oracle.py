@@ -294,6 +294,25 @@ def test_spilled_fraction_against_simulation():
     assert oracle.spilled_fraction(G, G) == 0.0 and oracle.spilled_fraction(2 * G, G) == 0.0
 
 
+def test_slot_filter_false_positive_against_simulation():
+    """Secs. 4.3.4 / 5.3.4: a one-byte filter per slot, each key setting one of the 8 bits of its home
+    slot's byte.  Simulated: K keys with uniform home slots and bits set their bits; absent keys
+    (their own uniform home slot and bit) test theirs.  The share that find their bit set matches
+    1 - (1 - 1/(8H))^K within 2%, at several loads K/H; also the closed forms at K = 0 and K = 1."""
+    rng = np.random.default_rng(59)
+    H = 50_000
+    for load in (0.3, 0.7, 0.9, 1.5):
+        K = int(load * H)
+        filt = np.zeros(H, dtype=np.uint8)
+        np.bitwise_or.at(filt, rng.integers(0, H, size=K), (1 << rng.integers(0, 8, size=K)).astype(np.uint8))
+        q = 400_000
+        hit = (filt[rng.integers(0, H, size=q)] & (1 << rng.integers(0, 8, size=q)).astype(np.uint8)) != 0
+        model = oracle.slot_filter_false_positive(K, H)
+        assert abs(hit.mean() - model) / model < 0.02, (load, hit.mean(), model)
+    assert oracle.slot_filter_false_positive(0, H) == 0.0
+    assert abs(oracle.slot_filter_false_positive(1, H) - 1.0 / (8 * H)) < 1e-15
+
+
 # ---- planted mistakes: each mutant of the oracle must fail one of the pins above --------------------
 
 MUTANTS = {
