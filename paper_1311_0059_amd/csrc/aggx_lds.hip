@@ -206,12 +206,14 @@ __device__ __forceinline__ void rec_store(uint8_t *dst, uint32_t vec, const uint
   for (int j = 0; j < RW / 2; ++j) reinterpret_cast<uint2 *>(dst)[j] = make_uint2(w[2 * j], w[2 * j + 1]);
 }
 
-// Word idx of a record held in registers (idx < RW; a select chain, not an indexed access).
+// Word idx of a record held in registers (idx < RW).  Masks rather than a
+// select chain: the compiler turns a select chain on a uniform index into an
+// indexed access, which puts the record in scratch memory.
 template <int RW>
 __device__ __forceinline__ uint32_t rec_word(const uint32_t *w, uint32_t idx) {
-  uint32_t r = w[0];
+  uint32_t r = 0;
 #pragma unroll
-  for (int j = 1; j < RW; ++j) r = idx == (uint32_t)j ? w[j] : r;
+  for (int j = 0; j < RW; ++j) r |= w[j] & (0u - (uint32_t)(idx == (uint32_t)j));
   return r;
 }
 
