@@ -70,8 +70,12 @@ typedef struct agg_fn {
 typedef enum agg_policy {
   AGG_POLICY_DESTAGE = 0,  /* Dynamic Destaging: a full partition is spilled whole (its grouping states
                               plus every later record of it, raw) at the next synchronisation point */
-  AGG_POLICY_PREPART = 1   /* Pre-Partitioning: a full partition keeps its groups; later records whose
+  AGG_POLICY_PREPART = 1,  /* Pre-Partitioning: a full partition keeps its groups; later records whose
                               key is resident are aggregated, the others are spilled raw */
+  AGG_POLICY_HASHSORT = 2  /* Hash-Sort (Sec. 4.2): one hash table fills the budget; each time it is full
+                              its groups are written out as a run sorted by slot (hash) order and it is
+                              emptied; the runs are then merged range by range and grouped.  Engine AUTO
+                              or TABLES only.  (Hybrid-hash runs that do not shrink fall back to it.) */
 } agg_policy;
 
 /* Aggregation engines (all compute the same rows). */
@@ -210,6 +214,12 @@ typedef struct agg_stats {
   uint32_t partitions_filtered;  /* partitions whose filter was built (all levels) */
   uint32_t reserved_stats2;
   uint64_t table_slots_l0;      /* HBM tables: slots of the level-0 tables (the paper's H, summed) */
+  /* Hash-Sort (Sec. 4.2), as the policy or as the fallback of Sec. 4.3 Phase 2 for a run that kept more
+   * than 80% of its input or a recursion deeper than a sort-based pass structure (two levels here): */
+  uint64_t hashsort_runs;       /* sorted runs written (a full table each, plus the last) */
+  uint64_t hashsort_windows;    /* hash ranges merged: each range's states from every run, grouped in a table */
+  uint32_t hashsort_fallbacks;  /* recursion levels handed to Hash-Sort by the fallback rule */
+  uint32_t reserved_stats3;
 } agg_stats;
 
 /* Start one GROUP BY query (Sec. 3.1) under the memory budget M of Sec. 3.2

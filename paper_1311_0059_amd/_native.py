@@ -13,7 +13,7 @@ STATUS = {0: "AGG_OK", -1: "AGG_E_INVALID", -2: "AGG_E_BUDGET", -3: "AGG_E_DEVIC
           -5: "AGG_E_NOMEM", -6: "AGG_E_INTERNAL"}
 TYPES = {"u32": 0, "u64": 1, "i32": 2, "i64": 3}
 OPS = {"COUNT": 0, "SUM": 1, "MIN": 2, "MAX": 3}
-POLICIES = {"destage": 0, "prepart": 1}
+POLICIES = {"destage": 0, "prepart": 1, "hashsort": 2}
 
 
 class Field(ctypes.Structure):
@@ -98,6 +98,10 @@ class Stats(ctypes.Structure):
         ("partitions_filtered", ctypes.c_uint32),
         ("reserved_stats2", ctypes.c_uint32),
         ("table_slots_l0", ctypes.c_uint64),
+        ("hashsort_runs", ctypes.c_uint64),
+        ("hashsort_windows", ctypes.c_uint64),
+        ("hashsort_fallbacks", ctypes.c_uint32),
+        ("reserved_stats3", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libaggx.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["aggx_kernels.hip", "aggx_lds.hip", "aggx_owner.hip", "aggx_sorted.hip", "aggx_batch.hip", "aggx_onchip.hip", "aggx_noalloc.hip", "aggx_runtime.cpp", "aggx_batch_rt.cpp", "aggx_server.cpp"]
+SOURCES = ["aggx_kernels.hip", "aggx_lds.hip", "aggx_owner.hip", "aggx_sorted.hip", "aggx_batch.hip", "aggx_onchip.hip", "aggx_noalloc.hip", "aggx_hashsort.hip", "aggx_runtime.cpp", "aggx_batch_rt.cpp", "aggx_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950", "-mcode-object-version=5",
          # no packed fp32 instructions anywhere (this library has no fp32 math)

@@ -201,6 +201,18 @@ hipError_t launch_sample_dups(hipStream_t s, const uint8_t *in, uint64_t n, cons
 // seen at least kHotMin times, most frequent first, at most kMaxHot (ctrl->sample_hot).
 hipError_t launch_sample_hot(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, Ctrl *ctrl);
 hipError_t sample_hot_setup();
+// Hash-Sort's sorted run generation (aggx_hashsort.hip): the groups of a
+// one-partition table of `nslots` slots (< 2^32), written to `out` (device-visible,
+// 1 + na words a state) in the order of hs = fmix64(key ^ seed).  `counts` and
+// `offsets` take hs_tiles(nslots) and hs_tiles(nslots) + 1 entries; offsets[tiles]
+// ends as the number of states written.
+hipError_t launch_hs_emit(hipStream_t s, const uint64_t *arena, uint64_t nslots, const KSpec &ks, uint64_t seed,
+                          uint32_t *counts, unsigned long long *offsets, uint64_t *out);
+uint64_t hs_tiles(uint64_t nslots);
+// The slot hash seed of a level's one-partition tables (hs = fmix64(key ^ seed)), and
+// that hash on the host.
+uint64_t hs_seed(uint32_t level, uint64_t level_slot_seed);
+uint64_t hs_host(uint64_t key, uint64_t seed);
 hipError_t launch_flush(hipStream_t s, const uint64_t *arena, uint64_t nslots, const KSpec &ks, uint64_t *out_keys,
                         const OutCols &out_cols, uint64_t out_cap, Ctrl *ctrl);
 hipError_t launch_u64_set(hipStream_t s, unsigned long long *p, uint32_t n, unsigned long long v);

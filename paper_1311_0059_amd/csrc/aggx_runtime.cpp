@@ -250,6 +250,16 @@ struct agg_handle {
   double l0_G = 0.0;     // estimated distinct keys of what level 0 spilled
   agg_stats st{};
   uint64_t lvl_in = 0;  // records + states fed to the current level (for the shrink guard)
+  // Hash-Sort (the policy, or the fallback of a recursion level): its phase-1 table,
+  // its sorted runs (states, with their host addresses for the range searches) and
+  // two regions for what a launch that found the table full spilled
+  bool hs_on = false;
+  uint32_t hs_level = 0;
+  uint64_t hs_seed_v = 0;
+  uint64_t hs_slots = 0;
+  RunSet hs_runs;
+  std::vector<const uint8_t *> hs_run_host;
+  RunSet hs_tmp[2];
 };
 
 namespace {
@@ -296,7 +306,9 @@ agg_status validate(const agg_spec *s) {
   if (wide && s->record_bytes % 8) return AGG_E_INVALID;
   if (s->fanout_bits > (uint32_t)kMaxFanBits) return AGG_E_INVALID;
   if (s->load_pct != 0 && (s->load_pct < 10 || s->load_pct > 95)) return AGG_E_INVALID;
-  if (s->policy > AGG_POLICY_PREPART || s->preagg > 2 || s->engine > AGG_ENGINE_ONCHIP) return AGG_E_INVALID;
+  if (s->policy > AGG_POLICY_HASHSORT || s->preagg > 2 || s->engine > AGG_ENGINE_ONCHIP) return AGG_E_INVALID;
+  if (s->policy == AGG_POLICY_HASHSORT && s->engine != AGG_ENGINE_AUTO && s->engine != AGG_ENGINE_TABLES)
+    return AGG_E_INVALID;
   if (s->device_workspace && (s->workspace_bytes < s->budget_bytes || ((uintptr_t)s->device_workspace & 255)))
     return AGG_E_BUDGET;
   if (s->device_workspace && s->budget_bytes == 0) return AGG_E_INVALID;
@@ -1404,10 +1416,283 @@ agg_status hybrid_pass(agg_handle *h, uint32_t depth, double G, uint32_t consume
   return flush_level(h, 0.0);
 }
 
+// ---- Hash-Sort (Sec. 4.2) ----------------------------------------------------
+// Phase 1, sorted run generation: one table over the whole budget (one
+// partition, no digit), fed by the update kernel.  A launch some of whose
+// records found the table full (their keys closed out, the records spilled)
+// ends with the table full: its groups are written as a run in hs order
+// (k_hs_emit), the table is emptied, and the spilled records are fed again.  A
+// launch takes at most as many records as the table holds groups, so those fit
+// the emptied table.  If everything fits, the table's groups are the rows.
+// Phase 2, merge and group: the runs are cut into ranges of hs; the states of a
+// range, found in every run by binary search, go through a table sized for them
+// and are flushed as rows, range after range in hs order.  (The paper merges the
+// runs with a loser tree, one group at a time; on the GPU each range is grouped
+// by one launch per run and one flush.)
+constexpr double kHsLoad = 0.7;  // groups per slot allowed in the phase-1 table (phase 2's tables stay below)
+constexpr uint32_t kSortLevels = 2;  // levels of a sort-based pass structure here (see finish_impl)
+
+uint64_t hs_aux_bytes(uint64_t nslots) {
+  const uint64_t t = hs_tiles(nslots);
+  return round_up(4 * t, 256) + round_up(8 * (t + 1), 256);
+}
+
+// Point the level plan at one table of `nslots` slots for up to `cap` groups, and clear it.
+agg_status hs_table(agg_handle *h, uint64_t nslots, uint64_t cap) {
+  LevelPlan &pl = h->plan;
+  pl = LevelPlan();
+  pl.level = h->hs_level;
+  pl.fan_bits = 0;
+  pl.F = 1;
+  pl.digit_shift = 0;
+  pl.seed_slot = level_seed(h->hs_level);
+  pl.arena_slots = nslots;
+  pl.meta.resize(1);
+  PartMeta &m = pl.meta[0];
+  m.base = 0;
+  m.nslots = (uint32_t)nslots;
+  m.cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap, nslots - 1));
+  m.spilled = 0;
+  m.filt = 0;
+  h->planned = true;
+  h->d_filter = nullptr;
+  HCK(h, hipMemcpyAsync(h->d_meta, pl.meta.data(), sizeof(PartMeta), hipMemcpyHostToDevice, h->stream));
+  HCK(h, launch_u32_fill(h->stream, h->d_cnt, kCntStride, 0));
+  HCK(h, launch_u32_fill(h->stream, h->d_ovf, 1, 0));
+  HCK(h, launch_table_init(h->stream, h->d_arena, nslots, h->ks));
+  HCK(h, launch_u64_set(h->stream, &h->d_ctrl->raw_ctr, 4, 0));  // raw_ctr, state_ctr, rows, any_ovf
+  HCK(h, hipStreamSynchronize(h->stream));  // the meta upload reads host memory
+  return AGG_OK;
+}
+
+// Start Hash-Sort at `level`: the largest table whose emit scratch fits the arena
+// (unlimited budget: a table for G groups).
+agg_status hs_begin(agg_handle *h, uint32_t level, double G) {
+  const uint64_t W8 = h->W8;
+  uint64_t S;
+  if (h->unlimited) {
+    S = (uint64_t)std::ceil(std::max(1.0, G) / kHsLoad) + 64;
+    S = std::min<uint64_t>(S, 0xfff00000ull);
+    agg_status s = grow_unlimited_pool(h, S * W8 + 256 + hs_aux_bytes(S));
+    if (s) return s;
+  } else {
+    S = std::min<uint64_t>(h->arena_cap_bytes / (W8 + 1), 0xfff00000ull);
+    while (S > 64 && round_up(S * W8, 256) + hs_aux_bytes(S) > h->arena_cap_bytes) S -= 64;
+  }
+  if (S < 64) return AGG_E_BUDGET;
+  h->hs_on = true;
+  h->hs_level = level;
+  h->hs_seed_v = hs_seed(level, level_seed(level));
+  h->hs_slots = S;
+  h->st.pool_high_water = std::max(h->st.pool_high_water, kOverhead + round_up(S * W8, 256) + hs_aux_bytes(S));
+  return hs_table(h, S, (uint64_t)std::floor(S * kHsLoad));
+}
+
+// Write the table's groups as the next sorted run and empty the table.
+agg_status hs_emit_run(agg_handle *h) {
+  const uint64_t S = h->plan.arena_slots, W8 = h->W8;
+  HCK(h, hipMemcpyAsync(h->h_scratch, h->d_cnt, 4, hipMemcpyDeviceToHost, h->stream));
+  HCK(h, hipStreamSynchronize(h->stream));
+  const uint64_t G = h->h_scratch[0];
+  if (G) {
+    uint8_t *dst = nullptr;
+    if (!h->hs_runs.reserve(G * W8, &dst)) return AGG_E_NOMEM;
+    uint8_t *aux = reinterpret_cast<uint8_t *>(h->d_arena) + round_up(S * W8, 256);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(aux);
+    auto *offsets = reinterpret_cast<unsigned long long *>(aux + round_up(4 * hs_tiles(S), 256));
+    HCK(h, launch_hs_emit(h->stream, h->d_arena, S, h->ks, h->hs_seed_v, counts, offsets,
+                          reinterpret_cast<uint64_t *>(dst)));
+    HCK(h, hipMemcpyAsync(h->h_scratch, offsets + hs_tiles(S), 8, hipMemcpyDeviceToHost, h->stream));
+    HCK(h, hipStreamSynchronize(h->stream));
+    uint64_t written = 0;
+    memcpy(&written, h->h_scratch, 8);
+    if (written != G) return AGG_E_INTERNAL;
+    const PinnedSeg &seg = h->hs_runs.segs.back();
+    h->hs_run_host.push_back(seg.host + (dst - seg.dev));
+    h->hs_runs.commit(dst, G, W8, true);
+    h->st.hashsort_runs += 1;
+    h->st.states_spilled += G;
+    h->st.bytes_spilled_d2h += G * W8;
+  }
+  return hs_table(h, S, (uint64_t)std::floor(S * kHsLoad));
+}
+
+// Phase 1: feed raw records (kind 0) or states (kind 1) to the table.
+agg_status hs_feed(agg_handle *h, int kind, const uint8_t *in, uint64_t n) {
+  const uint64_t in_bytes = kind == 0 ? h->ks.rb : h->W8;
+  const uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(kChunkBytes / in_bytes, h->plan.meta[0].cap));
+  KLevel lv;
+  lv.level = h->hs_level;
+  lv.digit_shift = 0;
+  lv.fan_mask = 0;
+  lv.slot_shift = 0;
+  lv.seed_slot = level_seed(h->hs_level);
+  lv.rec_base = ~0ULL;
+  lv.filter = nullptr;
+  const bool preagg = kind == 0 && h->preagg > 0 && h->hs_slots < (1ull << 32);
+  for (uint64_t off = 0; off < n; off += chunk) {
+    const uint8_t *src = in + off * in_bytes;
+    uint64_t cnt = std::min(chunk, n - off);
+    int t = 0;
+    while (cnt) {
+      uint8_t *dst = nullptr;
+      if (!h->hs_tmp[t].reserve(cnt * in_bytes, &dst)) return AGG_E_NOMEM;
+      HCK(h, launch_u64_set(h->stream, kind == 0 ? &h->d_ctrl->raw_ctr : &h->d_ctrl->state_ctr, 1, 0));
+      KSpill sp = spill_target(h, kind == 0 ? dst : nullptr, kind == 0 ? nullptr : dst);
+      HCK(h, hipEventRecord(h->ev0, h->stream));
+      HCK(h, launch_update(h->stream, kind, src, cnt, h->ks, lv, h->d_meta, h->d_cnt, h->d_ovf, h->d_arena,
+                           h->d_ctrl, sp, preagg));
+      HCK(h, hipEventRecord(h->ev1, h->stream));
+      agg_status s = read_ctrl(h);
+      if (s) return s;
+      float ms = 0.f;
+      HCK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      h->st.update_launches += 1;
+      h->st.update_records += cnt;
+      h->st.update_ms += ms;
+      const uint64_t got = kind == 0 ? h->h_ctrl->raw_ctr : h->h_ctrl->state_ctr;
+      if (got == 0 && h->h_ctrl->any_ovf == 0) break;
+      // the table is full: write it out, then feed the spilled ones again
+      HCK(h, hipMemcpyAsync(h->h_scratch, h->d_cnt, 4, hipMemcpyDeviceToHost, h->stream));
+      HCK(h, hipStreamSynchronize(h->stream));
+      if (got == cnt && h->h_scratch[0] == 0) return AGG_E_INTERNAL;  // nothing fit an empty table
+      s = hs_emit_run(h);
+      if (s) return s;
+      src = dst;
+      cnt = got;
+      t ^= 1;
+    }
+    h->hs_tmp[0].release();
+    h->hs_tmp[1].release();
+  }
+  return AGG_OK;
+}
+
+// First index of run r whose hs is >= x.
+uint64_t hs_lower_bound(const agg_handle *h, size_t r, uint64_t x) {
+  const uint64_t *st = reinterpret_cast<const uint64_t *>(h->hs_run_host[r]);
+  const uint64_t W = 1 + h->ks.na;
+  uint64_t lo = 0, hi = h->hs_runs.state[r].count;
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (hs_host(st[mid * W], h->hs_seed_v) < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Phase 2 for the hs range [lo, hi) (to_end: [lo, 2^64)): group its states from every run, flush them as rows.
+agg_status hs_range(agg_handle *h, uint64_t lo, uint64_t hi, bool to_end) {
+  const size_t R = h->hs_runs.state.size();
+  const uint64_t W8 = h->W8, cap_w = (uint64_t)std::floor(h->hs_slots * kHsLoad);
+  std::vector<std::pair<uint64_t, uint64_t>> seg(R);
+  uint64_t n_w = 0;
+  for (size_t r = 0; r < R; ++r) {
+    seg[r].first = hs_lower_bound(h, r, lo);
+    seg[r].second = to_end ? h->hs_runs.state[r].count : hs_lower_bound(h, r, hi);
+    n_w += seg[r].second - seg[r].first;
+  }
+  if (n_w == 0) return AGG_OK;
+  const auto split = [&]() -> agg_status {
+    const uint64_t width = to_end ? (0ULL - lo) : hi - lo;  // 2^64 - lo wraps to 0 only for lo = 0
+    const uint64_t mid = lo + (to_end && lo == 0 ? (1ULL << 63) : width / 2);
+    if (mid == lo) return AGG_E_INTERNAL;  // one hash value: at most one state per run
+    agg_status s = hs_range(h, lo, mid, false);
+    return s ? s : hs_range(h, mid, hi, to_end);
+  };
+  if (n_w > cap_w) return split();
+  const uint64_t slots = std::min<uint64_t>(h->hs_slots, round_up((uint64_t)std::ceil(n_w / kHsLoad) + 64, 64));
+  agg_status s = hs_table(h, slots, n_w + 1);
+  if (s) return s;
+  uint8_t *dst = nullptr;  // states of keys that found no slot within the probe limit (not expected)
+  if (!h->hs_tmp[0].reserve(n_w * W8, &dst)) return AGG_E_NOMEM;
+  KLevel lv;
+  lv.level = h->hs_level;
+  lv.digit_shift = 0;
+  lv.fan_mask = 0;
+  lv.slot_shift = 0;
+  lv.seed_slot = level_seed(h->hs_level);
+  lv.rec_base = ~0ULL;
+  lv.filter = nullptr;
+  HCK(h, hipEventRecord(h->ev0, h->stream));
+  for (size_t r = 0; r < R; ++r) {
+    const uint64_t c = seg[r].second - seg[r].first;
+    if (c == 0) continue;
+    HCK(h, launch_update(h->stream, 1, h->hs_runs.state[r].dev + seg[r].first * W8, c, h->ks, lv, h->d_meta,
+                         h->d_cnt, h->d_ovf, h->d_arena, h->d_ctrl, spill_target(h, nullptr, dst), false));
+    h->st.update_launches += 1;
+    h->st.update_records += c;
+  }
+  HCK(h, hipEventRecord(h->ev1, h->stream));
+  s = read_ctrl(h);
+  if (s) return s;
+  float ms = 0.f;
+  HCK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  h->st.update_ms += ms;
+  h->hs_tmp[0].release();
+  if (h->h_ctrl->state_ctr || h->h_ctrl->any_ovf) return split();  // a probe ran out: smaller ranges
+  h->st.bytes_reloaded_h2d += n_w * W8;
+  s = flush_level(h, 0.0);
+  if (s) return s;
+  h->st.hashsort_windows += 1;
+  return AGG_OK;
+}
+
+// The end of Hash-Sort: the table is flushed as rows when no run was written;
+// else it becomes the last run and the runs are merged range by range.
+agg_status hs_finish(agg_handle *h) {
+  if (h->hs_runs.empty()) {
+    agg_status s = flush_level(h, 0.0);
+    if (s) return s;
+  } else {
+    agg_status s = hs_emit_run(h);
+    if (s) return s;
+    const uint64_t cap_w = (uint64_t)std::floor(h->hs_slots * kHsLoad);
+    if (cap_w < h->hs_runs.state.size()) return AGG_E_BUDGET;  // a range must hold one state of every run
+    const uint64_t nw = std::max<uint64_t>(1, (uint64_t)std::ceil((double)h->hs_runs.n_state / (0.8 * cap_w)));
+    for (uint64_t j = 0; j < nw; ++j) {
+      const uint64_t lo = (uint64_t)(((unsigned __int128)j << 64) / nw);
+      const uint64_t hi = (uint64_t)(((unsigned __int128)(j + 1) << 64) / nw);
+      s = hs_range(h, lo, hi, j + 1 == nw);
+      if (s) return s;
+    }
+  }
+  h->hs_runs.release();
+  h->hs_run_host.clear();
+  h->hs_on = false;
+  return AGG_OK;
+}
+
+// The fallback: a recursion level's run set by Hash-Sort instead of another hybrid-hash level.
+agg_status hs_run_set(agg_handle *h, uint32_t depth, double G, const RunSet &in) {
+  agg_status s = hs_begin(h, depth, G);
+  if (s) return s;
+  for (const auto &pc : in.state) {
+    s = hs_feed(h, 1, pc.dev, pc.count);
+    if (s) return s;
+  }
+  for (const auto &pc : in.raw) {
+    s = hs_feed(h, 0, pc.dev, pc.count);
+    if (s) return s;
+  }
+  return hs_finish(h);
+}
+
 // Level 0 after the last batch: flush the resident tables to rows (their groups
 // are final: a resident key never spilled a record) and estimate the distinct
 // keys of what was spilled.
 agg_status finish_level0(agg_handle *h) {
+  if (h->hs_on && h->hs_level == 0) {
+    // Hash-Sort as the policy: its rows are all final once its runs are merged
+    const bool runs = !h->hs_runs.empty();
+    agg_status s = hs_finish(h);
+    if (s) return s;
+    h->st.resident_groups_l0 = h->r_rows;
+    h->st.levels = runs ? 2 : 1;
+    h->l0_G = 0.0;
+    h->l0_done = true;
+    return AGG_OK;
+  }
   const bool rows_direct = h->engine == 2 || h->engine == 4;  // level 0 wrote its rows without tables
   if (!h->planned && !rows_direct) {
     agg_status s = make_plan(h, 0, h->spec.est_groups ? (double)h->spec.est_groups : 1.0, 0);
@@ -1446,6 +1731,12 @@ agg_status finish_impl(agg_handle *h) {
   const double cap_groups = h->unlimited ? 1e300 : (double)h->arena_cap_bytes * lam / h->W8;
   uint32_t consumed = h->used_bits;
   uint32_t depth = 0;
+  // The fallback of Sec. 4.3 (Phase 2): a run that kept more than 80% of the input
+  // it was partitioned from, or a recursion deeper than a sort-based pass structure
+  // would go, is aggregated by Hash-Sort instead.  Here all of a level's spill is
+  // one run, and a sort-based pass structure takes two levels (run generation, then
+  // one merge of all runs), so the third level is the deepest hybrid-hash one.
+  bool use_hs = (double)(h->next.n_raw + h->next.n_state) > 0.8 * (double)h->st.records_in;
   // Phase 2: the spilled partitions are re-aggregated, one level at a time
   while (!h->next.empty()) {
     if (++depth >= AGG_MAX_LEVELS || consumed >= 64) return AGG_E_INTERNAL;
@@ -1454,6 +1745,15 @@ agg_status finish_impl(agg_handle *h) {
     const uint64_t fed = in.n_raw + in.n_state;
     const uint64_t fed_bytes = in.n_raw * h->ks.rb + in.n_state * h->W8;
     G = std::max(1.0, G * 1.05);
+    if (use_hs || depth >= kSortLevels) {
+      h->st.hashsort_fallbacks += 1;
+      s = hs_run_set(h, depth, G, in);
+      h->st.bytes_reloaded_h2d += fed_bytes;
+      in.release();
+      if (s) return s;
+      h->st.levels = depth + 1;
+      break;  // Hash-Sort spills nothing to a next level
+    }
     HCK(h, launch_u32_fill(h->stream, h->d_hll, kHllRegs, 0));  // sketch of what this level spills
     uint32_t used = 0;
     if (G <= 0.8 * cap_groups || consumed + 2 > 64) {
@@ -1493,7 +1793,10 @@ agg_status finish_impl(agg_handle *h) {
     in.release();
     if (s) return s;
     const uint64_t out = h->next.n_raw + h->next.n_state;
-    if ((double)out > 0.8 * (double)fed) h->st.guard_trips += 1;
+    if ((double)out > 0.8 * (double)fed) {
+      h->st.guard_trips += 1;
+      use_hs = true;
+    }
     if (!h->next.empty()) {
       G = read_hll(h, &s);
       if (s) return s;
@@ -1635,6 +1938,17 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     h->sample_sorted = ns >= 2 && h->h_ctrl->sample_unsorted == 0;
   }
   h->st.records_in += n;
+  if (h->spec.policy == AGG_POLICY_HASHSORT) {
+    // Hash-Sort (Sec. 4.2): every batch goes through its one table
+    if (!h->hs_on) {
+      h->engine = 1;
+      h->st.engine = 1;
+      h->st.partitions = 1;
+      agg_status s = hs_begin(h, 0, h->spec.est_groups ? (double)h->spec.est_groups : (double)n);
+      if (s) return s;
+    }
+    return hs_feed(h, 0, (const uint8_t *)d_records, n);
+  }
   if (h->engine == 0 &&
       (h->spec.engine == AGG_ENGINE_SORTED || (h->spec.engine == AGG_ENGINE_AUTO && h->sample_sorted))) {
     bool applied = false;
@@ -1750,6 +2064,9 @@ void agg_destroy(agg_handle *h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   h->next.release();
+  h->hs_runs.release();
+  h->hs_tmp[0].release();
+  h->hs_tmp[1].release();
   if (h->own_pool && h->pool) dev_put(h->pool, h->pool_bytes);
   if (h->r_block) dev_put(h->r_block, h->r_block_bytes);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
