@@ -68,8 +68,10 @@ typedef struct agg_fn {
 
 /* Spill policies once a partition's table is full (Sec. 4.3.3, 4.3.4). */
 typedef enum agg_policy {
-  AGG_POLICY_DESTAGE = 0,  /* Dynamic Destaging: a full partition is spilled whole (its grouping states
-                              plus every later record of it, raw) at the next synchronisation point */
+  AGG_POLICY_DESTAGE = 0,  /* Dynamic Destaging (Sec. 4.3.3): all partitions start resident on a pool of
+                              memory; a full partition's table grows from the pool, and while the pool
+                              is short the largest resident partition is spilled whole (its grouping
+                              states plus every later record of it, raw) and its memory recycled */
   AGG_POLICY_PREPART = 1,  /* Pre-Partitioning: a full partition keeps its groups; later records whose
                               key is resident are aggregated, the others are spilled raw */
   AGG_POLICY_HASHSORT = 2  /* Hash-Sort (Sec. 4.2): one hash table fills the budget; each time it is full
@@ -219,7 +221,12 @@ typedef struct agg_stats {
   uint64_t hashsort_runs;       /* sorted runs written (a full table each, plus the last) */
   uint64_t hashsort_windows;    /* hash ranges merged: each range's states from every run, grouped in a table */
   uint32_t hashsort_fallbacks;  /* recursion levels handed to Hash-Sort by the fallback rule */
-  uint32_t reserved_stats3;
+  /* Dynamic Destaging (Sec. 4.3.3) with a limited budget: every partition starts resident with a table
+   * from a pool of frames; a table that fills gets one twice as large, the largest resident partition
+   * being spilled (its frames recycled) while the pool has no room; the records that found a grown
+   * table full are fed again. */
+  uint32_t partitions_grown;    /* tables that grew */
+  uint64_t records_refed;       /* records (or states) fed again after their tables grew */
 } agg_stats;
 
 /* Start one GROUP BY query (Sec. 3.1) under the memory budget M of Sec. 3.2

@@ -101,7 +101,8 @@ class Stats(ctypes.Structure):
         ("hashsort_runs", ctypes.c_uint64),
         ("hashsort_windows", ctypes.c_uint64),
         ("hashsort_fallbacks", ctypes.c_uint32),
-        ("reserved_stats3", ctypes.c_uint32),
+        ("partitions_grown", ctypes.c_uint32),
+        ("records_refed", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:

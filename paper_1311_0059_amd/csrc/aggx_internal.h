@@ -222,6 +222,17 @@ hipError_t launch_gather_u32(hipStream_t s, const uint32_t *src, uint32_t stride
 // bit (hs & 7) of the byte of its home slot (the slot its probe starts from).
 hipError_t launch_filter_build(hipStream_t s, const uint64_t *arena, uint8_t *filter, uint64_t base, uint32_t nslots,
                                const KSpec &ks, const KLevel &lv);
+// Dynamic Destaging's growth (Sec. 4.3.3): the groups of a partition's table
+// moved into a larger, empty one.  One descriptor per table; `fail` is set when a
+// key found no slot within the probe limit (the old table is then still whole).
+struct MigDesc {
+  uint64_t old_base, new_base;
+  uint32_t old_n, new_n;
+  uint32_t fail, pad;
+};
+constexpr uint32_t kMigMax = 512;  // descriptors per launch (they sit in the 16 KB pack area)
+hipError_t launch_migrate(hipStream_t s, uint64_t *arena, MigDesc *descs, uint32_t n, const KSpec &ks,
+                          const KLevel &lv);
 hipError_t launch_extract(hipStream_t s, uint64_t *arena, uint64_t base, uint64_t nslots, const KSpec &ks,
                           Ctrl *ctrl, KSpill spill);
 // Grace partitioning of a run: histogram of the digit (h0 >> shift) & mask,

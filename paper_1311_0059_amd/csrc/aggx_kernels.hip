@@ -630,6 +630,45 @@ hipError_t launch_filter_build(hipStream_t s, const uint64_t *arena, uint8_t *fi
   return hipGetLastError();
 }
 
+// One workgroup per descriptor: each key of the old table is inserted into the
+// new one (empty, so every CAS on kEmpty that wins is the key's slot; the keys are
+// distinct), probing from its home slot there as the update kernel will, and its
+// aggregates copied.  The old table is left as it is.
+__global__ void __launch_bounds__(256) k_migrate(uint64_t *arena, MigDesc *descs, KSpec ks, KLevel lv) {
+  MigDesc &d = descs[blockIdx.x];
+  const uint32_t W = 1 + ks.na;
+  const uint64_t lim = d.new_n < kProbeLimit ? d.new_n : kProbeLimit;
+  for (uint64_t e = threadIdx.x; e < d.old_n; e += blockDim.x) {
+    const uint64_t *src = arena + (d.old_base + e) * W;
+    const uint64_t key = src[0];
+    if (key >= kClosed) continue;
+    const uint64_t hs = lv.level == 0 ? (fmix64(key ^ kSeed0) << lv.slot_shift) : fmix64(key ^ lv.seed_slot);
+    uint64_t x = mulhi64(hs, d.new_n);
+    bool placed = false;
+    for (uint64_t t = 0; t < lim; ++t) {
+      unsigned long long expect = kEmpty;
+      if (__hip_atomic_compare_exchange_strong(reinterpret_cast<unsigned long long *>(arena + (d.new_base + x) * W),
+                                               &expect, (unsigned long long)key, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)) {
+        uint64_t *dst = arena + (d.new_base + x) * W;
+        for (uint32_t a = 0; a < ks.na; ++a) dst[1 + a] = src[1 + a];
+        placed = true;
+        break;
+      }
+      x = x + 1 == d.new_n ? 0 : x + 1;
+    }
+    if (!placed) d.fail = 1;
+  }
+}
+
+hipError_t launch_migrate(hipStream_t s, uint64_t *arena, MigDesc *descs, uint32_t n, const KSpec &ks,
+                          const KLevel &lv) {
+  if (n == 0) return hipSuccess;
+  if (n > kMigMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_migrate, dim3(n), dim3(256), 0, s, arena, descs, ks, lv);
+  return hipGetLastError();
+}
+
 hipError_t launch_extract(hipStream_t s, uint64_t *arena, uint64_t base, uint64_t nslots, const KSpec &ks,
                           Ctrl *ctrl, KSpill spill) {
   if (nslots == 0) return hipSuccess;

@@ -13,6 +13,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <iterator>
+#include <map>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -175,7 +177,60 @@ struct RunSet {
     n_raw = n_state = 0;
   }
   bool empty() const { return n_raw == 0 && n_state == 0; }
+  // Keep the region just reserved out of later reservations without making it a
+  // piece (a launch's spill that is fed again rather than kept).
+  void claim(uint64_t bytes) { cursor += round_up(bytes, 256); }
 };
+
+// Dynamic Destaging's memory pool (Sec. 4.3.3): the arena's slots in frames of
+// kFrameSlots.  A table is a run of frames; a spilled partition's frames go back
+// to the pool (merged with free neighbours) for the tables that grow.
+constexpr uint64_t kFrameSlots = 32;
+constexpr uint64_t kMaxTableFrames = (1ull << 31) / kFrameSlots;  // a table's slot count stays within 32 bits
+static_assert(sizeof(MigDesc) * kMigMax <= (uint64_t)kMaxFan * 4, "migration descriptors fit the pack area");
+
+struct FramePool {
+  std::map<uint64_t, uint64_t> free_runs;  // offset -> length, in frames
+  uint64_t frames = 0;
+
+  void init(uint64_t n) {
+    frames = n;
+    free_runs.clear();
+    if (n) free_runs[0] = n;
+  }
+  // the smallest free run of at least `len` frames, cut from its front (~0 when none)
+  uint64_t alloc(uint64_t len) {
+    auto best = free_runs.end();
+    for (auto it = free_runs.begin(); it != free_runs.end(); ++it)
+      if (it->second >= len && (best == free_runs.end() || it->second < best->second)) best = it;
+    if (best == free_runs.end()) return ~0ULL;
+    const uint64_t off = best->first, rest = best->second - len;
+    free_runs.erase(best);
+    if (rest) free_runs[off + len] = rest;
+    return off;
+  }
+  bool can_alloc(uint64_t len) const {
+    for (const auto &r : free_runs)
+      if (r.second >= len) return true;
+    return false;
+  }
+  void release(uint64_t off, uint64_t len) {
+    auto next = free_runs.lower_bound(off);
+    if (next != free_runs.end() && next->first == off + len) {
+      len += next->second;
+      next = free_runs.erase(next);
+    }
+    if (next != free_runs.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += len;
+        return;
+      }
+    }
+    free_runs[off] = len;
+  }
+};
+
 
 enum HState { H_OPEN = 0, H_FINISHED = 1, H_POISONED = 2 };
 
@@ -260,6 +315,10 @@ struct agg_handle {
   RunSet hs_runs;
   std::vector<const uint8_t *> hs_run_host;
   RunSet hs_tmp[2];
+  // Dynamic Destaging with a frame pool (the current level's plan uses it)
+  bool dd_active = false;
+  FramePool dd_pool;
+  uint64_t dd_chunk = 0;  // records per launch while the estimate says the tables will fill (0: the default)
 };
 
 namespace {
@@ -434,6 +493,56 @@ agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_
   pl.F = 1u << b;
   pl.digit_shift = b ? 64 - consumed_bits - b : 0;
   pl.seed_slot = level_seed(level);
+  h->dd_active = false;
+  if (!h->unlimited && h->spec.policy == AGG_POLICY_DESTAGE && reserve == 0) {
+    // Dynamic Destaging (Sec. 4.3.3): every partition starts resident, with a table
+    // of frames from the pool; what is left of the pool is there for the tables that
+    // fill (handle_overflow).  At least two frames per partition.
+    const uint64_t frames = cap_bytes / (W8 * kFrameSlots);
+    while (!h->spec.fanout_bits && b > 0 && (2ull << b) > frames) --b;
+    if ((2ull << b) <= frames) {
+      pl.fan_bits = b;
+      pl.F = 1u << b;
+      pl.digit_shift = b ? 64 - consumed_bits - b : 0;
+      const double g = G / pl.F;
+      const double cap_need = g + 4.0 * std::sqrt(g) + 16.0;
+      const auto frames_for = [&](double load) {
+        return ((uint64_t)std::ceil(cap_need / load) + kFrameSlots) / kFrameSlots;
+      };
+      const uint64_t need = frames_for(lam), half = frames_for(0.5), tight = frames_for(kPlanMaxLoad);
+      const uint64_t spread = frames / pl.F;
+      // tables for the estimate (spread down to a load of one half) when they fit, the rest
+      // of the pool kept for tables that fill; else equal shares of the whole pool: every
+      // partition starts resident whatever the estimate says
+      uint64_t t = spread;
+      if (h->spec.load_pct) t = std::min(spread, need);  // an explicit load is taken as given
+      else if (need <= spread) t = std::min(spread, std::max(need, half));
+      t = std::min(t, kMaxTableFrames);
+      // when the estimate does not fit even at a high load, launches are kept to a quarter
+      // of what the tables hold, so that full tables are found (and grown, or spilled)
+      // before most of the input has met them full
+      h->dd_chunk = tight > spread ? std::max<uint64_t>(1 << 16, (uint64_t)(pl.F * t * kFrameSlots * kMaxLoad / 4)) : 0;
+      h->dd_pool.init(frames);
+      pl.meta.resize(pl.F);
+      for (uint32_t p = 0; p < pl.F; ++p) {
+        PartMeta &m = pl.meta[p];
+        const uint64_t off = h->dd_pool.alloc(t);
+        if (off == ~0ULL) return AGG_E_INTERNAL;  // F * t <= frames by construction
+        m.base = off * kFrameSlots;
+        m.nslots = (uint32_t)(kFrameSlots * t);
+        m.cap = (uint32_t)std::min<uint64_t>(m.nslots - 1, (uint64_t)std::floor(m.nslots * kMaxLoad));
+        m.spilled = 0;
+        m.filt = 0;
+      }
+      pl.arena_slots = frames * kFrameSlots;
+      pl.planned_spilled = 0;
+      if (level == 0) h->st.table_slots_l0 = (uint64_t)pl.F * kFrameSlots * t;
+      h->planned = true;
+      h->dd_active = true;
+      h->st.pool_high_water = std::max(h->st.pool_high_water, kOverhead + pl.arena_slots * W8);
+      return AGG_OK;
+    }
+  }
   const double g = G / pl.F;
   const double cap_need = g + 4.0 * std::sqrt(g) + 16.0;
   uint64_t slots_need = (uint64_t)std::ceil(cap_need / lam) + 1;
@@ -553,7 +662,179 @@ KSpill spill_target(agg_handle *h, uint8_t *raw, uint8_t *state) {
 // later records of absent keys spill without probing the table.  (A partition
 // flagged because a probe hit the probe limit below its group limit can still
 // gain keys: it gets no filter.)
-agg_status handle_overflow(agg_handle *h) {
+// Dynamic Destaging: spill partition p -- its `groups` states go to the spill
+// run, its table is cleared and its frames go back to the pool; all its later
+// records are spilled raw.  (The meta upload is the caller's.)
+agg_status dd_spill(agg_handle *h, uint32_t p, uint64_t groups) {
+  PartMeta &m = h->plan.meta[p];
+  uint8_t *dst = nullptr;
+  if (!h->next.reserve(std::max<uint64_t>(groups, 1) * h->W8, &dst)) return AGG_E_NOMEM;
+  HCK(h, launch_u64_set(h->stream, &h->d_ctrl->state_ctr, 1, 0));
+  HCK(h, launch_extract(h->stream, h->d_arena, m.base, m.nslots, h->ks, h->d_ctrl, spill_target(h, nullptr, dst)));
+  agg_status s = read_ctrl(h);
+  if (s) return s;
+  if (h->h_ctrl->state_ctr != groups) return AGG_E_INTERNAL;  // the group counter counts every key inserted
+  h->next.commit(dst, groups, h->W8, true);
+  h->st.states_spilled += groups;
+  h->st.bytes_spilled_d2h += groups * h->W8;
+  if (h->dd_active && m.nslots) h->dd_pool.release(m.base / kFrameSlots, m.nslots / kFrameSlots);
+  m.spilled = 1;
+  m.nslots = 0;
+  m.cap = 0;
+  if (h->plan.level == 0) h->st.partitions_spilled += 1;
+  return AGG_OK;
+}
+
+// Move the groups of the tables in `descs` (already given their new blocks in the
+// plan) and give the old blocks back to the pool, cleared; a table whose move
+// failed (a key found no slot within the probe limit) is spilled from its old
+// block instead.
+agg_status dd_migrate(agg_handle *h, std::vector<MigDesc> &descs, const std::vector<uint32_t> &desc_p) {
+  LevelPlan &pl = h->plan;
+  const uint32_t *groups = h->h_scratch + kMaxFan;
+  KLevel lv;
+  lv.level = pl.level;
+  lv.slot_shift = pl.fan_bits;
+  lv.seed_slot = pl.seed_slot;
+  MigDesc *d_desc = reinterpret_cast<MigDesc *>(h->d_pack);
+  for (size_t i0 = 0; i0 < descs.size(); i0 += kMigMax) {
+    const uint32_t nd = (uint32_t)std::min<size_t>(kMigMax, descs.size() - i0);
+    HCK(h, hipMemcpyAsync(d_desc, descs.data() + i0, nd * sizeof(MigDesc), hipMemcpyHostToDevice, h->stream));
+    HCK(h, launch_migrate(h->stream, h->d_arena, d_desc, nd, h->ks, lv));
+    HCK(h, hipMemcpyAsync(descs.data() + i0, d_desc, nd * sizeof(MigDesc), hipMemcpyDeviceToHost, h->stream));
+    HCK(h, hipStreamSynchronize(h->stream));
+  }
+  const uint64_t W = 1 + h->ks.na;
+  for (size_t i = 0; i < descs.size(); ++i) {
+    const MigDesc &d = descs[i];
+    const uint32_t p = desc_p[i];
+    PartMeta &m = pl.meta[p];
+    if (d.fail) {
+      HCK(h, launch_table_init(h->stream, h->d_arena + d.new_base * W, d.new_n, h->ks));
+      h->dd_pool.release(d.new_base / kFrameSlots, d.new_n / kFrameSlots);
+      m.base = d.old_base;
+      m.nslots = d.old_n;
+      agg_status s = dd_spill(h, p, groups[p]);
+      if (s) return s;
+      continue;
+    }
+    HCK(h, launch_table_init(h->stream, h->d_arena + d.old_base * W, d.old_n, h->ks));
+    h->dd_pool.release(d.old_base / kFrameSlots, d.old_n / kFrameSlots);
+    h->st.partitions_grown += 1;
+  }
+  HCK(h, hipStreamSynchronize(h->stream));
+  descs.clear();
+  return AGG_OK;
+}
+
+// Dynamic Destaging (Sec. 4.3.3), Stage 2: each partition whose table filled in
+// the last launch gets a table twice as large from the pool, its groups moved
+// there.  Tables are grown while the pool has room, in rounds (a round's old
+// blocks go back to the pool for the next); for the ones left, the largest
+// resident partition (by table, then by groups; not one grown just now) is
+// spilled and its frames recycled, until the pool has room -- or the full
+// partition is itself the largest and is the one spilled.  The caller feeds the
+// launch's spilled records again, so that the records of keys that found a
+// grown table full are aggregated after all.
+agg_status dd_grow_or_spill(agg_handle *h, const std::vector<uint32_t> &full) {
+  LevelPlan &pl = h->plan;
+  const uint32_t *groups = h->h_scratch + kMaxFan;
+  std::vector<uint32_t> pending(full);
+  std::sort(pending.begin(), pending.end(), [&](uint32_t a, uint32_t b) {
+    return pl.meta[a].nslots != pl.meta[b].nslots ? pl.meta[a].nslots > pl.meta[b].nslots : a < b;
+  });
+  std::vector<char> grown(pl.F, 0);
+  std::vector<MigDesc> descs;
+  std::vector<uint32_t> desc_p;
+  const auto len_of = [](const PartMeta &m) { return (uint64_t)m.nslots / kFrameSlots; };
+  // give p a table twice as large (the pool has room); the move is queued in descs
+  const auto grow = [&](uint32_t p) {
+    const uint64_t len2 = 2 * len_of(pl.meta[p]);
+    MigDesc d{};
+    d.old_base = pl.meta[p].base;
+    d.old_n = pl.meta[p].nslots;
+    d.new_base = h->dd_pool.alloc(len2) * kFrameSlots;
+    d.new_n = (uint32_t)(kFrameSlots * len2);
+    descs.push_back(d);
+    desc_p.push_back(p);
+    grown[p] = 1;
+    PartMeta &m = pl.meta[p];
+    m.base = d.new_base;
+    m.nslots = d.new_n;
+    m.cap = (uint32_t)std::min<uint64_t>(m.nslots - 1, (uint64_t)std::floor(m.nslots * kMaxLoad));
+  };
+  // rounds of growth without victims
+  for (;;) {
+    std::vector<uint32_t> rest;
+    desc_p.clear();
+    for (uint32_t p : pending) {
+      const uint64_t len2 = 2 * len_of(pl.meta[p]);
+      if (len2 <= kMaxTableFrames && h->dd_pool.can_alloc(len2)) grow(p);
+      else rest.push_back(p);
+    }
+    if (descs.empty()) break;
+    agg_status s = dd_migrate(h, descs, desc_p);
+    if (s) return s;
+    pending.swap(rest);
+  }
+  // the rest: victims until the pool has room
+  desc_p.clear();
+  std::vector<uint32_t> spill_p;
+  std::vector<PartMeta> spill_old;  // a victim's table before it was given up
+  const auto give_up = [&](uint32_t x) {
+    spill_p.push_back(x);
+    spill_old.push_back(pl.meta[x]);
+    h->dd_pool.release(pl.meta[x].base / kFrameSlots, len_of(pl.meta[x]));
+    pl.meta[x].spilled = 1;
+    pl.meta[x].nslots = 0;
+    pl.meta[x].cap = 0;
+  };
+  for (uint32_t p : pending) {
+    if (pl.meta[p].spilled) continue;  // already a victim of another's growth
+    const uint64_t len2 = 2 * len_of(pl.meta[p]);
+    bool self = len2 > kMaxTableFrames;  // a table may not pass 2^31 slots
+    while (!self && !h->dd_pool.can_alloc(len2)) {
+      int v = -1;
+      for (uint32_t q = 0; q < pl.F; ++q) {
+        if (pl.meta[q].spilled || grown[q]) continue;
+        if (v < 0 || pl.meta[q].nslots > pl.meta[v].nslots ||
+            (pl.meta[q].nslots == pl.meta[v].nslots && groups[q] > groups[v]))
+          v = (int)q;
+      }
+      if (v < 0 || (uint32_t)v == p) {
+        self = true;
+        break;
+      }
+      give_up((uint32_t)v);
+    }
+    if (self) give_up(p);
+    else grow(p);
+  }
+  // the victims' states out first (their frames may be a grown table's new block)
+  for (size_t i = 0; i < spill_p.size(); ++i) {
+    const uint32_t x = spill_p[i];
+    uint8_t *dst = nullptr;
+    const uint64_t g = groups[x];
+    if (!h->next.reserve(std::max<uint64_t>(g, 1) * h->W8, &dst)) return AGG_E_NOMEM;
+    HCK(h, launch_u64_set(h->stream, &h->d_ctrl->state_ctr, 1, 0));
+    HCK(h, launch_extract(h->stream, h->d_arena, spill_old[i].base, spill_old[i].nslots, h->ks, h->d_ctrl,
+                          spill_target(h, nullptr, dst)));
+    agg_status s = read_ctrl(h);
+    if (s) return s;
+    if (h->h_ctrl->state_ctr != g) return AGG_E_INTERNAL;
+    h->next.commit(dst, g, h->W8, true);
+    h->st.states_spilled += g;
+    h->st.bytes_spilled_d2h += g * h->W8;
+    if (pl.level == 0) h->st.partitions_spilled += 1;
+  }
+  agg_status s = dd_migrate(h, descs, desc_p);
+  if (s) return s;
+  HCK(h, hipMemcpyAsync(h->d_meta, pl.meta.data(), sizeof(PartMeta) * pl.F, hipMemcpyHostToDevice, h->stream));
+  HCK(h, hipStreamSynchronize(h->stream));
+  return AGG_OK;
+}
+
+agg_status handle_overflow(agg_handle *h, bool can_grow) {
   if (h->h_ctrl->any_ovf == 0) return AGG_OK;
   LevelPlan &pl = h->plan;
   HCK(h, hipMemcpyAsync(h->h_scratch, h->d_ovf, 4ull * pl.F, hipMemcpyDeviceToHost, h->stream));
@@ -564,23 +845,14 @@ agg_status handle_overflow(agg_handle *h) {
   for (uint32_t p = 0; p < pl.F; ++p)
     if (h->h_scratch[p] && !pl.meta[p].spilled) victims.push_back(p);
   if (h->spec.policy == AGG_POLICY_DESTAGE) {
-    for (uint32_t p : victims) {
-      PartMeta &m = pl.meta[p];
-      const uint64_t groups = h->h_scratch[kMaxFan + p];  // exact count of inserted groups
-      uint8_t *dst = nullptr;
-      if (!h->next.reserve(std::max<uint64_t>(groups, 1) * h->W8, &dst)) return AGG_E_NOMEM;
-      HCK(h, launch_u64_set(h->stream, &h->d_ctrl->state_ctr, 1, 0));
-      HCK(h, launch_extract(h->stream, h->d_arena, m.base, m.nslots, h->ks, h->d_ctrl, spill_target(h, nullptr, dst)));
-      agg_status s = read_ctrl(h);
-      if (s) return s;
-      h->next.commit(dst, h->h_ctrl->state_ctr, h->W8, true);
-      h->st.states_spilled += h->h_ctrl->state_ctr;
-      h->st.bytes_spilled_d2h += h->h_ctrl->state_ctr * h->W8;
-      m.spilled = 1;
-      m.nslots = 0;
-      m.cap = 0;
-      HCK(h, hipMemcpyAsync(h->d_meta + p, &m, sizeof(PartMeta), hipMemcpyHostToDevice, h->stream));
-      if (pl.level == 0) h->st.partitions_spilled += 1;
+    agg_status s = h->dd_active && can_grow ? dd_grow_or_spill(h, victims) : AGG_OK;
+    if (s) return s;
+    if (!(h->dd_active && can_grow)) {
+      for (uint32_t p : victims) {
+        s = dd_spill(h, p, h->h_scratch[kMaxFan + p]);
+        if (s) return s;
+      }
+      HCK(h, hipMemcpyAsync(h->d_meta, pl.meta.data(), sizeof(PartMeta) * pl.F, hipMemcpyHostToDevice, h->stream));
     }
   }
   if (h->spec.policy == AGG_POLICY_PREPART && h->d_filter) {
@@ -609,53 +881,73 @@ agg_status handle_overflow(agg_handle *h) {
 // has a bounded pinned reservation.
 agg_status run_stream(agg_handle *h, const uint8_t *in, uint64_t n, int kind) {
   const uint64_t in_bytes = kind == 0 ? h->ks.rb : h->W8;
-  const uint64_t chunk = std::max<uint64_t>(1, kChunkBytes / in_bytes);
+  uint64_t chunk = std::max<uint64_t>(1, kChunkBytes / in_bytes);
   KLevel lv;
   lv.level = h->plan.level;
   lv.digit_shift = h->plan.digit_shift;
   lv.fan_mask = h->plan.F - 1;
   lv.slot_shift = h->plan.fan_bits;
   lv.seed_slot = h->plan.seed_slot;
+  const bool grow = h->dd_active && h->spec.policy == AGG_POLICY_DESTAGE;
+  if (grow && h->dd_chunk) chunk = std::min(chunk, h->dd_chunk);
   for (uint64_t off = 0; off < n; off += chunk) {
     const uint64_t c = std::min(chunk, n - off);
-    uint8_t *dst = nullptr;
-    if (!h->next.reserve(c * in_bytes, &dst)) return AGG_E_NOMEM;
-    HCK(h, launch_u64_set(h->stream, kind == 0 ? &h->d_ctrl->raw_ctr : &h->d_ctrl->state_ctr, 1, 0));
-    KSpill sp = spill_target(h, kind == 0 ? dst : nullptr, kind == 0 ? nullptr : dst);
-    // level-0 raw records come from agg_consume, whose batch follows the records counted before it
-    lv.rec_base = h->plan.level == 0 && kind == 0 ? h->st.records_in - n + off : ~0ULL;
-    lv.filter = h->d_filter;
-    const bool preagg = h->preagg > 0 && h->plan.arena_slots < (1ull << 32);
-    if (preagg) h->st.preagg = 1;
-    HCK(h, hipEventRecord(h->ev0, h->stream));
-    HCK(h, launch_update(h->stream, kind, in + off * in_bytes, c, h->ks, lv, h->d_meta, h->d_cnt, h->d_ovf,
-                         h->d_arena, h->d_ctrl, sp, preagg));
-    HCK(h, hipEventRecord(h->ev1, h->stream));
-    agg_status s = read_ctrl(h);
-    if (s) return s;
-    float ms = 0.f;
-    HCK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
-    h->st.update_launches += 1;
-    h->st.update_records += c;
-    h->st.update_ms += ms;
-    if (h->plan.level == 0) {
-      h->st.update_launches_l0 += 1;
-      h->st.update_records_l0 += c;
-      h->st.update_ms_l0 += ms;
+    const uint8_t *src = in + off * in_bytes;
+    uint64_t cnt = c;
+    bool again = false;  // feeding what the last launch spilled, after its full tables grew
+    for (;;) {
+      uint8_t *dst = nullptr;
+      if (!h->next.reserve(cnt * in_bytes, &dst)) return AGG_E_NOMEM;
+      HCK(h, launch_u64_set(h->stream, kind == 0 ? &h->d_ctrl->raw_ctr : &h->d_ctrl->state_ctr, 1, 0));
+      KSpill sp = spill_target(h, kind == 0 ? dst : nullptr, kind == 0 ? nullptr : dst);
+      // level-0 raw records come from agg_consume, whose batch follows the records counted before it
+      lv.rec_base = h->plan.level == 0 && kind == 0 && !again ? h->st.records_in - n + off : ~0ULL;
+      lv.filter = h->d_filter;
+      const bool preagg = h->preagg > 0 && h->plan.arena_slots < (1ull << 32);
+      if (preagg) h->st.preagg = 1;
+      HCK(h, hipEventRecord(h->ev0, h->stream));
+      HCK(h, launch_update(h->stream, kind, src, cnt, h->ks, lv, h->d_meta, h->d_cnt, h->d_ovf, h->d_arena,
+                           h->d_ctrl, sp, preagg));
+      HCK(h, hipEventRecord(h->ev1, h->stream));
+      agg_status s = read_ctrl(h);
+      if (s) return s;
+      float ms = 0.f;
+      HCK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      h->st.update_launches += 1;
+      h->st.update_records += cnt;
+      h->st.update_ms += ms;
+      if (h->plan.level == 0) {
+        h->st.update_launches_l0 += 1;
+        h->st.update_records_l0 += cnt;
+        h->st.update_ms_l0 += ms;
+      }
+      if (again) h->st.records_refed += cnt;
+      const uint64_t got = kind == 0 ? h->h_ctrl->raw_ctr : h->h_ctrl->state_ctr;
+      if (h->plan.level == 0 && kind == 0 && !again)
+        h->st.first_full_record = std::min<uint64_t>(h->st.first_full_record, h->h_ctrl->first_full);
+      if (grow && h->h_ctrl->any_ovf) {
+        // Dynamic Destaging: full tables grow (or partitions are spilled), then what this
+        // launch spilled is fed again; its region is kept out of the run
+        if (got) h->next.claim(got * in_bytes);
+        s = handle_overflow(h, true);
+        if (s) return s;
+        if (got == 0) break;
+        src = dst;
+        cnt = got;
+        again = true;
+        continue;
+      }
+      h->next.commit(dst, got, in_bytes, kind == 1);
+      if (h->plan.level == 0 && kind == 0) h->st.records_spilled_l0 += got;
+      if (kind == 0)
+        h->st.records_spilled += got;
+      else
+        h->st.states_spilled += got;
+      h->st.bytes_spilled_d2h += got * in_bytes;
+      s = handle_overflow(h, false);
+      if (s) return s;
+      break;
     }
-    const uint64_t got = kind == 0 ? h->h_ctrl->raw_ctr : h->h_ctrl->state_ctr;
-    h->next.commit(dst, got, in_bytes, kind == 1);
-    if (h->plan.level == 0 && kind == 0) {
-      h->st.records_spilled_l0 += got;
-      h->st.first_full_record = std::min<uint64_t>(h->st.first_full_record, h->h_ctrl->first_full);
-    }
-    if (kind == 0)
-      h->st.records_spilled += got;
-    else
-      h->st.states_spilled += got;
-    h->st.bytes_spilled_d2h += got * in_bytes;
-    s = handle_overflow(h);
-    if (s) return s;
   }
   return AGG_OK;
 }
@@ -1162,7 +1454,7 @@ agg_status run_onchip(agg_handle *h, const uint8_t *in, uint64_t n, bool *applie
   h->st.onchip_classes = op.C;
   h->st.onchip_workers = op.workers;
   h->st.lds_narrow = op.narrow ? 1u : 0u;
-  return handle_overflow(h);
+  return handle_overflow(h, true);  // (nothing was spilled: a full table may grow)
 }
 
 // ---- sorted runs ------------------------------------------------------------
@@ -1295,7 +1587,7 @@ agg_status run_owner_stream(agg_handle *h, const uint8_t *in, uint64_t n) {
     h->st.records_spilled += got;
     h->st.records_spilled_l0 += got;
     h->st.bytes_spilled_d2h += got * rb;
-    s = handle_overflow(h);
+    s = handle_overflow(h, false);
     if (s) return s;
   }
   return AGG_OK;
@@ -1330,7 +1622,7 @@ agg_status demote_lds(agg_handle *h, uint64_t n_next) {
   h->st.bytes_spilled_d2h += h->h_ctrl->state_ctr * h->W8;
   h->r_rows = 0;
   h->engine = 1;
-  return handle_overflow(h);
+  return handle_overflow(h, false);  // the spilled states stay spilled: full partitions are spilled
 }
 
 // Run the pieces of a run set through the current level: states first, then raw records.
