@@ -149,10 +149,11 @@ __device__ __forceinline__ uint64_t in_key(const uint8_t *rec, const KSpec &ks) 
   return ld64(rec);
 }
 
-template <int KIND>
+// (kA bounds the loop where the caller knows that ks.na <= kA.)
+template <int KIND, int kA = kMaxAggs>
 __device__ __forceinline__ void in_vals(const uint8_t *rec, const KSpec &ks, uint64_t *vals) {
 #pragma unroll
-  for (int a = 0; a < kMaxAggs; ++a) {
+  for (int a = 0; a < kA; ++a) {
     if (a >= (int)ks.na) break;
     const uint32_t d = ks.agg[a];
     if (KIND == 0)
@@ -185,9 +186,10 @@ __device__ __forceinline__ void block_copy(uint32_t *dst, const uint32_t *src, u
 }
 
 // Fold one contribution into an LDS accumulator (the workgroup's hot-key cache).
+template <int kA = kMaxAggs>
 __device__ __forceinline__ void fold_lds(uint64_t *acc, uint32_t stride, const KSpec &ks, const uint64_t *vals) {
 #pragma unroll
-  for (int a = 0; a < kMaxAggs; ++a) {
+  for (int a = 0; a < kA; ++a) {
     if (a >= (int)ks.na) break;
     const uint32_t d = ks.agg[a];
     unsigned long long *w = reinterpret_cast<unsigned long long *>(acc + (uint64_t)a * stride);

@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const uint8_t *__re
 // costs less than a second partition pass over the whole batch.  The table's
 // slot index uses the hash bits below both digits (slot_shift).
 // One sweep of k_lds_agg over the partition's records [lo, hi).
-template <bool kNarrow>
+template <bool kNarrow, int kA>
 __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, uint64_t hi, const KSpec &ks,
                                               uint32_t slot_shift, uint32_t sweep_bits, uint32_t sweep,
                                               uint32_t nslots, uint32_t cap, Ctrl *ctrl, const KSpill &spill,
@@ -371,16 +371,32 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
   if (tid == 0) *s_groups = 0;
   __syncthreads();
   const uint64_t B = blockDim.x;
-  for (uint64_t t0 = lo; t0 < hi; t0 += kLdsUnroll * B) {
-    // the tile's records are read before any is probed, so that their loads are in flight together
-    uint64_t keys[kLdsUnroll], vals[kLdsUnroll][kMaxAggs];
+  // A tile's records are read before any is probed, so that their loads are in
+  // flight together; with up to four aggregates the next tile's loads are issued
+  // before this one is probed (the kernel waits on memory more than on anything
+  // else; with eight, both tiles would not fit the registers).
+  constexpr bool kAhead = kA <= 4;
+  uint64_t nkeys[kLdsUnroll], nvals[kLdsUnroll][kA];
+  const auto load_tile = [&](uint64_t t0) {
 #pragma unroll
     for (int u = 0; u < kLdsUnroll; ++u) {
       const uint64_t i = t0 + u * B + tid;
       const uint8_t *rec = buf + (i < hi ? i : lo) * rb;
-      keys[u] = read_key(rec, ks);
-      in_vals<0>(rec, ks, vals[u]);
+      nkeys[u] = read_key(rec, ks);
+      in_vals<0, kA>(rec, ks, nvals[u]);
     }
+  };
+  if (kAhead && lo < hi) load_tile(lo);
+  for (uint64_t t0 = lo; t0 < hi; t0 += kLdsUnroll * B) {
+    if (!kAhead) load_tile(t0);
+    uint64_t keys[kLdsUnroll], vals[kLdsUnroll][kA];
+#pragma unroll
+    for (int u = 0; u < kLdsUnroll; ++u) {
+      keys[u] = nkeys[u];
+#pragma unroll
+      for (int a = 0; a < kA; ++a) vals[u][a] = nvals[u][a];
+    }
+    if (kAhead && t0 + kLdsUnroll * B < hi) load_tile(t0 + kLdsUnroll * B);
 #pragma unroll
     for (int u = 0; u < kLdsUnroll; ++u) {
       const uint64_t i = t0 + u * B + tid;
@@ -399,8 +415,8 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
         // once per wave, whatever slot each lane ended on
         const uint32_t slot = lds_find_or_insert(t_key, nslots, cap, s_groups, key, h0 << slot_shift);
         if (slot != ~0u) {
-          if constexpr (kNarrow) fold_lds_cols<kNarrow>(t_cols, nslots, slot, ks, vals[u]);
-          else fold_lds(t_acc + slot, nslots, ks, vals[u]);
+          if constexpr (kNarrow) fold_lds_cols<kNarrow, kA>(t_cols, nslots, slot, ks, vals[u]);
+          else fold_lds<kA>(t_acc + slot, nslots, ks, vals[u]);
         }
         to_spill = slot == ~0u;
       }
@@ -452,7 +468,7 @@ __device__ __forceinline__ void lds_agg_sweep(const uint8_t *buf, uint64_t lo, u
   __syncthreads();  // every thread has read the table before it is cleared again
 }
 
-template <bool kNarrow>
+template <bool kNarrow, int kA>
 __global__ void __launch_bounds__(kLdsBlock) k_lds_agg(const uint8_t *__restrict__ buf,
                                                  const unsigned long long *__restrict__ offsets, KSpec ks,
                                                  uint32_t slot_shift, uint32_t sweep_bits, uint32_t nslots,
@@ -465,7 +481,7 @@ __global__ void __launch_bounds__(kLdsBlock) k_lds_agg(const uint8_t *__restrict
   uint64_t *t_key = reinterpret_cast<uint64_t *>(lds4);
   const uint64_t lo = offsets[blockIdx.x], hi = offsets[blockIdx.x + 1];
   for (uint32_t sweep = 0; sweep < (1u << sweep_bits); ++sweep)
-    lds_agg_sweep<kNarrow>(buf, lo, hi, ks, slot_shift, sweep_bits, sweep, nslots, cap, ctrl, spill, out_keys, out_cols,
+    lds_agg_sweep<kNarrow, kA>(buf, lo, hi, ks, slot_shift, sweep_bits, sweep, nslots, cap, ctrl, spill, out_keys, out_cols,
                   out_cap, t_key, &s_groups, &s_base, scratch);
 }
 
@@ -622,9 +638,13 @@ const DeviceSetup *device_setup() {
   allow(reinterpret_cast<const void *>(k_part_scatter<0>), &ds.scatter_lds_max);
   allow(reinterpret_cast<const void *>(k_part_scatter<6>), &sc6);
   ds.scatter_lds_max = std::min(ds.scatter_lds_max, sc6);
-  allow(reinterpret_cast<const void *>(k_lds_agg<false>), &ds.lds_max);
-  allow(reinterpret_cast<const void *>(k_lds_agg<true>), &narrow_max);
-  ds.lds_max = std::min(ds.lds_max, narrow_max);
+  allow(reinterpret_cast<const void *>(k_lds_agg<false, 8>), &ds.lds_max);
+  for (const void *fn : {reinterpret_cast<const void *>(k_lds_agg<true, 8>),
+                         reinterpret_cast<const void *>(k_lds_agg<false, 4>),
+                         reinterpret_cast<const void *>(k_lds_agg<true, 4>)}) {
+    allow(fn, &narrow_max);
+    ds.lds_max = std::min(ds.lds_max, narrow_max);
+  }
   (void)hipGetLastError();
   for (int kind = 0; kind < 2; ++kind)
     for (int pre = 0; pre < 2; ++pre)
@@ -659,12 +679,12 @@ hipError_t launch_lds_agg(hipStream_t s, const uint8_t *buf, const unsigned long
   if (sweep_bits > slot_shift || sweep_bits > 8 || nslots % 4 || nslots == 0 ||
       (uint64_t)lds_slot_bytes(ks, narrow) * nslots > lds_bytes)
     return hipErrorInvalidValue;
-  if (narrow)
-    hipLaunchKernelGGL(k_lds_agg<true>, dim3(F), dim3(kLdsBlock), lds_bytes, s, buf, offsets, ks, slot_shift,
-                       sweep_bits, nslots, cap, ctrl, spill, out_keys, out_cols, out_cap);
-  else
-    hipLaunchKernelGGL(k_lds_agg<false>, dim3(F), dim3(kLdsBlock), lds_bytes, s, buf, offsets, ks, slot_shift,
-                       sweep_bits, nslots, cap, ctrl, spill, out_keys, out_cols, out_cap);
+  // up to four aggregates: a kernel whose value arrays have four entries (the tile
+  // being probed and the next one fit the registers)
+  auto fn = narrow ? (ks.na <= 4 ? &k_lds_agg<true, 4> : &k_lds_agg<true, 8>)
+                   : (ks.na <= 4 ? &k_lds_agg<false, 4> : &k_lds_agg<false, 8>);
+  hipLaunchKernelGGL(fn, dim3(F), dim3(kLdsBlock), lds_bytes, s, buf, offsets, ks, slot_shift, sweep_bits, nslots,
+                     cap, ctrl, spill, out_keys, out_cols, out_cap);
   return hipGetLastError();
 }
 

@@ -38,10 +38,10 @@ __device__ __forceinline__ uint32_t narrow_identity(uint32_t d) {
 }
 
 // Fold one record's values into slot `e` of the table's columns.
-template <bool kNarrow>
+template <bool kNarrow, int kA = kMaxAggs>
 __device__ __forceinline__ void fold_lds_cols(uint8_t *cols, uint32_t nslots, uint32_t e, const KSpec &ks,
                                               const uint64_t *vals) {
-  for_lds_cols<kNarrow>(ks, cols, nslots, [&](int a, uint32_t d, bool nw, uint8_t *c) {
+  for_lds_cols<kNarrow, kA>(ks, cols, nslots, [&](int a, uint32_t d, bool nw, uint8_t *c) {
     const bool sg = type_signed(desc_type(d));
     const uint64_t v = vals[a];
     if (nw) {

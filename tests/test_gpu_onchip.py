@@ -62,12 +62,12 @@ def test_sizes(n, d):
 def test_r24_narrow_and_extremes():
     """Two-field keys, MIN/MAX of int32 fields at their extremes in 4-byte LDS columns."""
     rng = np.random.default_rng(11)
-    # 12k groups: four classes of 8-byte columns, three of narrow ones
+    # 12k groups: narrow columns save classes (six of 8-byte columns at two thirds load, four of narrow ones)
     rec = _rand_r24(rng, 300_000, _pool(rng, 11_900))
     print("case: onchip R24", flush=True)
     k, c, st = run_lib(rec, 24, SPEC_R24["keys"], SPEC_R24["aggs"], est_groups=12_000, engine="onchip")
     check_against_oracle(rec, SPEC_R24, k, c, "onchip R24")
-    assert st["engine"] == 5 and st["lds_narrow"] == 1 and st["onchip_classes"] == 3
+    assert st["engine"] == 5 and st["lds_narrow"] == 1 and st["onchip_classes"] == 4
 
 
 def test_reserved_keys_and_one_key():
