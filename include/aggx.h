@@ -227,6 +227,15 @@ typedef struct agg_stats {
    * table full are fed again. */
   uint32_t partitions_grown;    /* tables that grew */
   uint64_t records_refed;       /* records (or states) fed again after their tables grew */
+  /* The cost model that chooses the engine of an AUTO first batch: each engine's predicted time for it
+   * (0: not priced, the engine did not apply), and for the HBM tables the level-0 spill the paper's I/O
+   * model gives (R - (K/G) R records, Secs. 5.3.1 and 5.3.4) and the levels it takes. */
+  double cost_onchip_ms;
+  double cost_lds_ms;
+  double cost_tables_ms;
+  uint64_t cost_spilled_records;
+  uint32_t cost_levels;
+  uint32_t reserved_stats4;
 } agg_stats;
 
 /* Start one GROUP BY query (Sec. 3.1) under the memory budget M of Sec. 3.2

@@ -103,6 +103,12 @@ class Stats(ctypes.Structure):
         ("hashsort_fallbacks", ctypes.c_uint32),
         ("partitions_grown", ctypes.c_uint32),
         ("records_refed", ctypes.c_uint64),
+        ("cost_onchip_ms", ctypes.c_double),
+        ("cost_lds_ms", ctypes.c_double),
+        ("cost_tables_ms", ctypes.c_double),
+        ("cost_spilled_records", ctypes.c_uint64),
+        ("cost_levels", ctypes.c_uint32),
+        ("reserved_stats4", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:

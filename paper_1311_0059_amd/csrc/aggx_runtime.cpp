@@ -441,6 +441,13 @@ uint64_t level_seed(uint32_t level) {
 
 uint32_t floor_log2(uint64_t x) { return x ? 63u - (uint32_t)__builtin_clzll(x) : 0u; }
 
+// Yao's formula (Appendix, input component): records drawn, out of n holding m
+// distinct keys, until k distinct keys have been seen: n (1 - (1 - k/m)^(m/n)).
+double yao_i_raw(double k, double n, double m) {
+  if (k >= m) return n;
+  return n * (1.0 - std::pow(1.0 - k / m, m / n));
+}
+
 // Plan one hybrid-hash pass: fan-out, per-partition table sizes, and which
 // partitions are resident.  With an estimate G of the distinct keys, each of
 // the F partitions expects g = G/F groups; a resident table gets room for g
@@ -518,10 +525,16 @@ agg_status make_plan(agg_handle *h, uint32_t level, double G, uint32_t consumed_
       if (h->spec.load_pct) t = std::min(spread, need);  // an explicit load is taken as given
       else if (need <= spread) t = std::min(spread, std::max(need, half));
       t = std::min(t, kMaxTableFrames);
-      // when the estimate does not fit even at a high load, launches are kept to a quarter
-      // of what the tables hold, so that full tables are found (and grown, or spilled)
-      // before most of the input has met them full
-      h->dd_chunk = tight > spread ? std::max<uint64_t>(1 << 16, (uint64_t)(pl.F * t * kFrameSlots * kMaxLoad / 4)) : 0;
+      // When the estimate does not fit even at a high load, the tables will fill: launches
+      // are cut to a quarter of the records consumed before they do -- Yao's I_raw(K, n, G)
+      // (Appendix) with K the groups the tables hold and n the level's input (the first
+      // batch at level 0) -- so that full tables are found, and grown or spilled, early.
+      h->dd_chunk = 0;
+      if (tight > spread) {
+        const double K = (double)pl.F * t * kFrameSlots * kMaxLoad;
+        const double n_in = (double)std::max<uint64_t>(1, level == 0 ? h->plan_hint_n : h->lvl_in);
+        h->dd_chunk = std::max<uint64_t>(1 << 16, (uint64_t)(yao_i_raw(K, n_in, std::max(G, K)) / 4));
+      }
       h->dd_pool.init(frames);
       pl.meta.resize(pl.F);
       for (uint32_t p = 0; p < pl.F; ++p) {
@@ -1338,7 +1351,6 @@ constexpr double kOnchipLoad = 0.85;          // LDS table load at which a class
 // each tile from L2 per class.
 constexpr double kOnchipSizeLoad = 0.66;
 constexpr uint64_t kOnchipRecordsPerGroup = 16;  // records per worker and group before another worker pays
-constexpr double kOnchipAutoRatio = 256;         // records per group from which AUTO prefers this engine
 
 bool onchip_plan(const KSpec &ks, uint64_t n, double G, OnchipPlan *op) {
   const DeviceSetup *ds = device_setup();
@@ -1408,6 +1420,73 @@ bool onchip_plan(const KSpec &ks, uint64_t n, double G, OnchipPlan *op) {
   return true;
 }
 
+// ---- cost model ------------------------------------------------------------
+// The engine for a first batch is the one predicted cheapest.  The paper prices
+// an operator by its comparisons and its disk I/O (Sec. 5); here each engine is
+// priced by a fixed part per query and a part per byte of the batch, for its
+// kernels' passes over it, at rates measured on MI355X (uniform 16-byte records,
+// 250k to 300M of them, 2k to 40k keys, and the 200M- and 500M-record queries),
+// plus, for the HBM tables under a budget, the paper's I/O term: with K of the G
+// groups resident, R - (K/G) R records spill (C_IO, Secs. 5.3.1, 5.3.4), cross
+// the host link twice and are aggregated again at the next level.
+struct Cost {
+  double ms = HUGE_VAL;
+  double spilled = 0.0;  // records spilled at level 0
+  uint32_t levels = 1;
+};
+constexpr double kLinkBytesPerMs = 55e6;        // host link, either way, kernel or DMA (55-57 GB/s)
+constexpr double kCostLdsFixedMs = 0.46;        // partition-first: count, offsets, scatter, aggregate
+constexpr double kCostLdsPsPerByte = 2.37;      //   one pass over the batch
+constexpr double kCostScanPsPerByte = 0.25;     //   each further pass (the scatter reads the batch again)
+constexpr double kCostOnchipFixedMs = 0.55;     // on-chip: its kernel, the fold into and flush of the tables
+constexpr double kCostOnchipClassMs = 0.10;     //   per key class
+constexpr double kCostOnchipPsPerByte = 0.55;   //   per byte of the batch
+constexpr double kCostOnchipClassPs = 0.125;    //   per byte and key class (each class reads every tile)
+constexpr double kCostTablesFixedMs = 0.50;     // HBM tables with atomics
+constexpr double kCostTablesNsPerRecord = 0.16; //   per record (probe, insert, folds)
+
+Cost cost_onchip(const KSpec &ks, uint64_t n, const OnchipPlan &op) {
+  Cost c;
+  const double bytes = (double)n * ks.rb;
+  c.ms = kCostOnchipFixedMs + kCostOnchipClassMs * op.C + bytes * (kCostOnchipPsPerByte + kCostOnchipClassPs * op.C) * 1e-9;
+  return c;
+}
+
+Cost cost_lds(const agg_handle *h, uint64_t n, const LdsPlan &lp) {
+  Cost c;
+  const double bytes = (double)n * h->ks.rb;
+  const double passes = lp.passes ? std::ceil(bytes / (0.9 * (double)lp.buf_bytes)) : 1.0;
+  c.ms = kCostLdsFixedMs + bytes * (kCostLdsPsPerByte + (passes - 1.0) * kCostScanPsPerByte) * 1e-9;
+  return c;
+}
+
+// HBM tables: G groups, of which the budget keeps K resident at the highest load;
+// the spilled records are priced over the link and again at the next levels.
+Cost cost_tables(const agg_handle *h, uint64_t n, double G) {
+  Cost c;
+  const double cap = h->unlimited ? HUGE_VAL : (double)h->arena_cap_bytes * kMaxLoad / h->W8;
+  double ms = kCostTablesFixedMs, recs = (double)n, groups = std::max(1.0, G);
+  for (uint32_t level = 0; level < 4 && recs >= 1.0; ++level) {
+    ms += recs * kCostTablesNsPerRecord * 1e-6;
+    const double K = std::min(groups, cap);
+    const double spilled = recs * (1.0 - K / groups);  // C_IO: R - (K / G_t) R
+    if (level == 0) c.spilled = spilled;
+    if (spilled < 1.0) break;
+    ms += 2.0 * spilled * h->ks.rb / kLinkBytesPerMs;  // out to the host and back
+    c.levels = level + 2;
+    recs = spilled;
+    groups -= K;
+  }
+  c.ms = ms;
+  return c;
+}
+
+// The partition-first engine applies to an AUTO batch without repeated-key skew it
+// cannot take apart, within the input limit of an unlimited budget.
+bool lds_auto_applies(const agg_handle *h, uint64_t n) {
+  return (!h->hot_key || h->hot_n > 0) && h->spec.preagg != 1 && (n * h->ks.rb <= kLdsMaxInput || !h->unlimited);
+}
+
 // *applied is false when the engine does not apply, or when the batch had more
 // groups than the plan's tables held: the tables and side groups are then reset
 // and the batch goes to the other engines.
@@ -1421,13 +1500,21 @@ agg_status run_onchip(agg_handle *h, const uint8_t *in, uint64_t n, bool *applie
     if (!h->spec.est_groups) G = std::min(G, 1.25 * Gs);
     else if (Gs > 4.0 * G) return AGG_OK;
   }
-  // AUTO takes it where it pays: many records per group (each workgroup's LDS table then
-  // absorbs most updates), or a batch the partition-first engine does not take
-  if (h->spec.engine == AGG_ENGINE_AUTO && (double)n < kOnchipAutoRatio * G &&
-      !(h->unlimited && n * h->ks.rb > kLdsMaxInput))
-    return AGG_OK;
   OnchipPlan op;
   if (!onchip_plan(h->ks, n, G, &op)) return AGG_OK;
+  // AUTO takes it where the cost model prices it below the partition-first engine
+  // (when that applies); the tables engine is priced above both
+  const Cost co = cost_onchip(h->ks, n, op);
+  h->st.cost_onchip_ms = co.ms;
+  if (h->spec.engine == AGG_ENGINE_AUTO && lds_auto_applies(h, n)) {
+    LdsPlan lp;
+    const double Gl = h->spec.est_groups ? (double)h->spec.est_groups : (double)n;
+    if (lds_plan(h, n, Gl, &lp)) {
+      const Cost cl = cost_lds(h, n, lp);
+      h->st.cost_lds_ms = cl.ms;
+      if (cl.ms <= co.ms) return AGG_OK;
+    }
+  }
   h->plan_hint_n = n;
   agg_status s = make_plan(h, 0, G, 0);
   if (s) return s;
@@ -1711,6 +1798,9 @@ agg_status grace_split(agg_handle *h, const RunSet &in, uint32_t consumed, uint3
 // `consumed` bits, aggregate, spill what does not fit, flush the rest.
 agg_status hybrid_pass(agg_handle *h, uint32_t depth, double G, uint32_t consumed, const std::vector<RunPiece> &state,
                        const std::vector<RunPiece> &raw, uint32_t *bits_used) {
+  h->lvl_in = 0;
+  for (const auto &pc : state) h->lvl_in += pc.count;
+  for (const auto &pc : raw) h->lvl_in += pc.count;
   agg_status s = make_plan(h, depth, G, consumed);
   if (s) return s;
   *bits_used = h->plan.fan_bits;
@@ -2243,6 +2333,13 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     h->sample_sorted = ns >= 2 && h->h_ctrl->sample_unsorted == 0;
   }
   h->st.records_in += n;
+  if (h->st.records_in == n) {
+    // the first batch: the HBM tables' price, and the spill and levels the I/O model gives them
+    const Cost ct = cost_tables(h, n, h->spec.est_groups ? (double)h->spec.est_groups : (double)n);
+    h->st.cost_tables_ms = ct.ms;
+    h->st.cost_spilled_records = (uint64_t)std::llround(ct.spilled);
+    h->st.cost_levels = ct.levels;
+  }
   if (h->spec.policy == AGG_POLICY_HASHSORT) {
     // Hash-Sort (Sec. 4.2): every batch goes through its one table
     if (!h->hs_on) {
@@ -2277,9 +2374,15 @@ agg_status agg_consume(agg_handle *h, const void *d_records, uint64_t n) {
     // holds the partitioned batch; otherwise per-partition HBM tables.
     LdsPlan lp;
     const double G = h->spec.est_groups ? (double)h->spec.est_groups : (double)n;
-    if ((h->spec.engine == AGG_ENGINE_AUTO || h->spec.engine == AGG_ENGINE_LDS) &&
-        (h->spec.engine == AGG_ENGINE_LDS || ((!h->hot_key || h->hot_n > 0) && h->spec.preagg != 1)) &&
-        (n * h->ks.rb <= kLdsMaxInput || !h->unlimited) && lds_plan(h, n, G, &lp)) {
+    bool take_lds = false;
+    if (h->spec.engine == AGG_ENGINE_LDS) {
+      take_lds = lds_plan(h, n, G, &lp);
+    } else if (h->spec.engine == AGG_ENGINE_AUTO && lds_auto_applies(h, n) && lds_plan(h, n, G, &lp)) {
+      const Cost cl = cost_lds(h, n, lp);
+      h->st.cost_lds_ms = cl.ms;
+      take_lds = cl.ms <= h->st.cost_tables_ms;
+    }
+    if (take_lds) {
       bool applied = false;
       agg_status s = run_lds(h, (const uint8_t *)d_records, n, lp, &applied);
       if (s || applied) {

@@ -28,8 +28,9 @@ def _r16(keys, vals):
 
 
 def test_uniform_1m_10k_and_automatic_choice():
-    """The 1M-record / 10k-key workload on the on-chip engine; AUTO takes this engine when a
-    batch has many records per group (3M records, 5k keys) and not at 100 per group."""
+    """The 1M-record / 10k-key workload on the on-chip engine; AUTO takes this engine where the
+    cost model prices it below the partition-first engine (40M records over 2k keys), not at
+    100 records per group."""
     wl = workloads.uniform_small()
     rec = wl.generate()
     print("case: onchip uniform-1M-10k", flush=True)
@@ -39,11 +40,11 @@ def test_uniform_1m_10k_and_automatic_choice():
     assert st["records_spilled"] == 0 and st["levels"] == 1
     _, _, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d)
     assert st["engine"] == 2
-    wl = workloads.uniform_small().scaled(3_000_000, 5_000)
+    wl = workloads.uniform_small().scaled(40_000_000, 2_000)
     rec = wl.generate()
     k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=wl.d)
     check_against_oracle(rec, oracle_spec(wl), k, c, "auto onchip")
-    assert st["engine"] == 5
+    assert st["engine"] == 5 and st["cost_onchip_ms"] < st["cost_lds_ms"]
 
 
 @pytest.mark.parametrize("n,d", [(1, 1), (100, 7), (5000, 5000), (300_000, 2500), (3_000_000, 3000),
