@@ -267,20 +267,20 @@ __global__ void __launch_bounds__(256) k_sample_dups(const uint8_t *__restrict__
 // The frequent keys of a skewed batch: the keys of ns = kHotSample evenly spaced
 // records (all records of a smaller batch) are sorted in LDS (bitonic network),
 // each run of equal keys is one sampled key with its count, and the keys seen at
-// least kHotMin times become the frequent keys -- the most frequent first, by
-// bands of counts, at most kMaxHot.  One block.
+// least kHotMin times become the frequent keys -- the most frequent first, at
+// most kMaxHot.  One block.
 constexpr uint32_t kHotCand = 2048;  // candidate keys kept for the selection
 __global__ void __launch_bounds__(1024) k_sample_hot(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
                                                      Ctrl *ctrl) {
   extern __shared__ unsigned long long sk[];  // kHotSample keys
   __shared__ unsigned long long cand_key[kHotCand];
   __shared__ uint32_t cand_cnt[kHotCand];
-  __shared__ uint32_t ncand, nhot;
+  __shared__ uint32_t ncand;
   const uint32_t tid = threadIdx.x, N = kHotSample;
   const uint64_t ns = n < N ? n : N;
   for (uint32_t j = tid; j < N; j += blockDim.x)
     sk[j] = j < ns ? read_key(in + ((uint64_t)j * n / ns) * ks.rb, ks) : kEmpty;  // padding sorts last
-  if (tid == 0) ncand = nhot = 0;
+  if (tid == 0) ncand = 0;
   __syncthreads();
   for (uint32_t k = 2; k <= N; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -297,31 +297,59 @@ __global__ void __launch_bounds__(1024) k_sample_hot(const uint8_t *__restrict__
       __syncthreads();
     }
   }
-  // runs of equal keys: the thread holding a run's first element measures it
-  for (uint32_t i = tid; i < ns; i += blockDim.x) {
+  // runs of equal keys: each thread takes kHotSample / blockDim consecutive sorted
+  // keys and measures the runs that start there; the candidates are placed in key
+  // order (an exclusive scan of the threads' counts), the first kHotCand kept
+  const uint32_t per = N / blockDim.x, i0 = tid * per;
+  const auto run_at = [&](uint32_t i) -> uint32_t {  // length of the run starting at i (0: none)
+    if (i >= ns) return 0;
     const unsigned long long key = sk[i];
-    if (key >= kClosed || (i > 0 && sk[i - 1] == key)) continue;
+    if (key >= kClosed || (i > 0 && sk[i - 1] == key)) return 0;
     uint32_t e = i + 1;
     while (e < ns && sk[e] == key) ++e;
-    if (e - i < kHotMin) continue;
-    const uint32_t c = atomicAdd(&ncand, 1u);
-    if (c < kHotCand) {
-      cand_key[c] = key;
-      cand_cnt[c] = e - i;
-    }
+    return e - i;
+  };
+  uint32_t mine = 0;
+  for (uint32_t i = i0; i < i0 + per; ++i) mine += run_at(i) >= kHotMin ? 1u : 0u;
+  uint32_t total;
+  uint32_t at = block_exclusive_scan(mine, &total, reinterpret_cast<uint32_t *>(cand_cnt));
+  for (uint32_t i = i0; i < i0 + per && at < kHotCand; ++i) {
+    const uint32_t len = run_at(i);
+    if (len < kHotMin) continue;
+    cand_key[at] = sk[i];
+    cand_cnt[at] = len;
+    ++at;
   }
+  if (tid == 0) ncand = total;
   __syncthreads();
+  // the candidates by count, most frequent first, ties by key (a bitonic network
+  // over kHotCand entries; empty ones sort last), so that the same batch always
+  // yields the same frequent keys
   const uint32_t nc = ncand < kHotCand ? ncand : kHotCand;
-  const uint32_t bands[6] = {~0u, 512, 128, 32, 8, kHotMin};
-  for (int band = 1; band < 6; ++band) {
-    for (uint32_t c = tid; c < nc; c += blockDim.x) {
-      if (cand_cnt[c] < bands[band] || cand_cnt[c] >= bands[band - 1]) continue;
-      const uint32_t pos = atomicAdd(&nhot, 1u);
-      if (pos < kMaxHot) ctrl->sample_hot[pos] = cand_key[c];
+  for (uint32_t c = nc + tid; c < kHotCand; c += blockDim.x) cand_cnt[c] = 0;
+  __syncthreads();
+  const auto before = [&](uint32_t a, uint32_t b) {  // entry a sorts before entry b
+    return cand_cnt[a] != cand_cnt[b] ? cand_cnt[a] > cand_cnt[b] : cand_key[a] < cand_key[b];
+  };
+  for (uint32_t k = 2; k <= kHotCand; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = tid; i < kHotCand; i += blockDim.x) {
+        const uint32_t q = i ^ j;
+        if (q > i && before(q, i) == ((i & k) == 0)) {
+          const unsigned long long tk = cand_key[i];
+          cand_key[i] = cand_key[q];
+          cand_key[q] = tk;
+          const uint32_t tc = cand_cnt[i];
+          cand_cnt[i] = cand_cnt[q];
+          cand_cnt[q] = tc;
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  if (tid == 0) ctrl->sample_hot_n = nhot < kMaxHot ? nhot : kMaxHot;
+  const uint32_t nh = nc < kMaxHot ? nc : kMaxHot;
+  for (uint32_t c = tid; c < nh; c += blockDim.x) ctrl->sample_hot[c] = cand_key[c];
+  if (tid == 0) ctrl->sample_hot_n = nh;
 }
 
 __global__ void k_table_init(uint64_t *arena, uint64_t nslots, KSpec ks) {
