@@ -67,6 +67,8 @@ def parse():
                     help="runs of the CPU oracle over the whole input (median reported; 0 = skip)")
     ap.add_argument("--requests", type=int, default=120, help="served: requests in the trace")
     ap.add_argument("--load", type=float, default=0.8, help="served: offered load vs the plain path's capacity")
+    ap.add_argument("--loads", default="", help="served: comma-separated offered loads to sweep (the first is reported "
+                                                  "at the top level; default: --load alone)")
     ap.add_argument("--inflight", type=int, default=6, help="served: requests running at once (the library accepts at most 6)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy kernel (counter calibration for the traffic figure)")
@@ -546,6 +548,8 @@ def bench_served(args):
             lat, rows_ok, runs = [], True, []
             for i, w in enumerate(reqs):
                 res, info = srv.wait(tickets[i])
+                if (i + 1) % 100 == 0:
+                    log(args, f"[bench]   {i + 1} of {len(reqs)} requests done")
                 lat.append(info["latency_ms"])
                 runs.append(info["run_ms"])
                 rows_ok &= int(res.n_rows) == w.d
@@ -565,31 +569,48 @@ def bench_served(args):
     _, plain_busy, ok0, _, service = run_trace(1, zeros)
     ok3 = True
     cap_rps = len(reqs) / plain_busy
-    gaps = np.array([w.extra["gap"] for w in reqs]) / (args.load * cap_rps)
-    arrivals = list(np.cumsum(gaps) - gaps[0])
-    log(args, f"[bench] plain capacity {cap_rps:.1f} req/s ({plain_busy:.2f}s back to back); load {args.load}")
-    log(args, "[bench] plain path, Poisson arrivals")
-    lat_p, span_p, ok1, _, _ = run_trace(1, arrivals)
-    log(args, "[bench] served, Poisson arrivals")
-    lat_s, span_s, ok2, st_s, _ = run_trace(args.inflight, arrivals)
+    loads = [float(x) for x in args.loads.split(",") if x.strip()] if args.loads else [args.load]
     pct = lambda a, q: float(np.percentile(a, q))
+    sweep = []
+    for load in loads:
+        gaps = np.array([w.extra["gap"] for w in reqs]) / (load * cap_rps)
+        arrivals = list(np.cumsum(gaps) - gaps[0])
+        log(args, f"[bench] plain capacity {cap_rps:.1f} req/s ({plain_busy:.2f}s back to back); load {load}")
+        log(args, "[bench] plain path, Poisson arrivals")
+        lat_p, span_p, ok1, _, _ = run_trace(1, arrivals)
+        log(args, "[bench] served, Poisson arrivals")
+        lat_s, span_s, ok2, st_s, _ = run_trace(args.inflight, arrivals)
+        log(args, f"[bench] load {load}: served p50/p99 {pct(lat_s, 50):.1f}/{pct(lat_s, 99):.1f} ms, "
+                  f"{n_total / span_s / 1e9:.2f} G rec/s; plain p50/p99 {pct(lat_p, 50):.1f}/{pct(lat_p, 99):.1f} ms, "
+                  f"{n_total / span_p / 1e9:.2f} G rec/s")
+        sweep.append({
+            "offered_load": load,
+            "served": {"p50_ms": round(pct(lat_s, 50), 3), "p99_ms": round(pct(lat_s, 99), 3),
+                       "records_per_s": round(n_total / span_s, 1), "makespan_s": round(span_s, 3),
+                       "peak_running": st_s["peak_running"], "pool_peak_bytes": st_s["pool_peak"]},
+            "plain": {"p50_ms": round(pct(lat_p, 50), 3), "p99_ms": round(pct(lat_p, 99), 3),
+                      "records_per_s": round(n_total / span_p, 1), "makespan_s": round(span_p, 3)},
+            "rows_ok": bool(ok1 and ok2),
+            "span_s": span_s,
+        })
+    top = sweep[0]
+    span_s = top.pop("span_s")
+    for e in sweep[1:]:
+        e.pop("span_s")
     out = {
         "metric": METRIC, "value": round(n_total / span_s, 1), "unit": "records/s", "n_gpus": 1, "steps": 1,
         "warmup": 1, "ms_per_step": round(1000 * span_s, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"served-{len(reqs)}-requests", "records": n_total, "pool_bytes": pool,
-                   "inflight": args.inflight, "offered_load": args.load,
+                   "inflight": args.inflight, "offered_load": top["offered_load"],
                    "arrivals": "Poisson at offered_load x plain-path capacity"},
-        "served": {"p50_ms": round(pct(lat_s, 50), 3), "p99_ms": round(pct(lat_s, 99), 3),
-                   "records_per_s": round(n_total / span_s, 1), "makespan_s": round(span_s, 3),
-                   "peak_running": st_s["peak_running"], "pool_peak_bytes": st_s["pool_peak"]},
-        "plain": {"p50_ms": round(pct(lat_p, 50), 3), "p99_ms": round(pct(lat_p, 99), 3),
-                  "records_per_s": round(n_total / span_p, 1), "makespan_s": round(span_p, 3),
-                  "back_to_back_s": round(plain_busy, 3),
-                  "service_p50_ms": round(pct(service, 50), 3), "service_p99_ms": round(pct(service, 99), 3)},
+        "served": top["served"],
+        "plain": dict(top["plain"], back_to_back_s=round(plain_busy, 3),
+                      service_p50_ms=round(pct(service, 50), 3), service_p99_ms=round(pct(service, 99), 3)),
         "capacity": {"plain_records_per_s": round(n_total / plain_busy, 1),
                      "note": "plain path, all requests queued at t=0"},
-        "rows_ok": bool(ok0 and ok1 and ok2 and ok3),
+        "load_sweep": sweep,
+        "rows_ok": bool(ok0 and all(e["rows_ok"] for e in sweep)),
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

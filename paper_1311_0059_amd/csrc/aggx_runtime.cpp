@@ -15,6 +15,8 @@
 #include <cstring>
 #include <iterator>
 #include <map>
+#include <queue>
+#include <set>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -190,44 +192,51 @@ constexpr uint64_t kMaxTableFrames = (1ull << 31) / kFrameSlots;  // a table's s
 static_assert(sizeof(MigDesc) * kMigMax <= (uint64_t)kMaxFan * 4, "migration descriptors fit the pack area");
 
 struct FramePool {
-  std::map<uint64_t, uint64_t> free_runs;  // offset -> length, in frames
+  std::map<uint64_t, uint64_t> free_runs;          // offset -> length, in frames
+  std::set<std::pair<uint64_t, uint64_t>> by_len;  // (length, offset) of the same runs
   uint64_t frames = 0;
 
   void init(uint64_t n) {
     frames = n;
     free_runs.clear();
-    if (n) free_runs[0] = n;
+    by_len.clear();
+    if (n) add(0, n);
+  }
+  void add(uint64_t off, uint64_t len) {
+    free_runs[off] = len;
+    by_len.insert({len, off});
+  }
+  void drop(std::map<uint64_t, uint64_t>::iterator it) {
+    by_len.erase({it->second, it->first});
+    free_runs.erase(it);
   }
   // the smallest free run of at least `len` frames, cut from its front (~0 when none)
   uint64_t alloc(uint64_t len) {
-    auto best = free_runs.end();
-    for (auto it = free_runs.begin(); it != free_runs.end(); ++it)
-      if (it->second >= len && (best == free_runs.end() || it->second < best->second)) best = it;
-    if (best == free_runs.end()) return ~0ULL;
-    const uint64_t off = best->first, rest = best->second - len;
-    free_runs.erase(best);
-    if (rest) free_runs[off + len] = rest;
+    auto b = by_len.lower_bound({len, 0});
+    if (b == by_len.end()) return ~0ULL;
+    const uint64_t off = b->second, rest = b->first - len;
+    drop(free_runs.find(off));
+    if (rest) add(off + len, rest);
     return off;
   }
-  bool can_alloc(uint64_t len) const {
-    for (const auto &r : free_runs)
-      if (r.second >= len) return true;
-    return false;
-  }
+  bool can_alloc(uint64_t len) const { return by_len.lower_bound({len, 0}) != by_len.end(); }
   void release(uint64_t off, uint64_t len) {
     auto next = free_runs.lower_bound(off);
     if (next != free_runs.end() && next->first == off + len) {
       len += next->second;
-      next = free_runs.erase(next);
+      auto gone = next++;
+      drop(gone);
     }
     if (next != free_runs.begin()) {
       auto prev = std::prev(next);
       if (prev->first + prev->second == off) {
-        prev->second += len;
+        const uint64_t poff = prev->first, plen = prev->second;
+        drop(prev);
+        add(poff, plen + len);
         return;
       }
     }
-    free_runs[off] = len;
+    add(off, len);
   }
 };
 
@@ -802,43 +811,50 @@ agg_status dd_grow_or_spill(agg_handle *h, const std::vector<uint32_t> &full) {
     pl.meta[x].nslots = 0;
     pl.meta[x].cap = 0;
   };
+  // the victims, largest first (by frames, then groups, then the lower index)
+  const auto larger = [&](uint32_t a, uint32_t b) {  // a ranks below b in the heap
+    if (pl.meta[a].nslots != pl.meta[b].nslots) return pl.meta[a].nslots < pl.meta[b].nslots;
+    if (groups[a] != groups[b]) return groups[a] < groups[b];
+    return a > b;
+  };
+  std::priority_queue<uint32_t, std::vector<uint32_t>, decltype(larger)> heap(larger);
+  for (uint32_t q = 0; q < pl.F; ++q)
+    if (!pl.meta[q].spilled && !grown[q]) heap.push(q);
   for (uint32_t p : pending) {
     if (pl.meta[p].spilled) continue;  // already a victim of another's growth
     const uint64_t len2 = 2 * len_of(pl.meta[p]);
     bool self = len2 > kMaxTableFrames;  // a table may not pass 2^31 slots
     while (!self && !h->dd_pool.can_alloc(len2)) {
-      int v = -1;
-      for (uint32_t q = 0; q < pl.F; ++q) {
-        if (pl.meta[q].spilled || grown[q]) continue;
-        if (v < 0 || pl.meta[q].nslots > pl.meta[v].nslots ||
-            (pl.meta[q].nslots == pl.meta[v].nslots && groups[q] > groups[v]))
-          v = (int)q;
-      }
-      if (v < 0 || (uint32_t)v == p) {
+      while (!heap.empty() && (pl.meta[heap.top()].spilled || grown[heap.top()])) heap.pop();
+      if (heap.empty() || heap.top() == p) {
         self = true;
         break;
       }
-      give_up((uint32_t)v);
+      const uint32_t v = heap.top();
+      heap.pop();
+      give_up(v);
     }
     if (self) give_up(p);
     else grow(p);
   }
-  // the victims' states out first (their frames may be a grown table's new block)
-  for (size_t i = 0; i < spill_p.size(); ++i) {
-    const uint32_t x = spill_p[i];
+  // the victims' states out first (their frames may be a grown table's new block), all
+  // into one region of the run
+  uint64_t total = 0;
+  for (uint32_t x : spill_p) total += groups[x];
+  if (!spill_p.empty()) {
     uint8_t *dst = nullptr;
-    const uint64_t g = groups[x];
-    if (!h->next.reserve(std::max<uint64_t>(g, 1) * h->W8, &dst)) return AGG_E_NOMEM;
+    if (!h->next.reserve(std::max<uint64_t>(total, 1) * h->W8, &dst)) return AGG_E_NOMEM;
     HCK(h, launch_u64_set(h->stream, &h->d_ctrl->state_ctr, 1, 0));
-    HCK(h, launch_extract(h->stream, h->d_arena, spill_old[i].base, spill_old[i].nslots, h->ks, h->d_ctrl,
-                          spill_target(h, nullptr, dst)));
+    for (size_t i = 0; i < spill_p.size(); ++i)
+      HCK(h, launch_extract(h->stream, h->d_arena, spill_old[i].base, spill_old[i].nslots, h->ks, h->d_ctrl,
+                            spill_target(h, nullptr, dst)));
     agg_status s = read_ctrl(h);
     if (s) return s;
-    if (h->h_ctrl->state_ctr != g) return AGG_E_INTERNAL;
-    h->next.commit(dst, g, h->W8, true);
-    h->st.states_spilled += g;
-    h->st.bytes_spilled_d2h += g * h->W8;
-    if (pl.level == 0) h->st.partitions_spilled += 1;
+    if (h->h_ctrl->state_ctr != total) return AGG_E_INTERNAL;  // the group counters count every key inserted
+    h->next.commit(dst, total, h->W8, true);
+    h->st.states_spilled += total;
+    h->st.bytes_spilled_d2h += total * h->W8;
+    if (pl.level == 0) h->st.partitions_spilled += (uint32_t)spill_p.size();
   }
   agg_status s = dd_migrate(h, descs, desc_p);
   if (s) return s;
