@@ -548,7 +548,7 @@ def bench_served(args):
             lat, rows_ok, runs = [], True, []
             for i, w in enumerate(reqs):
                 res, info = srv.wait(tickets[i])
-                if (i + 1) % 100 == 0:
+                if (i + 1) % 25 == 0:
                     log(args, f"[bench]   {i + 1} of {len(reqs)} requests done")
                 lat.append(info["latency_ms"])
                 runs.append(info["run_ms"])

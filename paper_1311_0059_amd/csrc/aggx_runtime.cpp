@@ -2074,15 +2074,18 @@ agg_status hs_finish(agg_handle *h) {
   return AGG_OK;
 }
 
-// The fallback: a recursion level's run set by Hash-Sort instead of another hybrid-hash level.
-agg_status hs_run_set(agg_handle *h, uint32_t depth, double G, const RunSet &in) {
+// The fallback: runs (states and raw records) aggregated by Hash-Sort instead of
+// another hybrid-hash level.
+agg_status hs_pieces(agg_handle *h, uint32_t depth, double G, const std::vector<RunPiece> &state,
+                     const std::vector<RunPiece> &raw) {
+  h->st.hashsort_fallbacks += 1;
   agg_status s = hs_begin(h, depth, G);
   if (s) return s;
-  for (const auto &pc : in.state) {
+  for (const auto &pc : state) {
     s = hs_feed(h, 1, pc.dev, pc.count);
     if (s) return s;
   }
-  for (const auto &pc : in.raw) {
+  for (const auto &pc : raw) {
     s = hs_feed(h, 0, pc.dev, pc.count);
     if (s) return s;
   }
@@ -2144,10 +2147,14 @@ agg_status finish_impl(agg_handle *h) {
   uint32_t depth = 0;
   // The fallback of Sec. 4.3 (Phase 2): a run that kept more than 80% of the input
   // it was partitioned from, or a recursion deeper than a sort-based pass structure
-  // would go, is aggregated by Hash-Sort instead.  Here all of a level's spill is
-  // one run, and a sort-based pass structure takes two levels (run generation, then
-  // one merge of all runs), so the third level is the deepest hybrid-hash one.
-  bool use_hs = (double)(h->next.n_raw + h->next.n_state) > 0.8 * (double)h->st.records_in;
+  // would go, is aggregated by Hash-Sort instead.  Here the runs partitioned from a
+  // level's input are the sub-runs of its grace split (and a level's whole spill,
+  // which the next level takes as one run); a sort-based pass structure takes two
+  // levels (run generation, then one merge of all runs), so the third level is the
+  // deepest hybrid-hash one.  (Level 0's spill is not tested: under a budget far
+  // below the groups most of the input spills by design, and the grace split that
+  // follows divides it.)
+  bool use_hs = false;
   // Phase 2: the spilled partitions are re-aggregated, one level at a time
   while (!h->next.empty()) {
     if (++depth >= AGG_MAX_LEVELS || consumed >= 64) return AGG_E_INTERNAL;
@@ -2157,8 +2164,7 @@ agg_status finish_impl(agg_handle *h) {
     const uint64_t fed_bytes = in.n_raw * h->ks.rb + in.n_state * h->W8;
     G = std::max(1.0, G * 1.05);
     if (use_hs || depth >= kSortLevels) {
-      h->st.hashsort_fallbacks += 1;
-      s = hs_run_set(h, depth, G, in);
+      s = hs_pieces(h, depth, G, in.state, in.raw);
       h->st.bytes_reloaded_h2d += fed_bytes;
       in.release();
       if (s) return s;
@@ -2194,6 +2200,13 @@ agg_status finish_impl(agg_handle *h) {
         if (roff[d1] > roff[d0]) gr.push_back({rbase + roff[d0] * h->ks.rb, roff[d1] - roff[d0]});
         if (soff[d1] > soff[d0]) gs.push_back({sbase + soff[d0] * h->W8, soff[d1] - soff[d0]});
         if (gr.empty() && gs.empty()) continue;
+        const uint64_t grp = (roff[d1] - roff[d0]) + (soff[d1] - soff[d0]);
+        if ((double)grp > 0.8 * (double)fed) {
+          // the split left most of the run in these sub-runs (one frequent key's records,
+          // or keys the hash does not tell apart): Hash-Sort takes them
+          s = hs_pieces(h, depth, g_bin * (d1 - d0), gs, gr);
+          continue;
+        }
         s = hybrid_pass(h, depth, g_bin * (d1 - d0), consumed + bg, gs, gr, &used);
         used_max = std::max(used_max, used);
       }

@@ -7,8 +7,8 @@ merged range by range.  The paper's heavy-hitter set (one key with most of the
 records, every other key once) is where it collapses most; a uniform set with
 far more keys than the table holds makes many runs and ranges.
 
-As the fallback, a hybrid-hash level whose spill kept more than 80% of its input
-(a budget far below the groups) hands the run to Hash-Sort.
+As the fallback, a sub-run of a level's grace split that kept more than 80% of
+the run it was split from (a frequent key spilled whole) goes to Hash-Sort.
 """
 import numpy as np
 import pytest
@@ -73,17 +73,26 @@ def test_policy_r24_reserved_keys_batches():
     assert st["hashsort_runs"] >= 2
 
 
-@pytest.mark.parametrize("policy", ["destage", "prepart"])
-def test_fallback_when_the_spill_does_not_shrink(policy):
-    """A budget far below the groups: level 0 spills more than 80% of the input, and the
-    next level goes to Hash-Sort instead of another hybrid-hash level."""
-    wl = workloads.uniform_spill().scaled(2_000_000, 1_000_000)
-    rec = wl.generate()
-    print(f"case: hashsort fallback {policy}", flush=True)
-    k, c, st = run_lib(rec, **lib_spec_args(wl), budget=2 * MIB, est_groups=wl.d, policy=policy, engine="tables")
-    check_against_oracle(rec, oracle_spec(wl), k, c, f"hashsort fallback {policy}")
-    assert st["records_spilled_l0"] > 0.8 * rec.size
-    assert st["hashsort_fallbacks"] == 1 and st["hashsort_runs"] >= 2 and st["levels"] == 2
+def test_fallback_when_a_split_does_not_divide_the_run():
+    """Pre-Partitioning fills its tables with the keys of the first part of the input; a
+    frequent key that only arrives afterwards is spilled whole, with a few hundred thousand
+    other keys.  The next level's grace split cannot divide that key's records (over 80% of
+    its input), so that sub-run goes to Hash-Sort, whose table collapses the key at once."""
+    rng = np.random.default_rng(workloads.SEED_BASE + 61)
+    pool = np.unique(rng.integers(0, 2**63 - 2, size=450_000, dtype=np.int64).astype(np.uint64))
+    first, late, heavy = pool[:300_000], pool[300_000:400_000], pool[400_000]
+    part1 = rng.permutation(np.repeat(first, 2))
+    part2 = rng.permutation(np.concatenate([np.full(5_000_000, heavy, dtype=np.uint64), np.repeat(late, 2)]))
+    rec = np.empty(part1.size + part2.size, dtype=datagen.R16)
+    rec["key"] = np.concatenate([part1, part2])
+    rec["v"] = rng.integers(-10**6, 10**6, size=rec.size)
+    spec = {"record_bytes": 16, "keys": [(0, "u64")], "aggs": workloads.AGGS_R16_ALL}
+    print("case: hashsort fallback after a split", flush=True)
+    k, c, st = run_lib(rec, 16, spec["keys"], spec["aggs"], budget=4 * MIB, est_groups=400_001, policy="prepart",
+                       engine="tables")
+    check_against_oracle(rec, spec, k, c, "hashsort fallback")
+    assert st["records_spilled_l0"] > 5_000_000
+    assert st["hashsort_fallbacks"] >= 1 and st["levels"] >= 2
 
 
 def test_first_rows_under_hashsort():
