@@ -547,16 +547,19 @@ def bench_served(args):
             th.join()
             lat, rows_ok, runs = [], True, []
             for i, w in enumerate(reqs):
-                res, info = srv.wait(tickets[i])
+                try:
+                    res, info = srv.wait(tickets[i])
+                except P.AggError:
+                    log(args, f"[bench] request {i} failed: {w.n} records, {w.d} keys, budget {w.budget}")
+                    raise
                 if (i + 1) % 25 == 0:
                     log(args, f"[bench]   {i + 1} of {len(reqs)} requests done")
                 lat.append(info["latency_ms"])
                 runs.append(info["run_ms"])
                 rows_ok &= int(res.n_rows) == w.d
+                srv.release(tickets[i])  # its rows are counted: give its result memory back
             makespan = time.perf_counter() - t0
             st = srv.stats()
-            for t in tickets:
-                srv.release(t)
         return np.array(lat), makespan, rows_ok, st, np.array(runs)
 
     zeros = [0.0] * len(reqs)

@@ -236,6 +236,7 @@ typedef struct agg_stats {
   uint64_t cost_spilled_records;
   uint32_t cost_levels;
   uint32_t reserved_stats4;
+  uint64_t pinned_peak_bytes;   /* most pinned host memory the query's spill runs held at once (segments) */
 } agg_stats;
 
 /* Start one GROUP BY query (Sec. 3.1) under the memory budget M of Sec. 3.2

@@ -109,6 +109,7 @@ class Stats(ctypes.Structure):
         ("cost_spilled_records", ctypes.c_uint64),
         ("cost_levels", ctypes.c_uint32),
         ("reserved_stats4", ctypes.c_uint32),
+        ("pinned_peak_bytes", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:

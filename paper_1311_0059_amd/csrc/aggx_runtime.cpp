@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -65,6 +66,7 @@ struct PinnedSeg {
 
 std::mutex g_cache_mu;
 std::vector<PinnedSeg> g_pinned_free;
+std::atomic<uint64_t> g_pinned_live{0};  // bytes of pinned segments allocated and not freed
 struct DevBlock {
   void *p;
   uint64_t bytes;
@@ -86,19 +88,51 @@ bool pinned_get(uint64_t min_bytes, PinnedSeg *out) {
   }
   PinnedSeg s;
   s.bytes = std::max(round_up(min_bytes, 1 << 20), kPinnedSegment);
-  if (hipHostMalloc((void **)&s.host, s.bytes, hipHostMallocMapped) != hipSuccess) return false;
+  if (hipHostMalloc((void **)&s.host, s.bytes, hipHostMallocMapped) != hipSuccess) {
+    // the cached segments are all too small: give them back and try once more
+    std::vector<PinnedSeg> drop;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      drop.swap(g_pinned_free);
+    }
+    for (auto &d : drop) {
+      (void)hipHostFree(d.host);
+      g_pinned_live -= d.bytes;
+    }
+    if (hipHostMalloc((void **)&s.host, s.bytes, hipHostMallocMapped) != hipSuccess) {
+      if (getenv("AGGX_DEBUG"))
+        fprintf(stderr, "aggx: pinned host segment of %llu bytes not available (%llu bytes of segments live)\n",
+                (unsigned long long)s.bytes, (unsigned long long)g_pinned_live.load());
+      return false;
+    }
+  }
+  g_pinned_live += s.bytes;
   if (hipHostGetDevicePointer((void **)&s.dev, s.host, 0) != hipSuccess) {
     (void)hipHostFree(s.host);
+    g_pinned_live -= s.bytes;
     return false;
   }
   *out = s;
   return true;
 }
 
+// Freed segments are kept for reuse up to kPinnedCacheMax bytes in all; beyond
+// that they are given back (pinned memory is host memory no one else can use).
+constexpr uint64_t kPinnedCacheMax = 16ull << 30;
+
 void pinned_put(const PinnedSeg &s) {
   if (!s.host) return;
-  std::lock_guard<std::mutex> lk(g_cache_mu);
-  g_pinned_free.push_back(s);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    uint64_t cached = 0;
+    for (const auto &c : g_pinned_free) cached += c.bytes;
+    if (cached + s.bytes <= kPinnedCacheMax) {
+      g_pinned_free.push_back(s);
+      return;
+    }
+  }
+  (void)hipHostFree(s.host);
+  g_pinned_live -= s.bytes;
 }
 
 // Device blocks outside the budget (results) and library-owned budget pools.
@@ -123,7 +157,9 @@ bool dev_get(uint64_t bytes, void **p) {
     drop.swap(g_dev_free);
   }
   for (auto &b : drop) (void)hipFree(b.p);
-  return hipMalloc(p, bytes) == hipSuccess;
+  if (hipMalloc(p, bytes) == hipSuccess) return true;
+  if (getenv("AGGX_DEBUG")) fprintf(stderr, "aggx: device block of %llu bytes not available\n", (unsigned long long)bytes);
+  return false;
 }
 
 void dev_put(void *p, uint64_t bytes) {
@@ -151,6 +187,11 @@ struct RunSet {
 
   bool reserve(uint64_t bytes, uint8_t **dev) {
     if (segs.empty() || segs.back().bytes - cursor < bytes) {
+      // a last segment that holds nothing yet goes back before a larger one is taken
+      if (!segs.empty() && cursor == 0) {
+        pinned_put(segs.back());
+        segs.pop_back();
+      }
       PinnedSeg s;
       if (!pinned_get(bytes, &s)) return false;
       segs.push_back(s);
@@ -179,9 +220,11 @@ struct RunSet {
     n_raw = n_state = 0;
   }
   bool empty() const { return n_raw == 0 && n_state == 0; }
-  // Keep the region just reserved out of later reservations without making it a
-  // piece (a launch's spill that is fed again rather than kept).
-  void claim(uint64_t bytes) { cursor += round_up(bytes, 256); }
+  uint64_t held() const {
+    uint64_t b = 0;
+    for (const auto &s : segs) b += s.bytes;
+    return b;
+  }
 };
 
 // Dynamic Destaging's memory pool (Sec. 4.3.3): the arena's slots in frames of
@@ -324,6 +367,9 @@ struct agg_handle {
   RunSet hs_runs;
   std::vector<const uint8_t *> hs_run_host;
   RunSet hs_tmp[2];
+  // Dynamic Destaging: what a launch that met full tables spilled is copied aside
+  // here (alternately) and fed again
+  RunSet dd_tmp[2];
   // Dynamic Destaging with a frame pool (the current level's plan uses it)
   bool dd_active = false;
   FramePool dd_pool;
@@ -331,6 +377,13 @@ struct agg_handle {
 };
 
 namespace {
+
+// The pinned host memory this handle's runs hold now (plus `extra`), kept as a peak.
+void note_pinned(agg_handle *h, uint64_t extra = 0) {
+  const uint64_t b = h->next.held() + h->hs_runs.held() + h->hs_tmp[0].held() + h->hs_tmp[1].held() +
+                     h->dd_tmp[0].held() + h->dd_tmp[1].held() + extra;
+  h->st.pinned_peak_bytes = std::max<uint64_t>(h->st.pinned_peak_bytes, b);
+}
 
 agg_status dev_fail(agg_handle *h, hipError_t e, const char *what) {
   if (getenv("AGGX_DEBUG")) fprintf(stderr, "aggx: %s failed: %s\n", what, hipGetErrorString(e));
@@ -691,6 +744,7 @@ agg_status dd_spill(agg_handle *h, uint32_t p, uint64_t groups) {
   PartMeta &m = h->plan.meta[p];
   uint8_t *dst = nullptr;
   if (!h->next.reserve(std::max<uint64_t>(groups, 1) * h->W8, &dst)) return AGG_E_NOMEM;
+  note_pinned(h);
   HCK(h, launch_u64_set(h->stream, &h->d_ctrl->state_ctr, 1, 0));
   HCK(h, launch_extract(h->stream, h->d_arena, m.base, m.nslots, h->ks, h->d_ctrl, spill_target(h, nullptr, dst)));
   agg_status s = read_ctrl(h);
@@ -844,6 +898,7 @@ agg_status dd_grow_or_spill(agg_handle *h, const std::vector<uint32_t> &full) {
   if (!spill_p.empty()) {
     uint8_t *dst = nullptr;
     if (!h->next.reserve(std::max<uint64_t>(total, 1) * h->W8, &dst)) return AGG_E_NOMEM;
+    note_pinned(h);
     HCK(h, launch_u64_set(h->stream, &h->d_ctrl->state_ctr, 1, 0));
     for (size_t i = 0; i < spill_p.size(); ++i)
       HCK(h, launch_extract(h->stream, h->d_arena, spill_old[i].base, spill_old[i].nslots, h->ks, h->d_ctrl,
@@ -924,9 +979,11 @@ agg_status run_stream(agg_handle *h, const uint8_t *in, uint64_t n, int kind) {
     const uint8_t *src = in + off * in_bytes;
     uint64_t cnt = c;
     bool again = false;  // feeding what the last launch spilled, after its full tables grew
+    int t = 0;
     for (;;) {
       uint8_t *dst = nullptr;
       if (!h->next.reserve(cnt * in_bytes, &dst)) return AGG_E_NOMEM;
+      note_pinned(h);
       HCK(h, launch_u64_set(h->stream, kind == 0 ? &h->d_ctrl->raw_ctr : &h->d_ctrl->state_ctr, 1, 0));
       KSpill sp = spill_target(h, kind == 0 ? dst : nullptr, kind == 0 ? nullptr : dst);
       // level-0 raw records come from agg_consume, whose batch follows the records counted before it
@@ -955,15 +1012,23 @@ agg_status run_stream(agg_handle *h, const uint8_t *in, uint64_t n, int kind) {
       if (h->plan.level == 0 && kind == 0 && !again)
         h->st.first_full_record = std::min<uint64_t>(h->st.first_full_record, h->h_ctrl->first_full);
       if (grow && h->h_ctrl->any_ovf) {
-        // Dynamic Destaging: full tables grow (or partitions are spilled), then what this
-        // launch spilled is fed again; its region is kept out of the run
-        if (got) h->next.claim(got * in_bytes);
+        // Dynamic Destaging: what this launch spilled is copied aside (its region in the
+        // run is not kept), full tables grow or partitions are spilled, and the copy is
+        // fed again
+        uint8_t *aside = nullptr;
+        if (got) {
+          if (!h->dd_tmp[t].reserve(got * in_bytes, &aside)) return AGG_E_NOMEM;
+          note_pinned(h);
+          HCK(h, hipMemcpyAsync(aside, dst, got * in_bytes, hipMemcpyDefault, h->stream));
+          HCK(h, hipStreamSynchronize(h->stream));
+        }
         s = handle_overflow(h, true);
         if (s) return s;
-        if (got == 0) break;
-        src = dst;
+        if (!got) break;
+        src = aside;
         cnt = got;
         again = true;
+        t ^= 1;
         continue;
       }
       h->next.commit(dst, got, in_bytes, kind == 1);
@@ -977,6 +1042,8 @@ agg_status run_stream(agg_handle *h, const uint8_t *in, uint64_t n, int kind) {
       if (s) return s;
       break;
     }
+    h->dd_tmp[0].release();
+    h->dd_tmp[1].release();
   }
   return AGG_OK;
 }
@@ -1234,6 +1301,7 @@ agg_status lds_run_partitions(agg_handle *h, const uint8_t *in, uint64_t n, cons
   HCK(h, hipEventRecord(h->ev3, h->stream));
   uint8_t *dst = nullptr;
   if (!h->next.reserve(std::max<uint64_t>(records, 1) * h->ks.rb, &dst)) return AGG_E_NOMEM;
+  note_pinned(h);
   // rows per partition: at most its slot count per sweep
   agg_status s = ensure_result_cap(h, h->r_rows + std::min<uint64_t>(records, ((uint64_t)d_n << lp.sbits) * lp.nslots) + 1);
   if (s) return s;
@@ -1665,6 +1733,7 @@ agg_status run_owner_stream(agg_handle *h, const uint8_t *in, uint64_t n) {
     const uint64_t g = std::min(group, n - off);
     uint8_t *dst = nullptr;
     if (!h->next.reserve(g * rb, &dst)) return AGG_E_NOMEM;
+    note_pinned(h);
     HCK(h, launch_u64_set(h->stream, &h->d_ctrl->raw_ctr, 1, 0));
     const KSpill sp = spill_target(h, dst, nullptr);
     HCK(h, hipEventRecord(h->ev0, h->stream));
@@ -1720,6 +1789,7 @@ agg_status demote_lds(agg_handle *h, uint64_t n_next) {
   if (s) return s;
   uint8_t *dst = nullptr;
   if (!h->next.reserve(std::max<uint64_t>(h->r_rows, 1) * h->W8, &dst)) return AGG_E_NOMEM;
+  note_pinned(h);
   KLevel lv;
   lv.level = 0;
   lv.digit_shift = h->plan.digit_shift;
@@ -1789,12 +1859,14 @@ agg_status grace_split(agg_handle *h, const RunSet &in, uint32_t consumed, uint3
     PinnedSeg seg;
     if (!pinned_get(in.n_raw * h->ks.rb, &seg)) return AGG_E_NOMEM;
     sub.segs.push_back(seg);
+    note_pinned(h, sub.held());
     *raw_base = seg.dev;
   }
   if (in.n_state) {
     PinnedSeg seg;
     if (!pinned_get(in.n_state * h->W8, &seg)) return AGG_E_NOMEM;
     sub.segs.push_back(seg);
+    note_pinned(h, sub.held());
     *st_base = seg.dev;
   }
   for (uint32_t d = 0; d < F; ++d) {
@@ -1908,6 +1980,7 @@ agg_status hs_emit_run(agg_handle *h) {
   if (G) {
     uint8_t *dst = nullptr;
     if (!h->hs_runs.reserve(G * W8, &dst)) return AGG_E_NOMEM;
+    note_pinned(h);
     uint8_t *aux = reinterpret_cast<uint8_t *>(h->d_arena) + round_up(S * W8, 256);
     uint32_t *counts = reinterpret_cast<uint32_t *>(aux);
     auto *offsets = reinterpret_cast<unsigned long long *>(aux + round_up(4 * hs_tiles(S), 256));
@@ -1948,6 +2021,7 @@ agg_status hs_feed(agg_handle *h, int kind, const uint8_t *in, uint64_t n) {
     while (cnt) {
       uint8_t *dst = nullptr;
       if (!h->hs_tmp[t].reserve(cnt * in_bytes, &dst)) return AGG_E_NOMEM;
+      note_pinned(h);
       HCK(h, launch_u64_set(h->stream, kind == 0 ? &h->d_ctrl->raw_ctr : &h->d_ctrl->state_ctr, 1, 0));
       KSpill sp = spill_target(h, kind == 0 ? dst : nullptr, kind == 0 ? nullptr : dst);
       HCK(h, hipEventRecord(h->ev0, h->stream));
@@ -2017,6 +2091,7 @@ agg_status hs_range(agg_handle *h, uint64_t lo, uint64_t hi, bool to_end) {
   if (s) return s;
   uint8_t *dst = nullptr;  // states of keys that found no slot within the probe limit (not expected)
   if (!h->hs_tmp[0].reserve(n_w * W8, &dst)) return AGG_E_NOMEM;
+  note_pinned(h);
   KLevel lv;
   lv.level = h->hs_level;
   lv.digit_shift = 0;
@@ -2227,6 +2302,8 @@ agg_status finish_impl(agg_handle *h) {
     }
     h->st.levels = depth + 1;
   }
+  // the runs are all consumed: the segments reserved for spills that did not come go back
+  h->next.release();
   s = read_ctrl(h);
   if (s) return s;
   h->st.filter_rejects = h->h_ctrl->filter_rejects;
@@ -2298,6 +2375,7 @@ agg_status agg_create(const agg_spec *spec, agg_handle **out) {
   }
   if (hipHostMalloc((void **)&h->h_ctrl, sizeof(Ctrl), 0) != hipSuccess ||
       hipHostMalloc((void **)&h->h_scratch, kScratchBytes, 0) != hipSuccess) {
+    if (getenv("AGGX_DEBUG")) fprintf(stderr, "aggx: the handle's pinned mirrors are not available\n");
     agg_destroy(h);
     return AGG_E_NOMEM;
   }
@@ -2504,6 +2582,8 @@ void agg_destroy(agg_handle *h) {
   h->hs_runs.release();
   h->hs_tmp[0].release();
   h->hs_tmp[1].release();
+  h->dd_tmp[0].release();
+  h->dd_tmp[1].release();
   if (h->own_pool && h->pool) dev_put(h->pool, h->pool_bytes);
   if (h->r_block) dev_put(h->r_block, h->r_block_bytes);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
