@@ -360,6 +360,19 @@ typedef struct agg_batch_stats {
   uint32_t blocks;                /* persistent workgroups */
   double last_run_ms;             /* device time of the last graph launch (HIP events) */
   double tune_ms[4];              /* trial-run times of the autotuner's candidates (0: not run) */
+  /* The autotuner prices 27 candidate layouts (records per partition, records per
+   * count/scatter item, largest instance aggregated whole) with a cost model --
+   * bytes moved at the device's rate, the largest item at one workgroup's share,
+   * a fixed cost per queued item -- and times the four it prices lowest, in that
+   * order; tuned_candidate indexes these.  A shape tuned earlier in the process
+   * (same record size, aggregates, instance count and log2 of the records) reuses
+   * its choice untimed: then only entry 0 is filled. */
+  double predict_ms[4];           /* the cost model's price of each trial candidate */
+  uint64_t trial_part_records[4];
+  uint64_t trial_chunk_records[4];
+  uint64_t trial_solo_max[4];
+  uint32_t candidates_priced;     /* 27, or 0 when a cached choice was reused */
+  uint32_t reserved;
 } agg_batch_stats;
 
 /* Plan the batch (spec's record layout and aggregates; spec budget must be 0

@@ -133,11 +133,19 @@ class BatchStats(ctypes.Structure):
         ("blocks", ctypes.c_uint32),
         ("last_run_ms", ctypes.c_double),
         ("tune_ms", ctypes.c_double * 4),
+        ("predict_ms", ctypes.c_double * 4),
+        ("trial_part_records", ctypes.c_uint64 * 4),
+        ("trial_chunk_records", ctypes.c_uint64 * 4),
+        ("trial_solo_max", ctypes.c_uint64 * 4),
+        ("candidates_priced", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
+    _ARRAYS = ("tune_ms", "predict_ms", "trial_part_records", "trial_chunk_records", "trial_solo_max")
 
     def as_dict(self) -> dict:
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "tune_ms"}
-        d["tune_ms"] = list(self.tune_ms)
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in self._ARRAYS}
+        for k in self._ARRAYS:
+            d[k] = list(getattr(self, k))
         return d
 
 

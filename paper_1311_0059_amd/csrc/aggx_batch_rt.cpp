@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/aggx.h"
+#include "aggx_batch_model.h"
 #include "aggx_internal.h"
 
 using namespace aggx;
@@ -32,14 +33,22 @@ constexpr double kLoad = 0.75;
 constexpr uint32_t kSpinLimit = 50u * 1000u * 1000u;  // ~ seconds of s_sleep; ends a wait that cannot end
 
 // Autotuner candidates: records per partition, records per count/scatter item,
-// largest instance aggregated whole by one workgroup.
+// largest instance aggregated whole by one workgroup.  27 of them (three values
+// each); a cost model ranks them and the four it prices lowest are timed.
 struct Cand {
   uint64_t part_records, chunk_records, solo_max;
 };
-const Cand kCands[4] = {{65536, 65536, 262144}, {65536, 262144, 262144}, {65536, 1048576, 262144}, {65536, 262144, 524288}};
+constexpr uint32_t kTrials = 4;
+std::vector<Cand> all_cands() {
+  std::vector<Cand> v;
+  for (uint64_t p : {32768ull, 65536ull, 131072ull})
+    for (uint64_t c : {65536ull, 262144ull, 1048576ull})
+      for (uint64_t m : {131072ull, 262144ull, 524288ull}) v.push_back({p, c, m});
+  return v;
+}
 
 std::mutex g_tune_mu;
-std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, uint32_t> g_tune_cache;
+std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, Cand> g_tune_cache;
 
 uint64_t rup(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -178,6 +187,33 @@ Layout build_layout(const agg_batch *b, const Cand &c) {
   return L;
 }
 
+// The cost model's price of a layout: its queue replayed by the launch model
+// (aggx_batch_model.h) -- what each item streams (a count reads its chunk, a
+// scatter reads and writes it, an aggregation reads its partition, a
+// whole-instance item its instance), its fixed costs, and the waits of the
+// items that depend on others.
+double predict_ms(const agg_batch *b, const Layout &L) {
+  const double rb = b->ks.rb;
+  std::vector<SimItem> items;
+  items.reserve(L.items.size());
+  std::vector<uint32_t> chunks(L.binst.size(), 0);
+  for (size_t i = 0; i < L.binst.size(); ++i) chunks[i] = L.binst[i].nchunks;
+  for (const BItem &it : L.items) {
+    const BInst &I = L.binst[it.inst];
+    const uint32_t F = 1u << I.b;
+    SimItem s{SM_AGG, it.inst, F, 0.0};
+    switch (it.type) {
+      case IT_COUNT: s.type = SM_COUNT; s.bytes = (double)(it.hi - it.lo) * rb; break;
+      case IT_SCATTER: s.type = SM_SCATTER; s.bytes = 2.0 * (double)(it.hi - it.lo) * rb; break;
+      case IT_OFFS: s.type = SM_OFFS; break;
+      case IT_SOLO: s.type = SM_SOLO; s.bytes = (double)I.n * rb; break;
+      default: s.bytes = (double)I.n * rb / (double)F; break;
+    }
+    items.push_back(s);
+  }
+  return simulate_batch(items, chunks, b->blocks, kBatchModel);
+}
+
 }  // namespace
 
 extern "C" {
@@ -245,12 +281,51 @@ agg_status agg_batch_create(const agg_spec *spec, const agg_instance *inst, uint
     if (part_bits(b, inst[i].n, G, ~0ULL) == 99) b->alone[i] = 1;
     b->st.records += inst[i].n;
   }
-  // buffers sized for the largest candidate layout
-  uint64_t n_parts = 0, pbuf = 0, outt = 0, n_items = 0, n_cc = 0;
+  // A shape tuned before reuses its candidate; otherwise the cost model ranks every
+  // candidate and the four it prices lowest are tried.
+  const auto key = std::make_tuple(spec->record_bytes, spec->n_aggs, n_inst,
+                                   (uint32_t)std::log2((double)std::max<uint64_t>(b->st.records, 1)));
+  bool cached = false;
+  Cand cached_c{};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      cached_c = it->second;
+      cached = true;
+    }
+  }
   std::vector<Layout> lays;
-  for (const Cand &c : kCands) {
-    lays.push_back(build_layout(b, c));
-    const Layout &L = lays.back();
+  std::vector<Cand> trial;
+  if (cached) {
+    lays.push_back(build_layout(b, cached_c));
+    trial.push_back(cached_c);
+    b->st.predict_ms[0] = predict_ms(b, lays[0]);
+  } else {
+    const std::vector<Cand> all = all_cands();
+    std::vector<std::pair<double, uint32_t>> ranked;
+    std::vector<Layout> built;
+    for (uint32_t i = 0; i < (uint32_t)all.size(); ++i) {
+      built.push_back(build_layout(b, all[i]));
+      ranked.push_back({predict_ms(b, built.back()), i});
+    }
+    std::sort(ranked.begin(), ranked.end());
+    for (uint32_t t = 0; t < kTrials && t < ranked.size(); ++t) {
+      const Cand &c = all[ranked[t].second];
+      lays.push_back(std::move(built[ranked[t].second]));
+      trial.push_back(c);
+      b->st.predict_ms[t] = ranked[t].first;
+    }
+    b->st.candidates_priced = (uint32_t)all.size();
+  }
+  for (uint32_t t = 0; t < (uint32_t)trial.size(); ++t) {
+    b->st.trial_part_records[t] = trial[t].part_records;
+    b->st.trial_chunk_records[t] = trial[t].chunk_records;
+    b->st.trial_solo_max[t] = trial[t].solo_max;
+  }
+  // buffers sized for the largest trial layout
+  uint64_t n_parts = 0, pbuf = 0, outt = 0, n_items = 0, n_cc = 0;
+  for (const Layout &L : lays) {
     n_parts = std::max(n_parts, L.n_parts);
     n_cc = std::max(n_cc, L.n_ccounts);
     pbuf = std::max(pbuf, L.pbuf_bytes);
@@ -317,21 +392,10 @@ agg_status agg_batch_create(const agg_spec *spec, const agg_instance *inst, uint
   };
 
   // autotune: one timed trial launch per candidate, unless this shape is cached
-  const auto key = std::make_tuple(spec->record_bytes, spec->n_aggs, n_inst,
-                                   (uint32_t)std::log2((double)std::max<uint64_t>(b->st.records, 1)));
   uint32_t best = 0;
-  bool cached = false;
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-      best = it->second;
-      cached = true;
-    }
-  }
   if (!cached && b->st.records > 0) {
     float best_ms = 1e30f;
-    for (uint32_t ci = 0; ci < 4; ++ci) {
+    for (uint32_t ci = 0; ci < (uint32_t)lays.size(); ++ci) {
       agg_status s = upload(lays[ci]);
       if (s) return bail(s);
       // first launch warms caches and code; the second is timed
@@ -353,7 +417,7 @@ agg_status agg_batch_create(const agg_spec *spec, const agg_instance *inst, uint
       }
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = best;
+    g_tune_cache[key] = trial[best];
   }
   b->st.tuned_candidate = best;
   agg_status s = upload(lays[best]);

@@ -112,3 +112,28 @@ def test_batch_large_instances():
         wk, wc = oracle.groupby(r, SPEC)
         assert_rows_equal(rows[i][0], rows[i][1], wk, wc, f"large {i}")
     assert st["partitioned_instances"] == 3
+
+
+def test_autotuner_times_the_four_candidates_the_cost_model_prices_lowest():
+    """The cost model prices all 27 candidate layouts; the four cheapest are timed in price
+    order and the fastest is kept.  A second batch of the same shape reuses that choice
+    untimed, with the same rows."""
+    recs, ds = _mix(53, 37, 2e4, 6e5)
+    rows, st = _run_batch(recs, ds)
+    for i, r in enumerate(recs):
+        wk, wc = oracle.groupby(r, SPEC)
+        assert_rows_equal(rows[i][0], rows[i][1], wk, wc, f"tuned {i}")
+    print(f"  predicted {st['predict_ms']} timed {st['tune_ms']} chose {st['tuned_candidate']}", flush=True)
+    assert st["candidates_priced"] == 27
+    assert st["predict_ms"] == sorted(st["predict_ms"]) and st["predict_ms"][0] > 0
+    assert all(t > 0 for t in st["tune_ms"])
+    assert st["tune_ms"][st["tuned_candidate"]] == min(st["tune_ms"])
+    cands = set(zip(st["trial_part_records"], st["trial_chunk_records"], st["trial_solo_max"]))
+    assert len(cands) == 4
+    chosen = (st["trial_part_records"][st["tuned_candidate"]], st["trial_chunk_records"][st["tuned_candidate"]],
+              st["trial_solo_max"][st["tuned_candidate"]])
+    rows2, st2 = _run_batch(recs, ds)
+    assert st2["candidates_priced"] == 0 and st2["tuned_candidate"] == 0 and st2["tune_ms"] == [0.0] * 4
+    assert (st2["trial_part_records"][0], st2["trial_chunk_records"][0], st2["trial_solo_max"][0]) == chosen
+    for i in range(len(recs)):
+        assert np.array_equal(rows[i][0], rows2[i][0]) and np.array_equal(rows[i][1], rows2[i][1])
