@@ -200,7 +200,8 @@ typedef struct agg_stats {
   uint32_t onchip_workers;      /* on-chip engine: workgroups per class */
   double onchip_ms;             /* on-chip engine: device time of its kernel (HIP events) */
   uint32_t onchip_fallbacks;    /* on-chip engine: batches run again elsewhere (more groups than planned) */
-  uint32_t reserved_stats;
+  uint32_t onchip_kernel16;     /* on-chip engine: 1 when its 16-byte record kernel ran (records of one 8-byte
+                                   key and one 8-byte field every other aggregate reads, 16-byte aligned) */
   uint64_t onchip_direct;       /* on-chip engine: records whose key found no room in its class's LDS table
                                    (folded straight into the HBM tables) */
   uint64_t records_spilled_l0;  /* raw records spilled at level 0 (the spilled part of the input, the I/O

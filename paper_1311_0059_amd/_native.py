@@ -89,7 +89,7 @@ class Stats(ctypes.Structure):
         ("onchip_workers", ctypes.c_uint32),
         ("onchip_ms", ctypes.c_double),
         ("onchip_fallbacks", ctypes.c_uint32),
-        ("reserved_stats", ctypes.c_uint32),
+        ("onchip_kernel16", ctypes.c_uint32),
         ("onchip_direct", ctypes.c_uint64),
         ("records_spilled_l0", ctypes.c_uint64),
         ("first_full_record", ctypes.c_uint64),

@@ -81,39 +81,33 @@ __device__ void lds_aggregate(const uint8_t *in, uint64_t lo, uint64_t hi, const
   bool bad = false;
   // insert one record's key (or find it) and fold its values; false if it found no room.
   // Linear probing over groups of four slots (nslots is a multiple of four), whose keys
-  // come in two 16-byte reads.  The fold follows the probe loop, so that a wave runs it
+  // come in two 16-byte reads and are compared at once (a key, once written, stays: a
+  // match is the key's slot).  The fold follows the probe loop, so that a wave runs it
   // once whatever slot each lane found.
   auto fold_one = [&](uint64_t key, const uint64_t *vals) -> bool {
     const uint32_t ng = nslots / 4;
     uint32_t g = (uint32_t)mulhi64(fmix64(key ^ kSeed0) << slot_shift, ng);
     uint32_t slot = ~0u;
-    bool stop = false;
-    for (uint32_t t = 0; t < ng && !stop; ++t) {
+    for (uint32_t t = 0; t < ng;) {
       const ulonglong2 *gk = reinterpret_cast<const ulonglong2 *>(t_key + 4 * g);
       const ulonglong2 k01 = gk[0], k23 = gk[1];
-      const unsigned long long kv[4] = {k01.x, k01.y, k23.x, k23.y};
-#pragma unroll
-      for (uint32_t j = 0; j < 4; ++j) {
-        if (stop) break;
-        unsigned long long sk = kv[j];
-        if (sk == kEmpty) {
-          if (*s_groups >= P.cap) {
-            stop = true;
-            break;
-          }
-          sk = atomicCAS(reinterpret_cast<unsigned long long *>(t_key + 4 * g + j), (unsigned long long)kEmpty,
-                         (unsigned long long)key);
-          if (sk == kEmpty) {
-            atomicAdd(s_groups, 1u);
-            sk = key;
-          }
-        }
-        if (sk == key) {
-          slot = 4 * g + j;
-          stop = true;
-        }
+      slot = k01.x == key ? 4 * g : k01.y == key ? 4 * g + 1 : k23.x == key ? 4 * g + 2 : k23.y == key ? 4 * g + 3 : ~0u;
+      if (slot != ~0u) break;
+      const uint32_t j = k01.x == kEmpty ? 0 : k01.y == kEmpty ? 1 : k23.x == kEmpty ? 2 : k23.y == kEmpty ? 3 : 4;
+      if (j == 4) {  // four other keys: the next group
+        g = g + 1 == ng ? 0 : g + 1;
+        ++t;
+        continue;
       }
-      g = g + 1 == ng ? 0 : g + 1;
+      if (*s_groups >= P.cap) break;  // full: no room for a new key
+      const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(t_key + 4 * g + j),
+                                               (unsigned long long)kEmpty, (unsigned long long)key);
+      if (old == kEmpty) atomicAdd(s_groups, 1u);
+      if (old == kEmpty || old == key) {
+        slot = 4 * g + j;
+        break;
+      }
+      // another key took the slot: read the group again
     }
     if (slot == ~0u) return false;
     fold_lds(t_acc + slot, nslots, ks, vals);

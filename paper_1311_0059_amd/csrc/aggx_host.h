@@ -10,7 +10,8 @@ namespace aggx {
 agg_status spec_check(const agg_spec *s);
 // The kernels' view of a checked spec.
 KSpec spec_kernels(const agg_spec &s);
-// Launch shape of the on-chip engine for n records with about G groups; false
-// when they need more key classes than it takes.
-bool onchip_shape(const KSpec &ks, uint64_t n, double G, OnchipPlan *op);
+// Launch shape of the on-chip engine for n records with about G groups (aligned16:
+// the records start on a 16-byte boundary); false when they need more key
+// classes than it takes.
+bool onchip_shape(const KSpec &ks, uint64_t n, double G, bool aligned16, OnchipPlan *op);
 }  // namespace aggx

@@ -62,38 +62,50 @@ __device__ __forceinline__ void fold_lds_cols(uint8_t *cols, uint32_t nslots, ui
 // while the table holds fewer than `cap` groups (*s_groups counts them); once
 // full, a new key closes the empty slot it reaches, as in the HBM tables, so a
 // key is in the table for all of its records or for none.  Linear probing over
-// groups of four slots, whose keys come in two 16-byte reads, from the group
-// that the high bits of `hs` select.  Returns the slot, or ~0u (not resident).
+// groups of four slots, from the group that the high bits of `hs` select; a
+// group's four keys come in two 16-byte reads and are compared at once.
+// Returns the slot, or ~0u (not resident).
+//
+// A slot only ever changes from empty to a key or to closed, so when a key sits
+// in a slot, every slot before it on its probe path held a key already when it
+// was inserted (a closed slot would have stopped that insert): a match anywhere
+// in a group is the key's slot, and only when there is none does the order of
+// the group's empty and closed slots matter.
 __device__ __forceinline__ uint32_t lds_find_or_insert(uint64_t *t_key, uint32_t nslots, uint32_t cap,
                                                        uint32_t *s_groups, uint64_t key, uint64_t hs) {
   const uint32_t ng = nslots / 4;
   uint32_t g = (uint32_t)mulhi64(hs, ng);
-  uint32_t slot = ~0u;
-  bool stop = false;
-  for (uint32_t t = 0; t < ng && !stop; ++t) {
+  for (uint32_t t = 0; t < ng;) {
     const ulonglong2 *gk = reinterpret_cast<const ulonglong2 *>(t_key + 4 * g);
     const ulonglong2 k01 = gk[0], k23 = gk[1];
-    const unsigned long long kv[4] = {k01.x, k01.y, k23.x, k23.y};
-#pragma unroll
-    for (uint32_t j = 0; j < 4; ++j) {
-      if (stop) break;
-      const uint32_t idx = 4 * g + j;
-      unsigned long long sk = kv[j];
-      if (sk == kEmpty) {
-        const bool full = *s_groups >= cap;
-        const unsigned long long desired = full ? kClosed : key;
-        sk = atomicCAS(reinterpret_cast<unsigned long long *>(t_key + idx), (unsigned long long)kEmpty, desired);
-        if (sk == kEmpty) {
-          if (!full) atomicAdd(s_groups, 1u);
-          sk = desired;
-        }
-      }
-      if (sk == key) slot = idx;
-      stop = sk == key || sk == kClosed;
+    if (k01.x == key) return 4 * g;
+    if (k01.y == key) return 4 * g + 1;
+    if (k23.x == key) return 4 * g + 2;
+    if (k23.y == key) return 4 * g + 3;
+    // the first empty or closed slot of the group, if any (both compare >= kClosed)
+    const uint32_t j = k01.x >= kClosed ? 0 : k01.y >= kClosed ? 1 : k23.x >= kClosed ? 2 : k23.y >= kClosed ? 3 : 4;
+    if (j == 4) {  // four other keys: the next group
+      g = g + 1 == ng ? 0 : g + 1;
+      ++t;
+      continue;
     }
-    g = g + 1 == ng ? 0 : g + 1;
+    const unsigned long long first = j == 0 ? k01.x : j == 1 ? k01.y : j == 2 ? k23.x : k23.y;
+    if (first == kClosed) return ~0u;
+    const uint32_t idx = 4 * g + j;
+    const bool full = *s_groups >= cap;
+    const unsigned long long desired = full ? kClosed : key;
+    const unsigned long long old =
+        atomicCAS(reinterpret_cast<unsigned long long *>(t_key + idx), (unsigned long long)kEmpty, desired);
+    if (old == kEmpty) {
+      if (full) return ~0u;
+      atomicAdd(s_groups, 1u);
+      return idx;
+    }
+    if (old == key) return idx;
+    if (old == kClosed) return ~0u;
+    // another key took the slot: read the group again (it has one empty slot fewer)
   }
-  return slot;
+  return ~0u;
 }
 
 }  // namespace aggx

@@ -112,7 +112,7 @@ extern "C" agg_status agg_query_noalloc(const agg_spec *spec, const void *d_reco
   for (uint32_t a = 0; a < ks.na; ++a) oc.c[a] = d_cols[a];
   if (n) {
     OnchipPlan op;
-    if (!onchip_shape(ks, n, G, &op)) return AGG_E_BUDGET;
+    if (!onchip_shape(ks, n, G, ((uintptr_t)d_records & 15) == 0, &op)) return AGG_E_BUDGET;
     KLevel lv;
     lv.level = 0;
     lv.digit_shift = 0;

@@ -187,6 +187,13 @@ __device__ __forceinline__ void onchip_role(uint32_t C, uint32_t xcd_map, uint32
   }
 }
 
+// The LDS slot of `key` (Fibonacci hashing: one 64-bit multiply; the HBM tables
+// use the full hash), inserting it while there is room, or ~0u.
+__device__ __forceinline__ uint32_t lds_find(uint64_t *t_key, uint32_t nslots, uint32_t cap, uint32_t *s_groups,
+                                             uint64_t key) {
+  return lds_find_or_insert(t_key, nslots, cap, s_groups, key, key * 0x9E3779B97F4A7C15ull);
+}
+
 // Fold record i (read again: the class pass read its key moments before) into
 // the workgroup's LDS table, or, for a reserved key value or a key the table
 // has no room for, into its side group or the HBM tables.
@@ -202,7 +209,7 @@ __device__ __forceinline__ void onchip_take(const uint8_t *rec, const KSpec &ks,
     // full hash).  The table is a cache of partial states: a key's records may be folded
     // partly here and partly straight into the HBM tables, which add this table's states
     // at the end, so a key that finds no room here simply goes there.
-    const uint32_t slot = lds_find_or_insert(t_key, nslots, cap, s_groups, key, key * 0x9E3779B97F4A7C15ull);
+    const uint32_t slot = lds_find(t_key, nslots, cap, s_groups, key);
     if (slot != ~0u) {
 #pragma unroll
       for (int a = 0; a < kA; ++a)
@@ -306,6 +313,137 @@ __global__ void __launch_bounds__(kOnBlock) k_onchip(const uint8_t *__restrict__
   if (direct) __hip_atomic_fetch_add(&ctrl->onchip_direct, direct, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ---- 16-byte records, one class -------------------------------------------------
+// When one LDS table holds all of the batch's groups (one class), records of 16
+// bytes whose key is one 8-byte half and whose other aggregates all read the
+// other half as a 64-bit field (the common (key, value) pair) take a leaner
+// kernel: each thread loads whole records (one 16-byte load each) and folds
+// every one of them, with no class test and no staging; the value is at hand
+// for every column; the columns are plain 8-byte arrays with two operations, an
+// add (of 1 or of the value) and an unsigned maximum of the value xor a mask
+// (MIN and MAX, as above).  With several classes the general kernel runs.
+constexpr int kOn16Keys = 4;  // records a thread loads per tile
+
+bool onchip16_applies(const KSpec &ks, Fast16 *f) {
+  if (ks.rb != 16 || ks.nk != 1 || (ks.ktype0 != T_U64 && ks.ktype0 != T_I64) || (ks.koff0 != 0 && ks.koff0 != 8) ||
+      ks.na == 0 || ks.na > 4)
+    return false;
+  Fast16 g{};
+  g.key_hi = ks.koff0 == 8 ? 1u : 0u;
+  g.ncols = ks.na;
+  for (uint32_t a = 0; a < ks.na; ++a) {
+    const uint32_t d = ks.agg[a], op = desc_op(d), ty = desc_type(d);
+    if (op == OP_COUNT) {
+      g.kind[a] = 0;
+      continue;
+    }
+    if (desc_off(d) != 8 - ks.koff0 || (ty != T_U64 && ty != T_I64)) return false;
+    if (op == OP_SUM) {
+      g.kind[a] = 1;
+    } else {
+      g.kind[a] = 2;
+      g.mask[a] = (op == OP_MIN ? ~0ull : 0ull) ^ (ty == T_I64 ? 0x8000000000000000ull : 0ull);
+    }
+  }
+  *f = g;
+  return true;
+}
+
+// Fold a 16-byte record into the LDS table; false for a reserved key value or a
+// key the table has no room for (counted in *direct).
+template <int kA>
+__device__ __forceinline__ bool fold16(const uint4 &r, const Fast16 &f, unsigned long long *t_key,
+                                       unsigned long long *t_col, uint32_t nslots, uint32_t cap, uint32_t *s_groups,
+                                       unsigned long long *direct) {
+  const uint64_t lo = (uint64_t)r.x | ((uint64_t)r.y << 32), hi = (uint64_t)r.z | ((uint64_t)r.w << 32);
+  const uint64_t key = f.key_hi ? hi : lo, v = f.key_hi ? lo : hi;
+  if (key >= kClosed) return false;
+  const uint32_t slot = lds_find(reinterpret_cast<uint64_t *>(t_key), nslots, cap, s_groups, key);
+  if (slot == ~0u) {
+    ++*direct;
+    return false;
+  }
+#pragma unroll
+  for (int a = 0; a < kA; ++a) {
+    if (a >= (int)f.ncols) break;
+    unsigned long long *w = t_col + (uint64_t)a * nslots + slot;
+    if (f.kind[a] == 2) atomicMax(w, (unsigned long long)(v ^ f.mask[a]));
+    else atomicAdd(w, f.kind[a] == 0 ? 1ull : (unsigned long long)v);
+  }
+  return true;
+}
+
+template <int kA>
+__global__ void __launch_bounds__(kOnBlock) k_onchip16(const uint4 *__restrict__ in, uint64_t n, KSpec ks, Fast16 f,
+                                                       KLevel lv, const PartMeta *__restrict__ meta, uint32_t *cnt,
+                                                       uint64_t *arena, Ctrl *ctrl, uint32_t workers,
+                                                       uint32_t nslots, uint32_t cap) {
+  extern __shared__ uint4 lds4[];
+  __shared__ uint32_t s_groups;
+  unsigned long long *t_key = reinterpret_cast<unsigned long long *>(lds4);
+  unsigned long long *t_col = t_key + nslots;  // column a: nslots words from t_col + a * nslots
+  const uint32_t tid = threadIdx.x, worker = blockIdx.x;
+  for (uint32_t e = tid; e < nslots; e += blockDim.x) t_key[e] = kEmpty;
+  for (uint32_t w = tid; w < f.ncols * nslots; w += blockDim.x) t_col[w] = 0;
+  if (tid == 0) s_groups = 0;
+  __syncthreads();
+  const uint64_t T = (uint64_t)kOn16Keys * kOnBlock;
+  unsigned long long lost = 0, direct = 0;
+  for (uint64_t t0 = (uint64_t)worker * T; t0 < n; t0 += (uint64_t)workers * T) {
+    const uint4 *tile = in + t0;
+    const uint32_t nt = (uint32_t)(n - t0 < T ? n - t0 : T);
+    uint4 r[kOn16Keys];
+#pragma unroll
+    for (int u = 0; u < kOn16Keys; ++u) {
+      const uint32_t l = u * kOnBlock + tid;
+      r[u] = tile[l < nt ? l : 0];
+    }
+    uint32_t cold = 0;  // records for the side groups or the HBM tables, folded after the unrolled loop
+#pragma unroll
+    for (int u = 0; u < kOn16Keys; ++u) {
+      const uint32_t l = u * kOnBlock + tid;
+      if (l < nt && !fold16<kA>(r[u], f, t_key, t_col, nslots, cap, &s_groups, &direct)) cold |= 1u << u;
+    }
+#pragma nounroll
+    for (int u = 0; u < kOn16Keys; ++u)
+      if (cold >> u & 1u) {
+        const uint8_t *rec = reinterpret_cast<const uint8_t *>(tile + u * kOnBlock + tid);
+        if (!onchip_cold(rec, ks, lv, meta, cnt, arena, ctrl)) ++lost;
+      }
+  }
+  __syncthreads();
+  // the workgroup's groups, as grouping states, into the HBM tables
+  for (uint32_t e = tid; e < nslots; e += blockDim.x) {
+    const uint64_t key = t_key[e];
+    if (key >= kClosed) continue;
+    Vals8 st;
+#pragma unroll
+    for (int a = 0; a < kA; ++a)
+      if (a < (int)f.ncols) st.v[a] = t_col[(uint64_t)a * nslots + e] ^ (f.kind[a] == 2 ? f.mask[a] : 0ull);
+    if (!fold_into_tables(key, fmix64(key ^ kSeed0), st.v, ks, lv, meta, cnt, arena)) ++lost;
+  }
+  if (lost) __hip_atomic_fetch_add(&ctrl->onchip_lost, lost, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (direct) __hip_atomic_fetch_add(&ctrl->onchip_direct, direct, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+hipError_t onchip16_setup(uint32_t total_bytes, uint32_t *lds_bytes) {
+  const void *fns[] = {reinterpret_cast<const void *>(k_onchip16<2>), reinterpret_cast<const void *>(k_onchip16<4>)};
+  uint32_t best = total_bytes;
+  for (const void *fn : fns) {
+    hipFuncAttributes fa{};
+    hipError_t e = hipFuncGetAttributes(&fa, fn);
+    if (e != hipSuccess) return e;
+    if (fa.sharedSizeBytes >= total_bytes) return hipErrorInvalidValue;
+    best = std::min<uint32_t>(best, (total_bytes - (uint32_t)fa.sharedSizeBytes) & ~15u);
+  }
+  for (const void *fn : fns) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)best);
+    if (e != hipSuccess) return e;
+  }
+  *lds_bytes = best;
+  return hipSuccess;
+}
+
 #define AGGX_ONCHIP_KERNELS(X) X(false, 2) X(false, 4) X(false, 8) X(true, 2) X(true, 4) X(true, 8)
 
 hipError_t onchip_setup(uint32_t total_bytes, uint32_t *lds_bytes) {
@@ -328,7 +466,7 @@ hipError_t onchip_setup(uint32_t total_bytes, uint32_t *lds_bytes) {
   return hipSuccess;
 }
 
-uint64_t onchip_tile_records(uint32_t) { return (uint64_t)kOnKeys * kOnBlock; }
+uint64_t onchip_tile_records(bool fast) { return (uint64_t)(fast ? kOn16Keys : kOnKeys) * kOnBlock; }
 
 hipError_t launch_onchip(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, const KLevel &lv,
                          const PartMeta *meta, uint32_t *cnt, uint64_t *arena, Ctrl *ctrl, const OnchipPlan &op) {
@@ -337,8 +475,20 @@ hipError_t launch_onchip(hipStream_t s, const uint8_t *in, uint64_t n, const KSp
       (uint64_t)lds_slot_bytes(ks, op.narrow) * op.nslots > op.lds_bytes || (op.xcd_map && op.workers % 8) ||
       ks.na == 0 || ks.na > (uint32_t)kMaxAggs)
     return hipErrorInvalidValue;
+  if (op.fast) {
+    Fast16 f;
+    if (op.narrow || op.C != 1 || !onchip16_applies(ks, &f) || ((uintptr_t)in & 15)) return hipErrorInvalidValue;
+    const uint4 *in4 = reinterpret_cast<const uint4 *>(in);
+    if (ks.na <= 2)
+      hipLaunchKernelGGL((k_onchip16<2>), dim3(op.workers), dim3(kOnBlock), op.lds_bytes, s, in4, n, ks, f, lv, meta,
+                         cnt, arena, ctrl, op.workers, op.nslots, op.cap);
+    else
+      hipLaunchKernelGGL((k_onchip16<4>), dim3(op.workers), dim3(kOnBlock), op.lds_bytes, s, in4, n, ks, f, lv, meta,
+                         cnt, arena, ctrl, op.workers, op.nslots, op.cap);
+    return hipGetLastError();
+  }
   // a narrow COUNT column counts one workgroup's records: fewer than 2^32 of them
-  const uint64_t T = onchip_tile_records(ks.na);
+  const uint64_t T = onchip_tile_records(false);
   if (op.narrow && ((n + T - 1) / T + op.workers - 1) / op.workers * T >= (1ull << 32)) return hipErrorInvalidValue;
   const uint32_t blocks = op.C * op.workers;
   const int kA = onchip_aggs_for(ks.na);

@@ -1436,15 +1436,30 @@ constexpr double kOnchipLoad = 0.85;          // LDS table load at which a class
 constexpr double kOnchipSizeLoad = 0.66;
 constexpr uint64_t kOnchipRecordsPerGroup = 16;  // records per worker and group before another worker pays
 
-bool onchip_plan(const KSpec &ks, uint64_t n, double G, OnchipPlan *op) {
+bool onchip_plan_as(const KSpec &ks, uint64_t n, double G, bool fast, uint32_t lds_bytes, OnchipPlan *op);
+
+// 16-byte (key, value) records take the leaner kernel, whose columns are all 8
+// bytes, where one of its tables holds every group (one class); otherwise the
+// general kernel.
+bool onchip_plan(const KSpec &ks, uint64_t n, double G, bool aligned16, OnchipPlan *op) {
   const DeviceSetup *ds = device_setup();
   if (!ds || ds->onchip_lds_max == 0 || n == 0) return false;
+  Fast16 f16;
+  if (aligned16 && ds->onchip16_lds_max > 0 && onchip16_applies(ks, &f16) &&
+      onchip_plan_as(ks, n, G, true, ds->onchip16_lds_max, op) && op->C == 1)
+    return true;
+  return onchip_plan_as(ks, n, G, false, ds->onchip_lds_max, op);
+}
+
+bool onchip_plan_as(const KSpec &ks, uint64_t n, double G, bool fast, uint32_t lds_bytes, OnchipPlan *op) {
+  const DeviceSetup *ds = device_setup();
   *op = OnchipPlan();
-  op->lds_bytes = ds->onchip_lds_max;
-  const uint64_t T = onchip_tile_records(ks.na);
+  op->fast = fast;
+  op->lds_bytes = lds_bytes;
+  const uint64_t T = onchip_tile_records(op->fast);
   const uint64_t tiles = (n + T - 1) / T;
   // narrow columns when they hold more groups; the records a workgroup reads stay below 2^32
-  const uint32_t wide = lds_slot_bytes(ks, false), thin = lds_slot_bytes(ks, true);
+  const uint32_t wide = lds_slot_bytes(ks, false), thin = op->fast ? wide : lds_slot_bytes(ks, true);
   // the fewest classes whose tables hold the estimate at load `size_load` (the
   // tables take keys up to kOnchipLoad before the rest goes to the HBM tables)
   double size_load = kOnchipSizeLoad;
@@ -1585,7 +1600,7 @@ agg_status run_onchip(agg_handle *h, const uint8_t *in, uint64_t n, bool *applie
     else if (Gs > 4.0 * G) return AGG_OK;
   }
   OnchipPlan op;
-  if (!onchip_plan(h->ks, n, G, &op)) return AGG_OK;
+  if (!onchip_plan(h->ks, n, G, ((uintptr_t)in & 15) == 0, &op)) return AGG_OK;
   // AUTO takes it where the cost model prices it below the partition-first engine
   // (when that applies); the tables engine is priced above both
   const Cost co = cost_onchip(h->ks, n, op);
@@ -1638,6 +1653,7 @@ agg_status run_onchip(agg_handle *h, const uint8_t *in, uint64_t n, bool *applie
   h->st.onchip_classes = op.C;
   h->st.onchip_workers = op.workers;
   h->st.lds_narrow = op.narrow ? 1u : 0u;
+  h->st.onchip_kernel16 = op.fast ? 1u : 0u;
   return handle_overflow(h, true);  // (nothing was spilled: a full table may grow)
 }
 
@@ -2321,7 +2337,9 @@ namespace aggx {
 // allocates nothing (aggx_noalloc.hip).
 agg_status spec_check(const agg_spec *s) { return validate(s); }
 KSpec spec_kernels(const agg_spec &s) { return make_kspec(s); }
-bool onchip_shape(const KSpec &ks, uint64_t n, double G, OnchipPlan *op) { return onchip_plan(ks, n, G, op); }
+bool onchip_shape(const KSpec &ks, uint64_t n, double G, bool aligned16, OnchipPlan *op) {
+  return onchip_plan(ks, n, G, aligned16, op);
+}
 }  // namespace aggx
 
 extern "C" {

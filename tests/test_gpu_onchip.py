@@ -120,3 +120,77 @@ def test_later_batches_and_budget():
     k, c, st = run_lib(rec, **lib_spec_args(wl), batches=3, est_groups=wl.d, budget=4 << 20, engine="onchip")
     check_against_oracle(rec, oracle_spec(wl), k, c, "onchip batches")
     assert st["engine"] == 5 and st["pool_high_water"] <= 4 << 20
+
+
+R16_SWAPPED = np.dtype([("v", "<i8"), ("key", "<u8")])
+
+
+@pytest.mark.parametrize("d,aggs", [(1500, workloads.AGGS_R16_ALL), (9000, workloads.AGGS_R16_ALL),
+                                    (8000, workloads.AGGS_R16_CS)])
+def test_kernel16_one_class_general_kernel_for_several(d, aggs):
+    """16-byte (key, value) records whose groups fit one LDS table take the 16-byte record
+    kernel (every lane folds every record it loads); with more groups, several classes on the
+    general kernel.  COUNT+SUM and all four aggregates."""
+    wl = workloads.uniform_small().scaled(2_000_000, d)
+    rec = wl.generate()
+    spec = {"record_bytes": 16, "keys": [(0, "u64")], "aggs": aggs}
+    print(f"case: onchip kernel16 d={d} na={len(aggs)}", flush=True)
+    k, c, st = run_lib(rec, 16, spec["keys"], aggs, est_groups=d, engine="onchip")
+    check_against_oracle(rec, spec, k, c, f"kernel16 d={d}")
+    assert st["engine"] == 5 and st["onchip_fallbacks"] == 0
+    assert st["onchip_kernel16"] == (1 if d == 1500 else 0) and (st["onchip_classes"] == 1) == (d == 1500)
+
+
+def test_kernel16_key_in_second_half_signed_extremes():
+    """The key in the record's second 8 bytes, signed int64 values at both extremes (MIN/MAX
+    kept as unsigned maxima of a transformed value), and the two reserved key values."""
+    rng = np.random.default_rng(23)
+    pool = rng.integers(0, 2**63, size=2000, dtype=np.int64).astype(np.uint64)
+    pool[:2] = [2**64 - 1, 2**64 - 2]
+    rec = np.zeros(600_000, dtype=R16_SWAPPED)
+    rec["key"] = pool[rng.integers(0, pool.size, size=rec.size)]
+    rec["v"] = rng.integers(-2**63, 2**63 - 1, size=rec.size, dtype=np.int64)
+    rec["v"][:20] = -2**63
+    rec["v"][20:40] = 2**63 - 1
+    aggs = [("COUNT", 0, "i64"), ("SUM", 0, "i64"), ("MIN", 0, "i64"), ("MAX", 0, "i64")]
+    spec = {"record_bytes": 16, "keys": [(8, "u64")], "aggs": aggs}
+    print("case: onchip kernel16 key second", flush=True)
+    k, c, st = run_lib(rec, 16, spec["keys"], aggs, est_groups=2000, engine="onchip")
+    check_against_oracle(rec, spec, k, c, "kernel16 key second")
+    assert st["engine"] == 5 and st["onchip_kernel16"] == 1
+
+
+def test_unaligned_input_takes_the_general_kernel():
+    """Records that start 8 bytes past a 16-byte boundary: the general kernel, the same rows."""
+    import torch
+    import paper_1311_0059_amd as P
+    wl = workloads.uniform_small().scaled(500_000, 5000)
+    rec = wl.generate()
+    raw = np.zeros(rec.size * 16 + 8, dtype=np.uint8)
+    raw[8:] = rec.view(np.uint8).reshape(-1)
+    dev = torch.from_numpy(raw).cuda()
+    torch.cuda.synchronize()
+    print("case: onchip unaligned", flush=True)
+    spec = P.make_spec(16, [(0, "u64")], workloads.AGGS_R16_ALL, est_groups=wl.d, engine="onchip")
+    with P.GroupBy(spec) as g:
+        g.consume_ptr(dev.data_ptr() + 8, rec.size)
+        g.finish()
+        k, c = g.rows("cpu")
+        st = g.stats()
+    torch.cuda.synchronize()
+    keys = k.numpy().view(np.uint64)
+    order = np.argsort(keys)
+    check_against_oracle(rec, oracle_spec(wl), keys[order], c.numpy()[:, order], "onchip unaligned")
+    assert st["engine"] == 5 and st["onchip_kernel16"] == 0
+
+
+def test_kernel16_other_field_takes_the_general_kernel():
+    """An aggregate of a 32-bit field does not fit the 16-byte record kernel's form."""
+    rng = np.random.default_rng(29)
+    rec = _r16(rng.integers(0, 500, size=300_000).astype(np.uint64), rng.integers(-10**6, 10**6, size=300_000))
+    aggs = [("COUNT", 0, "i64"), ("MIN", 8, "i32"), ("MAX", 12, "i32")]
+    spec = {"record_bytes": 16, "keys": [(0, "u64")], "aggs": aggs}
+    print("case: onchip kernel16 not applicable", flush=True)
+    k, c, st = run_lib(rec, 16, spec["keys"], aggs, est_groups=500, engine="onchip")
+    check_against_oracle(rec, spec, k, c, "onchip i32 fields")
+    assert st["engine"] == 5 and st["onchip_kernel16"] == 0
