@@ -200,8 +200,9 @@ typedef struct agg_stats {
   uint32_t onchip_workers;      /* on-chip engine: workgroups per class */
   double onchip_ms;             /* on-chip engine: device time of its kernel (HIP events) */
   uint32_t onchip_fallbacks;    /* on-chip engine: batches run again elsewhere (more groups than planned) */
-  uint32_t onchip_kernel16;     /* on-chip engine: 1 when its 16-byte record kernel ran (records of one 8-byte
-                                   key and one 8-byte field every other aggregate reads, 16-byte aligned) */
+  uint32_t onchip_kernel16;     /* on-chip engine: its 16-byte record kernel that ran (records of one 8-byte
+                                   key and one 8-byte field every other aggregate reads, 16-byte aligned):
+                                   1 one class, 2 several (staged), 0 the general kernel */
   uint64_t onchip_direct;       /* on-chip engine: records whose key found no room in its class's LDS table
                                    (folded straight into the HBM tables) */
   uint64_t records_spilled_l0;  /* raw records spilled at level 0 (the spilled part of the input, the I/O
@@ -236,7 +237,8 @@ typedef struct agg_stats {
   double cost_tables_ms;
   uint64_t cost_spilled_records;
   uint32_t cost_levels;
-  uint32_t reserved_stats4;
+  uint32_t onchip_retries;      /* on-chip engine: batches the staged 16-byte record kernel left to the general
+                                   kernel (a reserved key value, or a class with more keys than its table) */
   uint64_t pinned_peak_bytes;   /* most pinned host memory the query's spill runs held at once (segments) */
 } agg_stats;
 

@@ -108,7 +108,7 @@ class Stats(ctypes.Structure):
         ("cost_tables_ms", ctypes.c_double),
         ("cost_spilled_records", ctypes.c_uint64),
         ("cost_levels", ctypes.c_uint32),
-        ("reserved_stats4", ctypes.c_uint32),
+        ("onchip_retries", ctypes.c_uint32),
         ("pinned_peak_bytes", ctypes.c_uint64),
     ]
 

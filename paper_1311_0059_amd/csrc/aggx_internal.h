@@ -287,7 +287,7 @@ hipError_t launch_run_reduce(hipStream_t s, const uint8_t *in, uint64_t n, const
 struct OnchipPlan {
   uint32_t C = 0, workers = 0, xcd_map = 0, nslots = 0, cap = 0, lds_bytes = 0;
   bool narrow = false;
-  bool fast = false;  // the 16-byte record kernel (one class, input 16-byte aligned, onchip16_applies)
+  bool fast = false;  // a 16-byte record kernel (by C; input 16-byte aligned, onchip16_applies)
 };
 // The on-chip engine's 16-byte record form: the key's half, and per column an
 // add of 1 (kind 0), an add of the value (1), or a maximum of value ^ mask (2).
@@ -298,7 +298,7 @@ struct Fast16 {
   uint64_t mask[4];
 };
 bool onchip16_applies(const KSpec &ks, Fast16 *f);
-hipError_t onchip16_setup(uint32_t total_bytes, uint32_t *lds_bytes);
+hipError_t onchip16_setup(uint32_t total_bytes, uint32_t *one_class, uint32_t *several);
 hipError_t launch_onchip(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, const KLevel &lv,
                          const PartMeta *meta, uint32_t *cnt, uint64_t *arena, Ctrl *ctrl, const OnchipPlan &op);
 hipError_t onchip_setup(uint32_t total_bytes, uint32_t *lds_bytes);
@@ -315,7 +315,8 @@ struct DeviceSetup {
   int cus;                     // compute units
   int update_per_cu[2][2][4];  // k_update<kind, preagg> blocks per CU without dynamic LDS, block = 64 (i + 1)
   uint32_t onchip_lds_max;     // dynamic LDS bytes of the on-chip engine's kernel (0: not available)
-  uint32_t onchip16_lds_max;   // the same for its 16-byte record kernel (one class)
+  uint32_t onchip16_lds_max;   // the same for its 16-byte record kernels: one class
+  uint32_t onchip16s_lds_max;  //   and several classes
   bool sample_hot_ok;          // the frequent-key sampler could be given its LDS
   uint32_t batch_lds_max;      // dynamic LDS bytes of the batched-mode kernel
   int batch_per_cu;            // its blocks per CU at batch_lds_max

@@ -654,7 +654,8 @@ const DeviceSetup *device_setup() {
         ds.update_per_cu[kind][pre][i] = per;
       }
   if (onchip_setup(want, &ds.onchip_lds_max) != hipSuccess) ds.onchip_lds_max = 0;
-  if (onchip16_setup(want, &ds.onchip16_lds_max) != hipSuccess) ds.onchip16_lds_max = 0;
+  if (onchip16_setup(want, &ds.onchip16_lds_max, &ds.onchip16s_lds_max) != hipSuccess)
+    ds.onchip16_lds_max = ds.onchip16s_lds_max = 0;
   ds.sample_hot_ok = sample_hot_setup() == hipSuccess;
   if (batch_kernel_setup(want, &ds.batch_lds_max, &ds.batch_per_cu) != hipSuccess || ds.batch_per_cu < 1) {
     // 64 KB in all when more cannot be had

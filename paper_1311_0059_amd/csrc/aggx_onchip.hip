@@ -321,7 +321,7 @@ __global__ void __launch_bounds__(kOnBlock) k_onchip(const uint8_t *__restrict__
 // every one of them, with no class test and no staging; the value is at hand
 // for every column; the columns are plain 8-byte arrays with two operations, an
 // add (of 1 or of the value) and an unsigned maximum of the value xor a mask
-// (MIN and MAX, as above).  With several classes the general kernel runs.
+// (MIN and MAX, as above).
 constexpr int kOn16Keys = 4;  // records a thread loads per tile
 
 bool onchip16_applies(const KSpec &ks, Fast16 *f) {
@@ -426,22 +426,128 @@ __global__ void __launch_bounds__(kOnBlock) k_onchip16(const uint4 *__restrict__
   if (direct) __hip_atomic_fetch_add(&ctrl->onchip_direct, direct, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-hipError_t onchip16_setup(uint32_t total_bytes, uint32_t *lds_bytes) {
-  const void *fns[] = {reinterpret_cast<const void *>(k_onchip16<2>), reinterpret_cast<const void *>(k_onchip16<4>)};
-  uint32_t best = total_bytes;
-  for (const void *fn : fns) {
-    hipFuncAttributes fa{};
-    hipError_t e = hipFuncGetAttributes(&fa, fn);
-    if (e != hipSuccess) return e;
-    if (fa.sharedSizeBytes >= total_bytes) return hipErrorInvalidValue;
-    best = std::min<uint32_t>(best, (total_bytes - (uint32_t)fa.sharedSizeBytes) & ~15u);
+// ---- 16-byte records, several classes ---------------------------------------------
+// The same records with more groups than one table holds: C workgroups per worker
+// (onchip_role), each folding its class.  A wave passes the records of its
+// workgroup's class to a ring of whole records in LDS (ballot and bit count place
+// them) and folds them 64 at a time, all lanes busy; unlike the general kernel's
+// ring of record indices, the fold reads nothing from memory again, so the loads
+// of the next tile stay in flight while it runs.  The rings take 16 KB of LDS
+// (workgroups of 512 threads: eight rings of 128 records).  A record this kernel
+// cannot fold in LDS (a reserved key value, or a key its class's table has no
+// room for) is counted as lost, and the batch runs again on another engine.
+constexpr uint32_t kOnSBlock = 512;  // threads per workgroup
+constexpr int kOnSKeys = 8;          // records a thread loads per tile
+constexpr uint32_t kOnSRing = 128;   // ring entries a wave: a carry under 64, plus one load's 64
+static_assert(kOnSKeys * kOnSBlock == kOn16Keys * kOnBlock, "the 16-byte record kernels' tiles");
+
+template <int kA>
+__global__ void __launch_bounds__(kOnSBlock) k_onchip16s(const uint4 *__restrict__ in, uint64_t n, KSpec ks,
+                                                         Fast16 f, KLevel lv, const PartMeta *__restrict__ meta,
+                                                         uint32_t *cnt, uint64_t *arena, Ctrl *ctrl, uint32_t C,
+                                                         uint32_t workers, uint32_t xcd_map, uint32_t nslots,
+                                                         uint32_t cap) {
+  extern __shared__ uint4 lds4[];
+  __shared__ uint32_t s_groups;
+  __shared__ uint4 s_ring[kOnSBlock / 64][kOnSRing];
+  unsigned long long *t_key = reinterpret_cast<unsigned long long *>(lds4);
+  unsigned long long *t_col = t_key + nslots;
+  const uint32_t tid = threadIdx.x, lane = __lane_id();
+  uint4 *ring = s_ring[tid >> 6];
+  uint32_t cls, worker;
+  onchip_role(C, xcd_map, &cls, &worker);
+  for (uint32_t e = tid; e < nslots; e += blockDim.x) t_key[e] = kEmpty;
+  for (uint32_t w = tid; w < f.ncols * nslots; w += blockDim.x) t_col[w] = 0;
+  if (tid == 0) s_groups = 0;
+  __syncthreads();
+  const uint64_t T = (uint64_t)kOnSKeys * kOnSBlock;
+  unsigned long long lost = 0, direct = 0;
+  uint32_t head = 0, tail = 0;  // the wave's ring (the same in every lane); tail - head < 64 between steps
+  auto load = [&](uint64_t t0, uint4 *r) {
+    const uint4 *tile = in + t0;
+    const uint32_t nt = (uint32_t)(n - t0 < T ? n - t0 : T);
+#pragma unroll
+    for (int u = 0; u < kOnSKeys; ++u) {
+      const uint32_t l = u * kOnSBlock + tid;
+      r[u] = tile[l < nt ? l : 0];
+    }
+  };
+  // one loaded record per lane: to the ring if of this class, then a fold of 64 when there are that many
+  auto step = [&](const uint4 &rec, bool valid) {
+    const uint64_t lo = (uint64_t)rec.x | ((uint64_t)rec.y << 32), hi = (uint64_t)rec.z | ((uint64_t)rec.w << 32);
+    const uint64_t key = f.key_hi ? hi : lo;
+    const bool mine = valid && (key >= kClosed ? cls == 0 : key_class(key, C) == cls);
+    const uint64_t m = __ballot(mine);
+    if (mine) ring[(tail + __popcll(m & lanemask_lt())) & (kOnSRing - 1)] = rec;
+    tail += __popcll(m);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (tail - head >= 64) {
+      const uint4 e = ring[(head + lane) & (kOnSRing - 1)];
+      head += 64;
+      if (!fold16<kA>(e, f, t_key, t_col, nslots, cap, &s_groups, &direct)) ++lost;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+  };
+  uint4 r[kOnSKeys];
+  if ((uint64_t)worker * T < n) load((uint64_t)worker * T, r);
+  for (uint64_t t0 = (uint64_t)worker * T; t0 < n; t0 += (uint64_t)workers * T) {
+    const uint32_t nt = (uint32_t)(n - t0 < T ? n - t0 : T);
+    uint4 cur[kOnSKeys];
+#pragma unroll
+    for (int u = 0; u < kOnSKeys; ++u) cur[u] = r[u];
+    const uint64_t t1 = t0 + (uint64_t)workers * T;
+    if (t1 < n) load(t1, r);  // the next tile's records, in flight while these are folded
+    static_assert(kOnSKeys == 8, "one step per record a lane loads");
+    step(cur[0], 0 * kOnSBlock + tid < nt);
+    step(cur[1], 1 * kOnSBlock + tid < nt);
+    step(cur[2], 2 * kOnSBlock + tid < nt);
+    step(cur[3], 3 * kOnSBlock + tid < nt);
+    step(cur[4], 4 * kOnSBlock + tid < nt);
+    step(cur[5], 5 * kOnSBlock + tid < nt);
+    step(cur[6], 6 * kOnSBlock + tid < nt);
+    step(cur[7], 7 * kOnSBlock + tid < nt);
   }
-  for (const void *fn : fns) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)best);
-    if (e != hipSuccess) return e;
+  // the rest (fewer than a wave)
+  if (head + lane < tail && !fold16<kA>(ring[(head + lane) & (kOnSRing - 1)], f, t_key, t_col, nslots, cap, &s_groups,
+                                        &direct))
+    ++lost;
+  __syncthreads();
+  for (uint32_t e = tid; e < nslots; e += blockDim.x) {
+    const uint64_t key = t_key[e];
+    if (key >= kClosed) continue;
+    Vals8 st;
+#pragma unroll
+    for (int a = 0; a < kA; ++a)
+      if (a < (int)f.ncols) st.v[a] = t_col[(uint64_t)a * nslots + e] ^ (f.kind[a] == 2 ? f.mask[a] : 0ull);
+    if (!fold_into_tables(key, fmix64(key ^ kSeed0), st.v, ks, lv, meta, cnt, arena)) ++lost;
   }
-  *lds_bytes = best;
-  return hipSuccess;
+  if (lost) __hip_atomic_fetch_add(&ctrl->onchip_lost, lost, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (direct) __hip_atomic_fetch_add(&ctrl->onchip_direct, direct, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The dynamic LDS the 16-byte record kernels may take: one_class for the
+// one-class kernels, several for the staged ones (whose rings are static LDS).
+hipError_t onchip16_setup(uint32_t total_bytes, uint32_t *one_class, uint32_t *several) {
+  const void *one[] = {reinterpret_cast<const void *>(k_onchip16<2>), reinterpret_cast<const void *>(k_onchip16<4>)};
+  const void *sev[] = {reinterpret_cast<const void *>(k_onchip16s<2>), reinterpret_cast<const void *>(k_onchip16s<4>)};
+  auto setup = [&](const void *const *fns, uint32_t *out) -> hipError_t {
+    uint32_t best = total_bytes;
+    for (int i = 0; i < 2; ++i) {
+      hipFuncAttributes fa{};
+      hipError_t e = hipFuncGetAttributes(&fa, fns[i]);
+      if (e != hipSuccess) return e;
+      if (fa.sharedSizeBytes >= total_bytes) return hipErrorInvalidValue;
+      best = std::min<uint32_t>(best, (total_bytes - (uint32_t)fa.sharedSizeBytes) & ~15u);
+    }
+    for (int i = 0; i < 2; ++i) {
+      hipError_t e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)best);
+      if (e != hipSuccess) return e;
+    }
+    *out = best;
+    return hipSuccess;
+  };
+  hipError_t e = setup(one, one_class);
+  return e != hipSuccess ? e : setup(sev, several);
 }
 
 #define AGGX_ONCHIP_KERNELS(X) X(false, 2) X(false, 4) X(false, 8) X(true, 2) X(true, 4) X(true, 8)
@@ -477,14 +583,25 @@ hipError_t launch_onchip(hipStream_t s, const uint8_t *in, uint64_t n, const KSp
     return hipErrorInvalidValue;
   if (op.fast) {
     Fast16 f;
-    if (op.narrow || op.C != 1 || !onchip16_applies(ks, &f) || ((uintptr_t)in & 15)) return hipErrorInvalidValue;
+    if (op.narrow || !onchip16_applies(ks, &f) || ((uintptr_t)in & 15)) return hipErrorInvalidValue;
     const uint4 *in4 = reinterpret_cast<const uint4 *>(in);
-    if (ks.na <= 2)
-      hipLaunchKernelGGL((k_onchip16<2>), dim3(op.workers), dim3(kOnBlock), op.lds_bytes, s, in4, n, ks, f, lv, meta,
-                         cnt, arena, ctrl, op.workers, op.nslots, op.cap);
-    else
-      hipLaunchKernelGGL((k_onchip16<4>), dim3(op.workers), dim3(kOnBlock), op.lds_bytes, s, in4, n, ks, f, lv, meta,
-                         cnt, arena, ctrl, op.workers, op.nslots, op.cap);
+    const bool two = ks.na <= 2;
+    if (op.C == 1) {
+      if (two)
+        hipLaunchKernelGGL((k_onchip16<2>), dim3(op.workers), dim3(kOnBlock), op.lds_bytes, s, in4, n, ks, f, lv, meta,
+                           cnt, arena, ctrl, op.workers, op.nslots, op.cap);
+      else
+        hipLaunchKernelGGL((k_onchip16<4>), dim3(op.workers), dim3(kOnBlock), op.lds_bytes, s, in4, n, ks, f, lv, meta,
+                           cnt, arena, ctrl, op.workers, op.nslots, op.cap);
+    } else {
+      const uint32_t blocks = op.C * op.workers;
+      if (two)
+        hipLaunchKernelGGL((k_onchip16s<2>), dim3(blocks), dim3(kOnSBlock), op.lds_bytes, s, in4, n, ks, f, lv, meta,
+                           cnt, arena, ctrl, op.C, op.workers, op.xcd_map, op.nslots, op.cap);
+      else
+        hipLaunchKernelGGL((k_onchip16s<4>), dim3(blocks), dim3(kOnSBlock), op.lds_bytes, s, in4, n, ks, f, lv, meta,
+                           cnt, arena, ctrl, op.C, op.workers, op.xcd_map, op.nslots, op.cap);
+    }
     return hipGetLastError();
   }
   // a narrow COUNT column counts one workgroup's records: fewer than 2^32 of them

@@ -89,7 +89,8 @@ def test_reserved_keys_and_one_key():
 
 def test_one_class_overflows_into_tables():
     """Keys x * 2^32 + x share their class (the class hash folds the two halves), so one
-    class's LDS table overflows and its extra keys go straight to the HBM tables."""
+    class's LDS table overflows: the staged kernel leaves the batch to the general kernel,
+    where the class's extra keys go straight to the HBM tables."""
     rng = np.random.default_rng(9)
     x = rng.choice(2**31, size=9000, replace=False).astype(np.uint64)
     pool = (x << np.uint64(32)) | x
@@ -99,6 +100,7 @@ def test_one_class_overflows_into_tables():
     k, c, st = run_lib(rec, 16, [(0, "u64")], workloads.AGGS_R16_ALL, est_groups=9000, engine="onchip")
     check_against_oracle(rec, SPEC_R16, k, c, "onchip one class")
     assert st["engine"] == 5 and st["onchip_classes"] > 1 and st["onchip_fallbacks"] == 0
+    assert st["onchip_retries"] == 1 and st["onchip_kernel16"] == 0 and st["onchip_direct"] > 0
 
 
 def test_low_estimate_runs_the_batch_again():
@@ -127,18 +129,18 @@ R16_SWAPPED = np.dtype([("v", "<i8"), ("key", "<u8")])
 
 @pytest.mark.parametrize("d,aggs", [(1500, workloads.AGGS_R16_ALL), (9000, workloads.AGGS_R16_ALL),
                                     (8000, workloads.AGGS_R16_CS)])
-def test_kernel16_one_class_general_kernel_for_several(d, aggs):
-    """16-byte (key, value) records whose groups fit one LDS table take the 16-byte record
-    kernel (every lane folds every record it loads); with more groups, several classes on the
-    general kernel.  COUNT+SUM and all four aggregates."""
+def test_kernel16_one_class_and_staged(d, aggs):
+    """16-byte (key, value) records whose groups fit one LDS table take the one-class kernel
+    (every lane folds every record it loads); with more groups, the staged kernel (a ring of
+    whole records per wave).  COUNT+SUM and all four aggregates."""
     wl = workloads.uniform_small().scaled(2_000_000, d)
     rec = wl.generate()
     spec = {"record_bytes": 16, "keys": [(0, "u64")], "aggs": aggs}
     print(f"case: onchip kernel16 d={d} na={len(aggs)}", flush=True)
     k, c, st = run_lib(rec, 16, spec["keys"], aggs, est_groups=d, engine="onchip")
     check_against_oracle(rec, spec, k, c, f"kernel16 d={d}")
-    assert st["engine"] == 5 and st["onchip_fallbacks"] == 0
-    assert st["onchip_kernel16"] == (1 if d == 1500 else 0) and (st["onchip_classes"] == 1) == (d == 1500)
+    assert st["engine"] == 5 and st["onchip_fallbacks"] == 0 and st["onchip_retries"] == 0
+    assert st["onchip_kernel16"] == (1 if d == 1500 else 2) and (st["onchip_classes"] == 1) == (d == 1500)
 
 
 def test_kernel16_key_in_second_half_signed_extremes():
@@ -194,3 +196,28 @@ def test_kernel16_other_field_takes_the_general_kernel():
     k, c, st = run_lib(rec, 16, spec["keys"], aggs, est_groups=500, engine="onchip")
     check_against_oracle(rec, spec, k, c, "onchip i32 fields")
     assert st["engine"] == 5 and st["onchip_kernel16"] == 0
+
+
+def test_staged_reserved_keys_go_to_the_general_kernel():
+    """A reserved key value among several classes: the staged kernel leaves the batch to the
+    general kernel (side groups), with the same rows as the oracle."""
+    wl = workloads.uniform_small().scaled(1_500_000, 9000)
+    rec = wl.generate()
+    rec["key"][::1001] = np.uint64(2**64 - 1)
+    rec["key"][5::1003] = np.uint64(2**64 - 2)
+    print("case: onchip staged reserved", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=9002, engine="onchip")
+    check_against_oracle(rec, oracle_spec(wl), k, c, "staged reserved")
+    assert st["engine"] == 5 and st["onchip_retries"] == 1 and st["onchip_kernel16"] == 0
+
+
+@pytest.mark.parametrize("n,d", [(4097, 3000), (1_000_003, 6000), (3_000_001, 17_000)])
+def test_staged_sizes_and_ragged_tails(n, d):
+    """The staged kernel over ragged last tiles (a ring's carry across tiles, the last partial
+    wave) and up to eight classes."""
+    wl = workloads.uniform_small().scaled(n, d)
+    rec = wl.generate()
+    print(f"case: onchip staged n={n} d={d}", flush=True)
+    k, c, st = run_lib(rec, **lib_spec_args(wl), est_groups=d, engine="onchip")
+    check_against_oracle(rec, oracle_spec(wl), k, c, f"staged n={n}")
+    assert st["engine"] == 5 and st["onchip_kernel16"] == 2 and st["onchip_retries"] == 0
