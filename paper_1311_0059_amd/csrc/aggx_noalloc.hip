@@ -113,6 +113,9 @@ extern "C" agg_status agg_query_noalloc(const agg_spec *spec, const void *d_reco
   if (n) {
     OnchipPlan op;
     if (!onchip_shape(ks, n, G, ((uintptr_t)d_records & 15) == 0, &op)) return AGG_E_BUDGET;
+    // the staged 16-byte record kernel leaves reserved key values and overfull classes
+    // to a second run, which this entry point does not make: the general kernel instead
+    if (op.fast && op.C > 1 && !onchip_shape(ks, n, G, false, &op)) return AGG_E_BUDGET;
     KLevel lv;
     lv.level = 0;
     lv.digit_shift = 0;

@@ -54,6 +54,19 @@ def test_r24_and_reserved_keys():
     assert_rows_equal(k, c, wk, wc, "noalloc R24")
 
 
+def test_r16_reserved_keys_several_classes():
+    """16-byte records with reserved key values and more groups than one LDS table: the
+    entry point runs the general kernel (the side groups), the rows equal the query path's."""
+    wl = workloads.uniform_small().scaled(400_000, 9_000)
+    rec = wl.generate().copy()
+    rec["key"][::997] = np.uint64(2**64 - 1)
+    rec["key"][3::991] = np.uint64(2**64 - 2)
+    print("case: noalloc R16 reserved keys", flush=True)
+    k, c = _noalloc(rec, wl, 9_002)
+    wk, wc, _ = run_lib(rec, **lib_spec_args(wl), est_groups=9_002)
+    assert_rows_equal(k, c, wk, wc, "noalloc R16 reserved")
+
+
 def test_errors():
     import paper_1311_0059_amd as P
     wl = workloads.uniform_small().scaled(200_000, 60_000)
