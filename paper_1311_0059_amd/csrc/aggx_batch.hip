@@ -113,7 +113,24 @@ __device__ void lds_aggregate(const uint8_t *in, uint64_t lo, uint64_t hi, const
     fold_lds(t_acc + slot, nslots, ks, vals);
     return true;
   };
-  for (uint64_t i = lo + tid; i < hi; i += blockDim.x) {
+  uint64_t i = lo + tid;
+  if (ks.na <= 2) {
+    // two records a thread are read before either is probed, so that their loads are
+    // in flight together (with up to two aggregates; more would crowd the registers)
+    const uint64_t B = blockDim.x;
+    for (; i + B < hi; i += 2 * B) {
+      const uint8_t *r0 = in + i * ks.rb, *r1 = in + (i + B) * ks.rb;
+      uint64_t v0[2], v1[2];
+      const uint64_t k0 = read_key(r0, ks), k1 = read_key(r1, ks);
+      in_vals<0, 2>(r0, ks, v0);
+      in_vals<0, 2>(r1, ks, v1);
+      if (k0 >= kClosed) bad = true;
+      else bad |= !fold_one(k0, v0);
+      if (k1 >= kClosed) bad = true;
+      else bad |= !fold_one(k1, v1);
+    }
+  }
+  for (; i < hi; i += blockDim.x) {
     const uint8_t *rec = in + i * ks.rb;
     uint64_t vals[kMaxAggs];
     const uint64_t key = read_key(rec, ks);
