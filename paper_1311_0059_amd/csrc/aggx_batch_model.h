@@ -35,10 +35,10 @@ struct BatchModelParams {
 // The rates and costs fitted to the persistent kernel (256 workgroups, 16-byte
 // records, COUNT and SUM) on 216 timed launches: the 27 layouts of each of
 // eight instance mixes of 37 to 4096 instances of 1e3 to 8e6 records.  The
-// model's times are within about 12% of the measured ones (root mean square
+// model's times are within about 9% of the measured ones (root mean square
 // of the log ratio), and in every mix the four layouts it prices lowest hold
-// one within 1.5% of the fastest of the 27.
-constexpr BatchModelParams kBatchModel = {1.85e9, 3.0e7, 1.5e-3, 6.6e-6, 3.3e-3, 0.018};
+// one within 1.8% of the fastest of the 27.
+constexpr BatchModelParams kBatchModel = {2.03e9, 3.3e7, 1.6e-3, 8.2e-6, 2.4e-3, 0.019};
 
 enum : uint32_t { SM_COUNT = 0, SM_SOLO = 1, SM_OFFS = 2, SM_SCATTER = 3, SM_AGG = 4 };
 
