@@ -80,6 +80,7 @@ struct Req {
   uint64_t bytes = 0;  // pool bytes it holds while running
   uint64_t off = 0;
   bool done = false;
+  uint32_t waiters = 0;  // threads inside agg_server_wait on it (release waits for them to leave)
   agg_status status = AGG_OK;
   agg_handle *h = nullptr;
   agg_result res{};
@@ -228,7 +229,10 @@ agg_status agg_server_wait(agg_server *s, uint64_t ticket, agg_result *out, agg_
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return AGG_E_INVALID;
   Req *r = it->second;
+  r->waiters += 1;
   s->cv_done.wait(lk, [&] { return r->done; });
+  r->waiters -= 1;
+  s->cv_done.notify_all();  // a release of this ticket may be waiting for this thread to leave
   if (info) {
     memset(info, 0, sizeof(*info));
     info->status = r->status;
@@ -251,7 +255,8 @@ agg_status agg_server_release(agg_server *s, uint64_t ticket) {
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return AGG_E_INVALID;
     r = it->second;
-    s->cv_done.wait(lk, [&] { return r->done; });
+    // freed only once no thread still waits on it (wait and release of one ticket may race)
+    s->cv_done.wait(lk, [&] { return r->done && r->waiters == 0; });
     s->reqs.erase(it);
   }
   if (r->h) agg_destroy(r->h);
