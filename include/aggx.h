@@ -83,13 +83,14 @@ typedef enum agg_policy {
 /* Aggregation engines (all compute the same rows). */
 typedef enum agg_engine {
   AGG_ENGINE_AUTO = 0,    /* for the first batch: the sorted-run path when a sample of it is sorted; else
-                             the LDS engine when it applies (keys frequent in a sample of the batch are
-                             then aggregated apart from its partitions); else HBM tables with atomics.
+                             of the on-chip engine and the LDS engine, those that apply, the one a cost
+                             model prices lower (keys frequent in a sample of the batch are then aggregated
+                             apart from the LDS engine's partitions); else HBM tables with atomics.
                              Later batches and recursion levels use HBM tables */
   AGG_ENGINE_TABLES = 1,  /* per-partition open-addressing tables in HBM, 64-bit atomics, chunked input */
   AGG_ENGINE_LDS = 2,     /* radix-partition the batch (up to 2^14 partitions), then one workgroup
                              aggregates each partition in an LDS table (in up to 4 sweeps when a partition
-                             has more groups than a table).  Up to 64 keys that are frequent in a sample of
+                             has more groups than a table).  Up to 256 keys that are frequent in a sample of
                              the batch are taken out of the partitions and aggregated while it is counted
                              (one row each).  When the budget holds only part of the partitioned batch,
                              runs of partitions that fit it are done one pass over the batch each.
@@ -106,9 +107,10 @@ typedef enum agg_engine {
                              8 LDS tables: one pass with no partitioning.  The keys are split into classes;
                              each class's records are aggregated in LDS by workgroups of their own that
                              read the same tiles of the batch, and fold their groups into the level-0 HBM
-                             tables at the end (early aggregation, Sec. 4.2).  When the batch has more
-                             groups than those tables hold, it is run again on the engine AUTO would choose
-                             next.  AUTO tries it first (after the sorted-run check) */
+                             tables at the end (early aggregation, Sec. 4.2).  Aligned 16-byte records of
+                             one 8-byte key and one 8-byte field take kernels of their own (one class, or
+                             whole records staged per wave).  When the batch has more groups than those
+                             tables hold, it is run again on the engine AUTO would choose next */
 } agg_engine;
 
 #define AGG_MAX_AGGS 8
