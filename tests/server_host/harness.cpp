@@ -9,6 +9,9 @@
 //
 // Usage: harness TRACE MAX_INFLIGHT ROUNDS
 //   TRACE: one request a line, "records budget_bytes"
+// Built with -DAGGX_HARNESS_LIB (as a shared library, no main) it exports every
+// call of include/aggx.h, so that the Python binding can load it in place of the
+// library and drive the server from Python threads as the benchmark does.
 #include <atomic>
 #include <chrono>
 #include <cstdio>
@@ -108,9 +111,23 @@ agg_status agg_get_stats(const agg_handle *h, agg_stats *out) {
 
 void agg_destroy(agg_handle *h) { delete h; }
 
+// the rest of the interface, which the server does not use (the binding looks them up)
+agg_status agg_first_rows(agg_handle *, agg_result *) { return AGG_E_INVALID; }
+const char *agg_strerror(agg_status) { return "stand-in"; }
+agg_status agg_batch_create(const agg_spec *, const agg_instance *, uint32_t, agg_batch **) { return AGG_E_INVALID; }
+agg_status agg_batch_run(agg_batch *) { return AGG_E_INVALID; }
+agg_status agg_batch_result(const agg_batch *, uint32_t, agg_result *) { return AGG_E_INVALID; }
+agg_status agg_batch_get_stats(const agg_batch *, agg_batch_stats *) { return AGG_E_INVALID; }
+void agg_batch_destroy(agg_batch *) {}
+agg_status agg_query_noalloc(const agg_spec *, const void *, uint64_t, uint64_t *, int64_t *const *, uint64_t,
+                             uint64_t *) {
+  return AGG_E_INVALID;
+}
+
 }  // extern "C"
 
 // ---- the driver ---------------------------------------------------------------
+#ifndef AGGX_HARNESS_LIB
 static int fail(const char *what, int code) {
   fprintf(stderr, "harness: %s (%d)\n", what, code);
   return 1;
@@ -193,3 +210,4 @@ int main(int argc, char **argv) {
   printf("server harness ok\n");
   return 0;
 }
+#endif  // AGGX_HARNESS_LIB

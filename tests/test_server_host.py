@@ -44,3 +44,22 @@ def test_served_trace_all_queued(tmp_path, san):
         assert r.returncode == 0, f"{san} {inflight} in flight:\n{r.stdout[-2000:]}\n{r.stderr[-4000:]}"
         assert "server harness ok" in r.stdout
         assert f"peak {inflight} in flight" in r.stdout or inflight > 8  # the trace keeps them all busy
+
+
+def test_served_trace_through_the_binding(tmp_path):
+    """The same trace driven from Python threads through the binding's Server class, with the
+    stand-in library under AddressSanitizer (preloaded into the interpreter)."""
+    so = tmp_path / "libharness.so"
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-pthread", "-shared", "-fPIC", "-DAGGX_HARNESS_LIB",
+                    "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-I", HERE, "-o", str(so),
+                    os.path.join(HERE, "harness.cpp")], check=True, capture_output=True)
+    asan = subprocess.run(["g++", "-print-file-name=libasan.so"], check=True, capture_output=True,
+                          text=True).stdout.strip()
+    ubsan = subprocess.run(["g++", "-print-file-name=libubsan.so"], check=True, capture_output=True,
+                           text=True).stdout.strip()
+    env = dict(os.environ, LD_PRELOAD=f"{asan}:{ubsan}", ASAN_OPTIONS="detect_leaks=0:abort_on_error=0",
+               MALLOC_CHECK_="3")
+    r = subprocess.run(["python", os.path.join(HERE, "drive.py"), str(so), "8", "1000", "2"], env=env,
+                       capture_output=True, text=True, timeout=600, cwd=ROOT)
+    assert r.returncode == 0, f"{r.stdout[-2000:]}\n{r.stderr[-4000:]}"
+    assert "python driver ok" in r.stdout and "peak 8 in flight" in r.stdout
