@@ -207,41 +207,55 @@ __global__ void __launch_bounds__(256) k_update(const uint8_t *__restrict__ in, 
 // keys into an LDS set, counts the records whose key was already present, and
 // the largest number of samples that share one key.  The host turns the
 // hot-key cache on when keys repeat, and keeps skewed inputs (one key holding
-// a large share) away from the partition-per-workgroup engine.
-__global__ void __launch_bounds__(256) k_sample_dups(const uint8_t *__restrict__ in, uint64_t n, KSpec ks, uint32_t ns,
-                                                     Ctrl *ctrl) {
+// a large share) away from the partition-per-workgroup engine.  Each thread
+// loads its (at most kDupsPer) sampled keys before using any, so that the loads
+// are in flight together: one trip to memory rather than one per sample.
+constexpr uint32_t kDupsBlock = 1024, kDupsPer = 2;  // ns <= kDupsBlock * kDupsPer = 2048
+__global__ void __launch_bounds__(kDupsBlock) k_sample_dups(const uint8_t *__restrict__ in, uint64_t n, KSpec ks,
+                                                            uint32_t ns, Ctrl *ctrl) {
   __shared__ unsigned long long set[4096];
-  __shared__ uint32_t cnt[4096];
-  __shared__ uint32_t dups, maxc;
-  for (uint32_t i = threadIdx.x; i < 4096; i += blockDim.x) {
-    set[i] = kEmpty;
-    cnt[i] = 0;
+  // the sampled keys in sample order (for the order check), then the set's counts
+  __shared__ union {
+    unsigned long long key[kDupsBlock * kDupsPer];
+    uint32_t cnt[4096];
+  } u;
+  __shared__ uint32_t dups, maxc, descents;
+  uint64_t mine[kDupsPer];
+#pragma unroll
+  for (uint32_t k = 0; k < kDupsPer; ++k) {
+    const uint32_t j = k * blockDim.x + threadIdx.x;
+    mine[k] = j < ns ? read_key(in + ((uint64_t)j * n / ns) * ks.rb, ks) : 0;
   }
-  if (threadIdx.x == 0) dups = maxc = 0;
+  for (uint32_t i = threadIdx.x; i < 4096; i += blockDim.x) set[i] = kEmpty;
+#pragma unroll
+  for (uint32_t k = 0; k < kDupsPer; ++k) {
+    const uint32_t j = k * blockDim.x + threadIdx.x;
+    if (j < ns) u.key[j] = mine[k];
+  }
+  if (threadIdx.x == 0) dups = maxc = descents = 0;
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < ns; j += blockDim.x) {
-    const uint64_t i = (uint64_t)j * n / ns;
-    const uint64_t key = read_key(in + i * ks.rb, ks);
+  // is the sample in non-decreasing key order?
+  for (uint32_t j = threadIdx.x; j + 1 < ns; j += blockDim.x)
+    if (u.key[j + 1] < u.key[j]) atomicAdd(&descents, 1u);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < 4096; i += blockDim.x) u.cnt[i] = 0;
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < kDupsPer; ++k) {
+    if (k * blockDim.x + threadIdx.x >= ns) continue;
+    const uint64_t key = mine[k];
     uint32_t e = (uint32_t)(fmix64(key ^ kSeed0) >> 52);
     for (int t = 0; t < 4096; ++t) {
       const unsigned long long prev = atomicCAS(&set[e], (unsigned long long)kEmpty, (unsigned long long)key);
       if (prev == kEmpty || prev == key) {
         if (prev == key) atomicAdd(&dups, 1u);
-        atomicMax(&maxc, atomicAdd(&cnt[e], 1u) + 1);
+        atomicMax(&maxc, atomicAdd(&u.cnt[e], 1u) + 1);
         break;
       }
       e = (e + 1) & 4095;
     }
   }
-  // is the sample in non-decreasing key order?
-  __shared__ uint32_t descents;
-  if (threadIdx.x == 0) descents = 0;
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j + 1 < ns; j += blockDim.x) {
-    const uint64_t a = read_key(in + ((uint64_t)j * n / ns) * ks.rb, ks);
-    const uint64_t b = read_key(in + ((uint64_t)(j + 1) * n / ns) * ks.rb, ks);
-    if (b < a) atomicAdd(&descents, 1u);
-  }
   // the frequent keys (at least kHotMin samples), most frequent first: one scan
   // per band of counts, while there is room
   __shared__ uint32_t nhot;
@@ -250,7 +264,7 @@ __global__ void __launch_bounds__(256) k_sample_dups(const uint8_t *__restrict__
   const uint32_t bands[5] = {~0u, 64, 16, 6, kHotMin};
   for (int band = 1; band < 5; ++band) {
     for (uint32_t e = threadIdx.x; e < 4096; e += blockDim.x) {
-      if (set[e] >= kClosed || cnt[e] < bands[band] || cnt[e] >= bands[band - 1]) continue;
+      if (set[e] >= kClosed || u.cnt[e] < bands[band] || u.cnt[e] >= bands[band - 1]) continue;
       const uint32_t pos = atomicAdd(&nhot, 1u);
       if (pos < kMaxHot) ctrl->sample_hot[pos] = set[e];
     }
@@ -638,7 +652,8 @@ hipError_t launch_sample_hot(hipStream_t s, const uint8_t *in, uint64_t n, const
 
 hipError_t launch_sample_dups(hipStream_t s, const uint8_t *in, uint64_t n, const KSpec &ks, uint32_t ns,
                               Ctrl *ctrl) {
-  hipLaunchKernelGGL(k_sample_dups, dim3(1), dim3(256), 0, s, in, n, ks, ns, ctrl);
+  if (ns > kDupsBlock * kDupsPer) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sample_dups, dim3(1), dim3(kDupsBlock), 0, s, in, n, ks, ns, ctrl);
   return hipGetLastError();
 }
 
