@@ -1381,6 +1381,18 @@ agg_status run_lds(agg_handle *h, const uint8_t *in, uint64_t n, const LdsPlan &
   }
   *applied = true;
   h->st.pool_high_water = std::max(h->st.pool_high_water, kOverhead + lp.need);
+  // result rows for every pass at once (a partition's rows are at most its slots per
+  // sweep), so that no pass has to grow them and copy the rows of the passes before
+  {
+    uint64_t bound = h->r_rows + hot.n + 1;
+    uint32_t d_prev = 0;
+    for (const auto &r : runs) {
+      bound += std::min<uint64_t>(r.second, ((uint64_t)(r.first - d_prev) << lp.sbits) * lp.nslots);
+      d_prev = r.first;
+    }
+    agg_status s = ensure_result_cap(h, bound);
+    if (s) return s;
+  }
   uint32_t d_lo = 0;
   for (const auto &r : runs) {
     agg_status s = lds_run_partitions(h, in, n, lp, d_lo, r.first - d_lo, r.second);
