@@ -171,6 +171,58 @@ void dev_put(void *p, uint64_t bytes) {
   g_dev_free.push_back({p, bytes, dev});
 }
 
+// A handle's host-side resources -- its four timing events and the pinned mirrors
+// of the control block and of the readback scratch, and a library-owned stream --
+// are kept for the next handle on the same device when it is destroyed: creating
+// and pinning them costs more than a small query's kernels.  At most
+// kHandleCache of each are kept.
+struct HandleRes {
+  int device;
+  hipEvent_t ev[4];
+  Ctrl *h_ctrl;
+  uint32_t *h_scratch;
+};
+constexpr size_t kHandleCache = 16;
+std::mutex g_res_mu;
+std::vector<HandleRes> g_res_free;
+std::vector<std::pair<int, hipStream_t>> g_stream_free;
+
+bool res_get(int device, HandleRes *r) {
+  std::lock_guard<std::mutex> lk(g_res_mu);
+  for (size_t i = 0; i < g_res_free.size(); ++i)
+    if (g_res_free[i].device == device) {
+      *r = g_res_free[i];
+      g_res_free.erase(g_res_free.begin() + i);
+      return true;
+    }
+  return false;
+}
+
+bool res_put(const HandleRes &r) {
+  std::lock_guard<std::mutex> lk(g_res_mu);
+  if (g_res_free.size() >= kHandleCache) return false;
+  g_res_free.push_back(r);
+  return true;
+}
+
+bool stream_get(int device, hipStream_t *st) {
+  std::lock_guard<std::mutex> lk(g_res_mu);
+  for (size_t i = 0; i < g_stream_free.size(); ++i)
+    if (g_stream_free[i].first == device) {
+      *st = g_stream_free[i].second;
+      g_stream_free.erase(g_stream_free.begin() + i);
+      return true;
+    }
+  return false;
+}
+
+bool stream_put(int device, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_res_mu);
+  if (g_stream_free.size() >= kHandleCache) return false;
+  g_stream_free.push_back({device, st});
+  return true;
+}
+
 // A spill run: records (raw) or states written by the kernels into pinned
 // segments.  Each launch gets a contiguous region large enough for its worst
 // case; after the launch the region is trimmed to what was written.
@@ -2415,22 +2467,33 @@ agg_status agg_create(const agg_spec *spec, agg_handle **out) {
   if (spec->stream) {
     h->stream = (hipStream_t)spec->stream;
   } else {
-    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+    if (!stream_get(h->device, &h->stream) && hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
       delete h;
       return AGG_E_DEVICE;
     }
     h->own_stream = true;
   }
-  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
-      hipEventCreate(&h->ev2) != hipSuccess || hipEventCreate(&h->ev3) != hipSuccess) {
-    agg_destroy(h);
-    return AGG_E_DEVICE;
-  }
-  if (hipHostMalloc((void **)&h->h_ctrl, sizeof(Ctrl), 0) != hipSuccess ||
-      hipHostMalloc((void **)&h->h_scratch, kScratchBytes, 0) != hipSuccess) {
-    if (getenv("AGGX_DEBUG")) fprintf(stderr, "aggx: the handle's pinned mirrors are not available\n");
-    agg_destroy(h);
-    return AGG_E_NOMEM;
+  HandleRes res;
+  if (res_get(h->device, &res)) {
+    h->ev0 = res.ev[0];
+    h->ev1 = res.ev[1];
+    h->ev2 = res.ev[2];
+    h->ev3 = res.ev[3];
+    h->h_ctrl = res.h_ctrl;
+    h->h_scratch = res.h_scratch;
+    memset(h->h_ctrl, 0, sizeof(Ctrl));
+  } else {
+    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+        hipEventCreate(&h->ev2) != hipSuccess || hipEventCreate(&h->ev3) != hipSuccess) {
+      agg_destroy(h);
+      return AGG_E_DEVICE;
+    }
+    if (hipHostMalloc((void **)&h->h_ctrl, sizeof(Ctrl), 0) != hipSuccess ||
+        hipHostMalloc((void **)&h->h_scratch, kScratchBytes, 0) != hipSuccess) {
+      if (getenv("AGGX_DEBUG")) fprintf(stderr, "aggx: the handle's pinned mirrors are not available\n");
+      agg_destroy(h);
+      return AGG_E_NOMEM;
+    }
   }
   h->unlimited = spec->budget_bytes == 0;
   if (spec->device_workspace) {
@@ -2639,15 +2702,19 @@ void agg_destroy(agg_handle *h) {
   h->dd_tmp[1].release();
   if (h->own_pool && h->pool) dev_put(h->pool, h->pool_bytes);
   if (h->r_block) dev_put(h->r_block, h->r_block_bytes);
-  if (h->ev0) (void)hipEventDestroy(h->ev0);
-  if (h->ev1) (void)hipEventDestroy(h->ev1);
-  if (h->ev2) (void)hipEventDestroy(h->ev2);
-  if (h->ev3) (void)hipEventDestroy(h->ev3);
   for (auto &e : h->ev_own)
     if (e) (void)hipEventDestroy(e);
-  if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
-  if (h->h_scratch) (void)hipHostFree(h->h_scratch);
-  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  // a complete set goes back to the cache (the stream was synchronized above)
+  const HandleRes res{h->device, {h->ev0, h->ev1, h->ev2, h->ev3}, h->h_ctrl, h->h_scratch};
+  if (!(h->ev0 && h->ev1 && h->ev2 && h->ev3 && h->h_ctrl && h->h_scratch && res_put(res))) {
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->ev2) (void)hipEventDestroy(h->ev2);
+    if (h->ev3) (void)hipEventDestroy(h->ev3);
+    if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
+    if (h->h_scratch) (void)hipHostFree(h->h_scratch);
+  }
+  if (h->own_stream && h->stream && !stream_put(h->device, h->stream)) (void)hipStreamDestroy(h->stream);
   delete h;
 }
 
