@@ -296,7 +296,11 @@ agg_status agg_finish(agg_handle *h, agg_result *out);
  * models.  AGG_E_INVALID on a NULL argument. */
 agg_status agg_get_stats(const agg_handle *h, agg_stats *out);
 
-/* Free everything the handle owns.  Safe on a poisoned handle and on NULL. */
+/* Free everything the handle owns.  Safe on a poisoned handle and on NULL.
+ * Waits for the handle's stream.  Its timing events, its two small pinned host
+ * mirrors and a library-owned stream are kept for the next handle on the same
+ * device (at most 16 sets a process, held until the process ends); its device
+ * blocks go to the library's block cache. */
 void agg_destroy(agg_handle *h);
 
 /* Static description of a status code. */
